@@ -1,0 +1,280 @@
+"""ctypes binding of libtddft.so (argument marshalling only).
+
+Every computation runs in the library's HIP kernels. PyTorch supplies the
+device memory (its caching allocator, through the allocator callbacks of
+``tddft_config``) and the stream; nothing here falls back to a CPU path: if
+the library is not built, loading fails with an error.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtddft.so")
+
+ABI_VERSION = 1
+OK, EINVAL, ENOMEM, EDEVICE, EUNSTABLE, ESTATE, ENUMERIC = range(7)
+STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "EUNSTABLE", 5: "ESTATE",
+                6: "ENUMERIC"}
+PERIODIC, ISOLATED = 0, 1
+C128, MIXED = 0, 1
+VELOCITY, LENGTH = 0, 1
+XC_NONE, XC_PZ81 = 0, 1
+FLAG_ALLOW_UNSTABLE, FLAG_DEBUG_SYNC, FLAG_NO_GRAPH = 1, 2, 4
+
+EXPORTED = ["tddft_abi_version", "tddft_init", "tddft_set_potential", "tddft_propagate",
+            "tddft_density_current", "tddft_get_orbitals", "tddft_set_orbitals", "tddft_energy",
+            "tddft_norms", "tddft_dipole", "tddft_kick", "tddft_last_timing", "tddft_last_error",
+            "tddft_free"]
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+
+
+class Config(C.Structure):
+    _fields_ = [("abi_version", C.c_uint32), ("struct_size", C.c_uint32), ("n", C.c_int32 * 3),
+                ("cell", C.c_double * 3), ("boundary", C.c_int32), ("n_orb", C.c_int32),
+                ("n_k", C.c_int32), ("kpt", _dp), ("kw", _dp), ("dt", C.c_double),
+                ("precision", C.c_int32), ("hartree", C.c_int32), ("xc", C.c_int32),
+                ("gauge", C.c_int32), ("flags", C.c_uint32), ("stream", C.c_void_p),
+                ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN), ("alloc_user", C.c_void_p)]
+
+
+class Atom(C.Structure):
+    _fields_ = [("npts", C.c_int32), ("n_proj", C.c_int32), ("idx", _ip), ("x", _dp),
+                ("beta", _dp), ("e_kb", _dp)]
+
+
+class TDDFTError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libtddft.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library not built: {path} is missing "
+                           "(run python -m paper_1804_01404_amd.build)")
+    # One HIP runtime per process: torch carries its own libamdhip64, so it is
+    # brought up first and the library's libamdhip64.so.7 dependency then
+    # resolves to the copy already loaded (same soname).
+    import torch
+    if torch.cuda.is_available():
+        torch.cuda.init()
+    lib = C.CDLL(path)
+    lib.tddft_abi_version.restype = C.c_uint32
+    lib.tddft_init.argtypes = [C.POINTER(Config), _dp, C.POINTER(C.c_void_p)]
+    lib.tddft_set_potential.argtypes = [C.c_void_p, _dp, C.c_int32, C.POINTER(Atom)]
+    lib.tddft_propagate.argtypes = [C.c_void_p, C.c_int32, _dp, _dp]
+    lib.tddft_density_current.argtypes = [C.c_void_p, _dp, _dp]
+    lib.tddft_get_orbitals.argtypes = [C.c_void_p, _dp]
+    lib.tddft_set_orbitals.argtypes = [C.c_void_p, _dp]
+    lib.tddft_energy.argtypes = [C.c_void_p, _dp]
+    lib.tddft_norms.argtypes = [C.c_void_p, _dp]
+    lib.tddft_dipole.argtypes = [C.c_void_p, _dp]
+    lib.tddft_kick.argtypes = [C.c_void_p, C.c_double, C.c_int32]
+    lib.tddft_last_timing.argtypes = [C.c_void_p, _dp]
+    lib.tddft_last_error.argtypes = [C.c_void_p]
+    lib.tddft_last_error.restype = C.c_char_p
+    lib.tddft_free.argtypes = [C.c_void_p]
+    lib.tddft_free.restype = None
+    for name in ("tddft_init", "tddft_set_potential", "tddft_propagate", "tddft_density_current",
+                 "tddft_get_orbitals", "tddft_set_orbitals", "tddft_energy", "tddft_norms",
+                 "tddft_dipole", "tddft_kick", "tddft_last_timing"):
+        getattr(lib, name).restype = C.c_int
+    if lib.tddft_abi_version() != ABI_VERSION:
+        raise RuntimeError("libtddft.so ABI version mismatch")
+    _lib = lib
+    return lib
+
+
+def _ptr(a: np.ndarray, ctype=C.c_double):
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+class _TorchMemory:
+    """Allocator callbacks backed by torch's caching allocator on one stream."""
+
+    def __init__(self, device: int, stream):
+        import torch
+        self.torch = torch
+        self.device = device
+        self.stream = stream
+        self.alloc_cb = ALLOC_FN(self._alloc)
+        self.free_cb = FREE_FN(self._free)
+
+    def _alloc(self, nbytes, _user):
+        try:
+            return int(self.torch.cuda.caching_allocator_alloc(int(nbytes), self.device, self.stream))
+        except Exception:  # reported to the library as a NULL allocation (ENOMEM)
+            return None
+
+    def _free(self, ptr, _user):
+        self.torch.cuda.caching_allocator_delete(int(ptr))
+
+
+class TDDFT:
+    """One TDKS cell on the GPU, driven through the C ABI."""
+
+    def __init__(self, system, *, precision: Optional[str] = None, flags: int = 0,
+                 torch_memory: bool = True, psi0: Optional[np.ndarray] = None):
+        self.lib = load_library()
+        s = system
+        self.system = s
+        prec = precision or s.precision
+        self.n = tuple(s.n)
+        self.n_orb, self.n_k = s.n_orb, s.n_k
+        self._kpt = np.ascontiguousarray(s.kpts, dtype=np.float64)
+        self._kw = np.ascontiguousarray(s.kw, dtype=np.float64)
+        self._mem = None
+        self._stream = None
+        cfg = Config()
+        cfg.abi_version = ABI_VERSION
+        cfg.struct_size = C.sizeof(Config)
+        cfg.n[:] = list(s.n)
+        cfg.cell[:] = list(s.cell)
+        cfg.boundary = PERIODIC if s.boundary == "periodic" else ISOLATED
+        cfg.n_orb = s.n_orb
+        cfg.n_k = s.n_k
+        cfg.kpt = _ptr(self._kpt)
+        cfg.kw = _ptr(self._kw)
+        cfg.dt = s.dt
+        cfg.precision = MIXED if prec == "mixed" else C128
+        cfg.hartree = int(bool(s.hartree))
+        cfg.xc = XC_PZ81 if s.xc else XC_NONE
+        cfg.gauge = LENGTH if s.gauge == "length" else VELOCITY
+        cfg.flags = flags
+        if torch_memory:
+            import torch
+            dev = torch.cuda.current_device()
+            self._stream = torch.cuda.Stream(device=dev)
+            self._mem = _TorchMemory(dev, self._stream.cuda_stream)
+            cfg.stream = C.c_void_p(self._stream.cuda_stream)
+            cfg.dev_alloc = self._mem.alloc_cb
+            cfg.dev_free = self._mem.free_cb
+        self._cfg = cfg
+        psi = np.ascontiguousarray(s.psi0 if psi0 is None else psi0, dtype=np.complex128)
+        assert psi.shape == (s.n_k, s.n_orb, s.n[2], s.n[1], s.n[0])
+        h = C.c_void_p()
+        st = self.lib.tddft_init(C.byref(cfg), _ptr(psi.view(np.float64)), C.byref(h))
+        if st != OK:
+            raise TDDFTError(st, "tddft_init failed (invalid configuration or device error)")
+        self.h = h
+
+    # -----------------------------------------------------------------
+    def _check(self, st):
+        if st != OK:
+            msg = self.lib.tddft_last_error(self.h)
+            raise TDDFTError(st, msg.decode() if msg else "")
+
+    def set_potential(self, v_loc=None, projectors=None):
+        s = self.system
+        v = np.ascontiguousarray(s.v_loc if v_loc is None else v_loc, dtype=np.float64)
+        projs = s.projectors if projectors is None else projectors
+        keep = []
+        atoms = (Atom * max(1, len(projs)))()
+        for i, p in enumerate(projs):
+            idx = np.ascontiguousarray(p.idx, dtype=np.int32)
+            x = np.ascontiguousarray(p.x, dtype=np.float64)
+            beta = np.ascontiguousarray(p.beta, dtype=np.float64)
+            ekb = np.ascontiguousarray(p.e_kb, dtype=np.float64)
+            keep += [idx, x, beta, ekb]
+            atoms[i].npts = idx.shape[0]
+            atoms[i].n_proj = beta.shape[0]
+            atoms[i].idx = _ptr(idx, C.c_int32)
+            atoms[i].x = _ptr(x)
+            atoms[i].beta = _ptr(beta)
+            atoms[i].e_kb = _ptr(ekb)
+        self._check(self.lib.tddft_set_potential(self.h, _ptr(v), len(projs),
+                                                 atoms if projs else None))
+        return self
+
+    def propagate(self, A: np.ndarray) -> np.ndarray:
+        A = np.ascontiguousarray(A, dtype=np.float64)
+        nsteps = A.shape[0] - 1
+        J = np.zeros((max(nsteps, 0), 3))
+        self._check(self.lib.tddft_propagate(self.h, nsteps, _ptr(A), _ptr(J)))
+        return J
+
+    def density_current(self):
+        rho = np.empty((self.n[2], self.n[1], self.n[0]))
+        J = np.empty(3)
+        self._check(self.lib.tddft_density_current(self.h, _ptr(rho), _ptr(J)))
+        return rho, J
+
+    def orbitals(self) -> np.ndarray:
+        psi = np.empty((self.n_k, self.n_orb, self.n[2], self.n[1], self.n[0]), dtype=np.complex128)
+        self._check(self.lib.tddft_get_orbitals(self.h, _ptr(psi.view(np.float64))))
+        return psi
+
+    def set_orbitals(self, psi: np.ndarray):
+        psi = np.ascontiguousarray(psi, dtype=np.complex128)
+        self._check(self.lib.tddft_set_orbitals(self.h, _ptr(psi.view(np.float64))))
+
+    def energy(self) -> float:
+        e = C.c_double()
+        self._check(self.lib.tddft_energy(self.h, C.byref(e)))
+        return e.value
+
+    def norms(self) -> np.ndarray:
+        out = np.empty((self.n_k, self.n_orb))
+        self._check(self.lib.tddft_norms(self.h, _ptr(out)))
+        return out
+
+    def dipole(self) -> np.ndarray:
+        d = np.empty(3)
+        self._check(self.lib.tddft_dipole(self.h, _ptr(d)))
+        return d
+
+    def kick(self, F0: float, axis: int):
+        self._check(self.lib.tddft_kick(self.h, float(F0), int(axis)))
+
+    def last_timing_ms(self) -> float:
+        ms = C.c_double()
+        self._check(self.lib.tddft_last_timing(self.h, C.byref(ms)))
+        return ms.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.tddft_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def mfma_layout_check(A: np.ndarray, B: np.ndarray) -> np.ndarray:
+    """Run one v_mfma_f64_16x16x4f64 with the lane layout the projector
+    kernel assumes; returns D (16 x 16) for comparison with A @ B."""
+    lib = load_library()
+    fn = lib.tddft_test_mfma_layout
+    fn.argtypes = [_dp, _dp, _dp]
+    fn.restype = C.c_int
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    B = np.ascontiguousarray(B, dtype=np.float64)
+    D = np.zeros((16, 16))
+    if fn(_ptr(A), _ptr(B), _ptr(D)) != 0:
+        raise RuntimeError("mfma layout check failed to run")
+    return D

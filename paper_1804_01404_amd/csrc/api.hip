@@ -1,0 +1,946 @@
+// C ABI of the TDKS time step (declared in include/tddft.h).
+//
+// One step, enqueued on the context's stream and captured once as a hipGraph:
+//   1. per-step parameters: kappa_k, sphere phases, length-gauge field (from
+//      the A table indexed by a device step counter);
+//   2. four Horner stages s = 4, 3, 2, 1, each preceded (when projectors are
+//      present) by the MFMA projection of its input for the nonlocal add-back;
+//   3. observables of the new orbitals (norms, momentum, kinetic and local
+//      energy sums) and the moment projections for the nonlocal current;
+//   4. density (two fixed-order passes), Hartree by FFT, LDA, new V;
+//   5. current reduction into the device J table, counter + 1.
+// The potential stays frozen at rho(t_n) during a step.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/tddft.h"
+#include "internal.h"
+
+using namespace td;
+
+namespace {
+
+const double kFdC[5] = {-205.0 / 72.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0};
+const double kFdD[4] = {4.0 / 5.0, -1.0 / 5.0, 4.0 / 105.0, -1.0 / 280.0};
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct tddft_ctx {
+  tddft_config cfg{};
+  std::vector<double> kpt, kw;
+  std::string err;
+  bool poisoned = false;
+  bool potential_set = false;
+  bool own_stream = false;
+  hipStream_t stream = nullptr;
+  int device = 0;
+
+  Geometry g{};
+  int bc = kPeriodicPlane;
+  size_t N = 0, n_orb_tot = 0;
+  bool mixed = false;
+  double dV = 0, volume = 0;
+  double lap[3][5]{}, dh[3][4]{}, cdiag = 0;
+
+  std::vector<DevBuf> owned;
+  void *W = nullptr, *U0 = nullptr, *U1 = nullptr;
+  double *Vd = nullptr, *Vloc = nullptr, *vh = nullptr, *exc = nullptr, *rho = nullptr, *rho0 = nullptr;
+  float* Vf = nullptr;
+  double* rho_part = nullptr;
+  int rho_chunk = 64, rho_nchunks = 0;
+  double2* fft = nullptr;
+  double* Kfft = nullptr;
+  int M[3] = {0, 0, 0};
+  double vh_scale = 0;
+  double *kpt_d = nullptr, *kw_d = nullptr;
+
+  // nonlocal
+  NLTables nl{};
+  double* ent_x = nullptr;
+  double2* Eu = nullptr;
+  double* jnl = nullptr;
+  double nl_bound = 0;
+  double vabs = 0;
+  int max_overlap = 0;
+
+  // per step
+  double *kappa = nullptr, *kappaJ = nullptr, *efield = nullptr, *Alast = nullptr;
+  double2 *phA = nullptr, *phAJ = nullptr;
+  double* obs = nullptr;
+  double *Atab = nullptr, *Jtab = nullptr;
+  int cap_steps = 0;
+  double* Aobs = nullptr;  // [2][3] for observation calls
+  int *counter = nullptr, *nanflag = nullptr;
+  double *scalars = nullptr, *sums = nullptr;
+  double A_last[3] = {0, 0, 0};
+
+  hipGraphExec_t graph = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  double last_ms = 0;
+};
+
+namespace {
+
+tddft_status fail(tddft_ctx* c, tddft_status st, const std::string& msg) {
+  if (c) {
+    c->err = msg;
+    if (st == TDDFT_EDEVICE || st == TDDFT_ENUMERIC) c->poisoned = true;
+  }
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                          \
+  do {                                                                                         \
+    hipError_t e_ = (expr);                                                                    \
+    if (e_ != hipSuccess)                                                                      \
+      return fail(c, TDDFT_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));        \
+  } while (0)
+
+tddft_status dalloc(tddft_ctx* c, size_t bytes, void** out) {
+  *out = nullptr;
+  if (bytes == 0) bytes = 16;
+  void* p = nullptr;
+  if (c->cfg.dev_alloc) {
+    p = c->cfg.dev_alloc(bytes, c->cfg.alloc_user);
+    if (!p) return fail(c, TDDFT_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+  } else {
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(c, TDDFT_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
+  }
+  c->owned.push_back({p, bytes});
+  *out = p;
+  return TDDFT_OK;
+}
+
+template <typename P>
+tddft_status dalloc_t(tddft_ctx* c, size_t count, P** out) {
+  void* p = nullptr;
+  tddft_status st = dalloc(c, count * sizeof(P), &p);
+  *out = static_cast<P*>(p);
+  return st;
+}
+
+void dfree_all(tddft_ctx* c) {
+  for (auto& b : c->owned) {
+    if (c->cfg.dev_free)
+      c->cfg.dev_free(b.p, c->cfg.alloc_user);
+    else
+      (void)hipFree(b.p);
+  }
+  c->owned.clear();
+}
+
+bool debug_sync(const tddft_ctx* c) { return (c->cfg.flags & TDDFT_FLAG_DEBUG_SYNC) != 0; }
+
+tddft_status check_launch(tddft_ctx* c, hipError_t e, const char* what) {
+  if (e != hipSuccess) return fail(c, TDDFT_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  if (debug_sync(c)) {
+    hipError_t s = hipStreamSynchronize(c->stream);
+    if (s != hipSuccess) return fail(c, TDDFT_EDEVICE, std::string(what) + " (sync): " + hipGetErrorString(s));
+  }
+  return TDDFT_OK;
+}
+
+#define LAUNCH(expr, what)                                   \
+  do {                                                       \
+    tddft_status st_ = check_launch(c, (expr), what);        \
+    if (st_ != TDDFT_OK) return st_;                         \
+  } while (0)
+
+// Largest divisor of n that is <= cap and >= 4 (or n itself when n <= cap).
+int tile_dim(int n, int cap) {
+  if (n <= cap) return n;
+  for (int d = cap; d >= 4; --d)
+    if (n % d == 0) return d;
+  return -1;
+}
+
+bool fft_size_ok(int m) {
+  for (int r : {2, 3, 5})
+    while (m % r == 0) m /= r;
+  return m == 1;
+}
+
+// Gauss-Legendre nodes and weights on [0, 1].
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.resize(n);
+  w.resize(n);
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      double dp = n * (z * p1 - p0) / (z * z - 1.0);
+      double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    double p0 = 1.0, p1 = z;
+    for (int k = 2; k <= n; ++k) {
+      double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    double dp = n * (z * p1 - p0) / (z * z - 1.0);
+    x[i] = 0.5 * (1.0 - z);
+    w[i] = 1.0 / ((1.0 - z * z) * dp * dp) * 2.0 * 0.5;
+  }
+}
+
+// Mean of 1/|r| over the cell [-h1/2, h1/2] x ... : split the positive octant
+// box into three pyramids with apex at the origin; in each, r = t (1, s, u)
+// turns the singular integrand into the smooth 1 / sqrt(1 + s^2 + u^2).
+double self_cell_inverse_r(double h1, double h2, double h3) {
+  std::vector<double> x, w;
+  gauss_legendre(48, x, w);
+  const double a[3] = {0.5 * h1, 0.5 * h2, 0.5 * h3};
+  double tot = 0.0;
+  for (int ax = 0; ax < 3; ++ax) {
+    const double p = a[ax], q = a[(ax + 1) % 3], r = a[(ax + 2) % 3];
+    const double S = q / p, U = r / p;
+    double I = 0.0;
+    for (int i = 0; i < 48; ++i)
+      for (int j = 0; j < 48; ++j) {
+        const double s = S * x[i], u = U * x[j];
+        I += w[i] * w[j] / std::sqrt(1.0 + s * s + u * u);
+      }
+    tot += 0.5 * p * p * I * S * U;
+  }
+  return 8.0 * tot / (h1 * h2 * h3);
+}
+
+template <typename T>
+typename Vec2<T>::type* as2(void* p) {
+  return static_cast<typename Vec2<T>::type*>(p);
+}
+
+// ---------------------------------------------------------------------------
+// enqueue helpers
+
+template <typename T>
+tddft_status enqueue_density_potential(tddft_ctx* c) {
+  const int N = (int)c->N;
+  LAUNCH(launch_rho_partial<T>(as2<T>(c->W), c->kw_d, c->cfg.n_orb, c->cfg.n_k, N, c->rho_chunk,
+                               c->rho_part, c->stream),
+         "rho_partial");
+  LAUNCH(launch_rho_reduce(c->rho_part, c->rho_nchunks, N, c->rho, c->stream), "rho_reduce");
+  if (!c->potential_set) return TDDFT_OK;
+  if (c->cfg.hartree) {
+    LAUNCH(launch_pack_rho(c->rho, c->g.n1, c->g.n2, c->g.n3, c->M[0], c->M[1], c->M[2], c->fft, c->stream),
+           "pack_rho");
+    for (int ax = 0; ax < 3; ++ax)
+      LAUNCH(launch_fft_axis(c->fft, c->M[0], c->M[1], c->M[2], ax, -1, c->stream), "fft fwd");
+    LAUNCH(launch_scale_real(c->fft, c->Kfft, (size_t)c->M[0] * c->M[1] * c->M[2], c->stream), "poisson");
+    for (int ax = 0; ax < 3; ++ax)
+      LAUNCH(launch_fft_axis(c->fft, c->M[0], c->M[1], c->M[2], ax, +1, c->stream), "fft inv");
+  }
+  LAUNCH(launch_xc_assemble(c->fft, c->g.n1, c->g.n2, c->g.n3, c->M[0], c->M[1], c->M[2], c->vh_scale,
+                            c->rho, c->Vloc, c->cfg.hartree, c->cfg.xc, c->Vd, c->Vf, c->vh, c->exc,
+                            c->stream),
+         "xc_assemble");
+  return TDDFT_OK;
+}
+
+template <typename T>
+StageArgs<T> stage_args(tddft_ctx* c) {
+  StageArgs<T> a{};
+  a.V = nullptr;
+  a.kappa = c->kappa;
+  a.efield = (c->cfg.gauge == TDDFT_LENGTH) ? c->efield : nullptr;
+  a.Eu = c->nl.n_atoms > 0 ? c->Eu : nullptr;
+  a.phA = c->phA;
+  a.nl = c->nl;
+  a.g = c->g;
+  std::memcpy(a.lap, c->lap, sizeof(a.lap));
+  std::memcpy(a.dh, c->dh, sizeof(a.dh));
+  a.cdiag = c->cdiag;
+  return a;
+}
+
+template <typename T>
+const T* vpot(tddft_ctx* c);
+template <>
+const double* vpot<double>(tddft_ctx* c) {
+  return c->Vd;
+}
+template <>
+const float* vpot<float>(tddft_ctx* c) {
+  return c->Vf;
+}
+
+// observables of W with kappaJ / phAJ already set: obs, jnl, then finish
+template <typename T>
+tddft_status enqueue_observe(tddft_ctx* c, int bump) {
+  ObserveArgs<T> oa{};
+  oa.w = as2<T>(c->W);
+  oa.Vloc = c->Vloc;
+  oa.g = c->g;
+  std::memcpy(oa.dh, c->dh, sizeof(oa.dh));
+  std::memcpy(oa.lap, c->lap, sizeof(oa.lap));
+  oa.cdiag = c->cdiag;
+  oa.out = c->obs;
+  LAUNCH(launch_observe<T>(c->bc, oa, c->stream), "observe");
+  const bool nl = c->nl.n_atoms > 0;
+  if (nl) {
+    ProjArgs<T> pa{};
+    pa.u = as2<T>(c->W);
+    pa.phA = c->phAJ;
+    pa.nl = c->nl;
+    pa.N = (int)c->N;
+    pa.n_orb = c->cfg.n_orb;
+    pa.n_orb_tot = (int)c->n_orb_tot;
+    pa.dV = c->dV;
+    pa.moments = 1;
+    pa.Eu = c->Eu;
+    pa.jnl = c->jnl;
+    LAUNCH(launch_project<T>(pa, c->stream), "project moments");
+  }
+  LAUNCH(launch_finish(c->obs, c->g.tiles_x * c->g.tiles_y, c->jnl, nl ? 1 : 0, c->kw_d, c->kappaJ,
+                       c->cfg.n_orb, c->cfg.n_k, c->dV, c->volume, c->counter, bump, c->Jtab, c->scalars,
+                       c->nanflag, c->stream),
+         "finish");
+  return TDDFT_OK;
+}
+
+template <typename T>
+tddft_status enqueue_step(tddft_ctx* c) {
+  LAUNCH(launch_step_params(c->Atab, c->counter, 1, c->kpt_d, c->cfg.n_k, c->ent_x, c->nl.n_ent,
+                            c->cfg.gauge, c->cfg.dt, c->kappa, c->kappaJ, c->efield, c->phA, c->phAJ,
+                            c->Alast, c->stream),
+         "step_params");
+  StageArgs<T> a = stage_args<T>(c);
+  a.V = vpot<T>(c);
+  void* bufs_in[4] = {c->W, c->U0, c->U1, c->U0};
+  void* bufs_out[4] = {c->U0, c->U1, c->U0, c->W};
+  for (int i = 0; i < 4; ++i) {
+    const int s = 4 - i;
+    if (c->nl.n_atoms > 0) {
+      ProjArgs<T> pa{};
+      pa.u = as2<T>(bufs_in[i]);
+      pa.phA = c->phA;
+      pa.nl = c->nl;
+      pa.N = (int)c->N;
+      pa.n_orb = c->cfg.n_orb;
+      pa.n_orb_tot = (int)c->n_orb_tot;
+      pa.dV = c->dV;
+      pa.moments = 0;
+      pa.Eu = c->Eu;
+      pa.jnl = c->jnl;
+      LAUNCH(launch_project<T>(pa, c->stream), "project");
+    }
+    a.in = as2<T>(bufs_in[i]);
+    a.w = as2<T>(c->W);
+    a.out = as2<T>(bufs_out[i]);
+    a.tau = c->cfg.dt / s;
+    const int mode = (s == 4) ? kFirst : (s == 1 ? kLast : kMid);
+    LAUNCH(launch_stage<T>(mode, c->bc, a, c->stream), "stage");
+  }
+  tddft_status st = enqueue_observe<T>(c, 1);
+  if (st != TDDFT_OK) return st;
+  return enqueue_density_potential<T>(c);
+}
+
+tddft_status step_dispatch(tddft_ctx* c) { return c->mixed ? enqueue_step<float>(c) : enqueue_step<double>(c); }
+tddft_status observe_dispatch(tddft_ctx* c) {
+  return c->mixed ? enqueue_observe<float>(c, 0) : enqueue_observe<double>(c, 0);
+}
+tddft_status potential_dispatch(tddft_ctx* c) {
+  return c->mixed ? enqueue_density_potential<float>(c) : enqueue_density_potential<double>(c);
+}
+
+// observation at the current time with the last A: set kappaJ/phAJ, run observe
+tddft_status observe_now(tddft_ctx* c) {
+  double Ab[6];
+  for (int i = 0; i < 3; ++i) Ab[i] = Ab[3 + i] = c->A_last[i];
+  HIP_TRY(hipMemcpyAsync(c->Aobs, Ab, sizeof(Ab), hipMemcpyHostToDevice, c->stream));
+  LAUNCH(launch_step_params(c->Aobs, c->counter, 0, c->kpt_d, c->cfg.n_k, c->ent_x, c->nl.n_ent,
+                            c->cfg.gauge, c->cfg.dt, c->kappa, c->kappaJ, c->efield, c->phA, c->phAJ,
+                            c->Alast, c->stream),
+         "step_params");
+  tddft_status st = observe_dispatch(c);
+  if (st != TDDFT_OK) return st;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return TDDFT_OK;
+}
+
+void invalidate_graph(tddft_ctx* c) {
+  if (c->graph) {
+    (void)hipGraphExecDestroy(c->graph);
+    c->graph = nullptr;
+  }
+}
+
+tddft_status upload_orbitals(tddft_ctx* c, const double* psi) {
+  const size_t total = c->n_orb_tot * c->N;
+  // stage through U0 (which is at least total * sizeof(T2)); for c128 copy straight into W
+  if (!c->mixed) {
+    HIP_TRY(hipMemcpyAsync(c->W, psi, total * sizeof(double2), hipMemcpyHostToDevice, c->stream));
+  } else {
+    // U0 and U1 together hold total double2 (each holds total float2)
+    HIP_TRY(hipMemcpyAsync(c->U0, psi, total * sizeof(double2), hipMemcpyHostToDevice, c->stream));
+    LAUNCH(launch_convert_in<float>(static_cast<const double2*>(c->U0), as2<float>(c->W), total, c->stream),
+           "convert_in");
+  }
+  return TDDFT_OK;
+}
+
+// kinetic + potential + nonlocal upper bound of |lambda(h)| for the stability check
+double spectral_bound(const tddft_ctx* c, double amax, double vmin, double vmax) {
+  const double h[3] = {c->g.h1, c->g.h2, c->g.h3};
+  double k2pi = 0.0;  // K2(pi) = -c0 - 2 sum c_m cos(m pi)
+  k2pi = -kFdC[0];
+  for (int m = 1; m <= 4; ++m) k2pi -= 2.0 * kFdC[m] * ((m % 2) ? -1.0 : 1.0);
+  double k1max = 0.0;  // max over theta of |K1(theta)| = |2 sum d_m sin(m theta)|
+  for (int i = 0; i <= 2000; ++i) {
+    const double th = M_PI * i / 2000.0;
+    double v = 0.0;
+    for (int m = 1; m <= 4; ++m) v += 2.0 * kFdD[m - 1] * std::sin(m * th);
+    k1max = std::max(k1max, std::fabs(v));
+  }
+  double kmax[3] = {0, 0, 0};
+  for (int k = 0; k < c->cfg.n_k; ++k)
+    for (int i = 0; i < 3; ++i) kmax[i] = std::max(kmax[i], std::fabs(c->kpt[3 * k + i]) + amax / kC);
+  double lam = 0.0, kk = 0.0;
+  for (int i = 0; i < 3; ++i) {
+    lam += 0.5 * k2pi / (h[i] * h[i]) + kmax[i] * k1max / h[i];
+    kk += kmax[i] * kmax[i];
+  }
+  lam += 0.5 * kk;
+  const double vabs = std::max(std::fabs(vmin), std::fabs(vmax));
+  return lam + vabs + c->nl_bound;
+}
+
+}  // namespace
+
+// ===========================================================================
+
+extern "C" {
+
+uint32_t tddft_abi_version(void) { return TDDFT_ABI_VERSION; }
+
+const char* tddft_last_error(const tddft_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+void tddft_free(tddft_ctx* ctx) {
+  if (!ctx) return;
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  invalidate_graph(ctx);
+  if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+  if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+  dfree_all(ctx);
+  if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+}
+
+tddft_status tddft_init(const tddft_config* cfg, const double* psi0, tddft_ctx** out) {
+  if (!out) return TDDFT_EINVAL;
+  *out = nullptr;
+  if (!cfg || !psi0) return TDDFT_EINVAL;
+  if (cfg->abi_version != TDDFT_ABI_VERSION || cfg->struct_size != sizeof(tddft_config)) return TDDFT_EINVAL;
+  auto* c = new tddft_ctx();
+  c->cfg = *cfg;
+  auto bad = [&](const std::string& m) {
+    tddft_status st = fail(c, TDDFT_EINVAL, m);
+    tddft_free(c);
+    return st;
+  };
+  for (int i = 0; i < 3; ++i) {
+    if (cfg->n[i] < 8) return bad("grid dimension below 8");
+    if (!(cfg->cell[i] > 0)) return bad("cell length must be positive");
+  }
+  if (cfg->boundary != TDDFT_PERIODIC && cfg->boundary != TDDFT_ISOLATED) return bad("boundary");
+  if (cfg->n_orb < 1 || cfg->n_k < 1) return bad("n_orb and n_k must be >= 1");
+  if (!cfg->kpt || !cfg->kw) return bad("kpt and kw are required");
+  if (!(cfg->dt != 0.0) || !std::isfinite(cfg->dt)) return bad("dt must be finite and nonzero");
+  if (cfg->precision != TDDFT_C128 && cfg->precision != TDDFT_MIXED) return bad("precision");
+  if (cfg->gauge != TDDFT_VELOCITY && cfg->gauge != TDDFT_LENGTH) return bad("gauge");
+  if (cfg->gauge == TDDFT_LENGTH && cfg->boundary != TDDFT_ISOLATED)
+    return bad("length gauge needs an isolated box");
+  if (cfg->xc != TDDFT_XC_NONE && cfg->xc != TDDFT_XC_PZ81) return bad("xc");
+  if ((cfg->dev_alloc == nullptr) != (cfg->dev_free == nullptr)) return bad("dev_alloc and dev_free go together");
+  c->kpt.assign(cfg->kpt, cfg->kpt + 3 * cfg->n_k);
+  c->kw.assign(cfg->kw, cfg->kw + cfg->n_k);
+  double ws = 0;
+  for (double v : c->kw) {
+    if (!std::isfinite(v) || v < 0) return bad("k weights must be finite and >= 0");
+    ws += v;
+  }
+  if (std::fabs(ws - 1.0) > 1e-10) return bad("k weights must sum to 1");
+  for (double v : c->kpt)
+    if (!std::isfinite(v)) return bad("k-points must be finite");
+  c->cfg.kpt = nullptr;
+  c->cfg.kw = nullptr;
+
+  Geometry& g = c->g;
+  g.n1 = cfg->n[0];
+  g.n2 = cfg->n[1];
+  g.n3 = cfg->n[2];
+  g.h1 = cfg->cell[0] / g.n1;
+  g.h2 = cfg->cell[1] / g.n2;
+  g.h3 = cfg->cell[2] / g.n3;
+  g.periodic = cfg->boundary == TDDFT_PERIODIC;
+  g.n_orb = cfg->n_orb;
+  g.n_k = cfg->n_k;
+  c->N = (size_t)g.n1 * g.n2 * g.n3;
+  if (c->N > (size_t)INT32_MAX / 2) return bad("grid too large");
+  c->n_orb_tot = (size_t)cfg->n_orb * cfg->n_k;
+  c->mixed = cfg->precision == TDDFT_MIXED;
+  c->dV = g.h1 * g.h2 * g.h3;
+  c->volume = cfg->cell[0] * cfg->cell[1] * cfg->cell[2];
+  if (g.periodic && g.n1 * g.n2 <= 1024) {
+    c->bc = kPeriodicPlane;
+    g.TX = g.n1;
+    g.TY = g.n2;
+  } else {
+    c->bc = g.periodic ? kPeriodicTile : kIsolatedTile;
+    g.TX = tile_dim(g.n1, 32);
+    g.TY = g.TX > 0 ? tile_dim(g.n2, std::max(4, 1024 / g.TX)) : -1;
+    if (g.TX < 4 || g.TY < 4 || g.TX * g.TY > 1024) return bad("no workgroup tiling for this grid");
+  }
+  g.tiles_x = g.n1 / g.TX;
+  g.tiles_y = g.n2 / g.TY;
+  const double h[3] = {g.h1, g.h2, g.h3};
+  c->cdiag = 0;
+  for (int mu = 0; mu < 3; ++mu) {
+    for (int m = 0; m < 5; ++m) c->lap[mu][m] = -0.5 * kFdC[m] / (h[mu] * h[mu]);
+    for (int m = 0; m < 4; ++m) c->dh[mu][m] = kFdD[m] / h[mu];
+    c->cdiag += c->lap[mu][0];
+  }
+  if (cfg->hartree) {
+    for (int i = 0; i < 3; ++i) {
+      c->M[i] = g.periodic ? cfg->n[i] : 2 * cfg->n[i];
+      if (!fft_size_ok(c->M[i])) return bad("FFT sizes must have prime factors 2, 3, 5 only");
+    }
+  } else {
+    c->M[0] = g.n1;
+    c->M[1] = g.n2;
+    c->M[2] = g.n3;
+  }
+
+  if (cfg->stream) {
+    c->stream = static_cast<hipStream_t>(cfg->stream);
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+      tddft_status st = fail(c, TDDFT_EDEVICE, "hipStreamCreate failed");
+      tddft_free(c);
+      return st;
+    }
+    c->own_stream = true;
+  }
+  (void)hipGetDevice(&c->device);
+  auto cleanup = [&](tddft_status st) {
+    std::string m = c->err;
+    tddft_free(c);
+    (void)m;
+    return st;
+  };
+  tddft_status st = TDDFT_OK;
+  const size_t esz = c->mixed ? sizeof(float2) : sizeof(double2);
+  const size_t total = c->n_orb_tot * c->N;
+  // the two stage buffers are contiguous so that a c128 upload can be staged through them
+  void* u01 = nullptr;
+  if ((st = dalloc(c, total * esz, &c->W)) != TDDFT_OK) return cleanup(st);
+  if ((st = dalloc(c, 2 * total * esz, &u01)) != TDDFT_OK) return cleanup(st);
+  c->U0 = u01;
+  c->U1 = static_cast<char*>(u01) + total * esz;
+  const size_t N = c->N;
+  if ((st = dalloc_t(c, N, &c->Vd)) || (st = dalloc_t(c, N, &c->Vf)) || (st = dalloc_t(c, N, &c->Vloc)) ||
+      (st = dalloc_t(c, N, &c->vh)) || (st = dalloc_t(c, N, &c->exc)) || (st = dalloc_t(c, N, &c->rho)) ||
+      (st = dalloc_t(c, N, &c->rho0)))
+    return cleanup(st);
+  c->rho_chunk = 64;
+  c->rho_nchunks = (int)((c->n_orb_tot + c->rho_chunk - 1) / c->rho_chunk);
+  if ((st = dalloc_t(c, (size_t)c->rho_nchunks * N, &c->rho_part))) return cleanup(st);
+  const size_t Mt = (size_t)c->M[0] * c->M[1] * c->M[2];
+  if ((st = dalloc_t(c, Mt, &c->fft)) || (st = dalloc_t(c, Mt, &c->Kfft))) return cleanup(st);
+  if ((st = dalloc_t(c, 3 * (size_t)cfg->n_k, &c->kpt_d)) || (st = dalloc_t(c, (size_t)cfg->n_k, &c->kw_d)) ||
+      (st = dalloc_t(c, 3 * (size_t)cfg->n_k, &c->kappa)) || (st = dalloc_t(c, 3 * (size_t)cfg->n_k, &c->kappaJ)) ||
+      (st = dalloc_t(c, 3, &c->efield)) || (st = dalloc_t(c, 3, &c->Alast)) || (st = dalloc_t(c, 6, &c->Aobs)) ||
+      (st = dalloc_t(c, 1, &c->counter)) || (st = dalloc_t(c, 1, &c->nanflag)) ||
+      (st = dalloc_t(c, 8, &c->scalars)) || (st = dalloc_t(c, 8, &c->sums)) ||
+      (st = dalloc_t(c, c->n_orb_tot * g.tiles_x * g.tiles_y * 8, &c->obs)) ||
+      (st = dalloc_t(c, c->n_orb_tot * 4, &c->jnl)) || (st = dalloc_t(c, 1, &c->phA)) ||
+      (st = dalloc_t(c, 1, &c->phAJ)) || (st = dalloc_t(c, 3, &c->ent_x)))
+    return cleanup(st);
+  if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess)
+    return cleanup(fail(c, TDDFT_EDEVICE, "hipEventCreate failed"));
+  if (hipMemcpyAsync(c->kpt_d, c->kpt.data(), 3 * sizeof(double) * cfg->n_k, hipMemcpyHostToDevice, c->stream) ||
+      hipMemcpyAsync(c->kw_d, c->kw.data(), sizeof(double) * cfg->n_k, hipMemcpyHostToDevice, c->stream))
+    return cleanup(fail(c, TDDFT_EDEVICE, "upload of k-points failed"));
+  if ((st = upload_orbitals(c, psi0)) != TDDFT_OK) return cleanup(st);
+  if (launch_fill(c->Vloc, 0.0, N, c->stream) != hipSuccess || launch_fill(c->vh, 0.0, N, c->stream) != hipSuccess ||
+      launch_fill(c->exc, 0.0, N, c->stream) != hipSuccess)
+    return cleanup(fail(c, TDDFT_EDEVICE, "initial fill failed"));
+  if (launch_set_int(c->nanflag, 0, c->stream) != hipSuccess)
+    return cleanup(fail(c, TDDFT_EDEVICE, "flag reset failed"));
+  if ((st = potential_dispatch(c)) != TDDFT_OK) return cleanup(st);
+  if (hipMemcpyAsync(c->rho0, c->rho, N * sizeof(double), hipMemcpyDeviceToDevice, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess)
+    return cleanup(fail(c, TDDFT_EDEVICE, "initial density failed"));
+  *out = c;
+  return TDDFT_OK;
+}
+
+tddft_status tddft_set_potential(tddft_ctx* c, const double* v_loc, int32_t n_atoms, const tddft_atom* atoms) {
+  if (!c) return TDDFT_EINVAL;
+  if (c->poisoned) return fail(c, TDDFT_ESTATE, "context poisoned: " + c->err);
+  if (!v_loc || n_atoms < 0 || (n_atoms > 0 && !atoms)) return fail(c, TDDFT_EINVAL, "bad potential arguments");
+  const size_t N = c->N;
+  double vmin = 1e300, vmax = -1e300;
+  for (size_t i = 0; i < N; ++i) {
+    if (!std::isfinite(v_loc[i])) return fail(c, TDDFT_EINVAL, "v_loc not finite");
+    vmin = std::min(vmin, v_loc[i]);
+    vmax = std::max(vmax, v_loc[i]);
+  }
+  // ---- nonlocal tables on the host
+  std::vector<int> atom_start(1, 0), ent_idx, ent_atom;
+  std::vector<double> ent_B, atom_E, ent_x;
+  std::vector<int> cover(N, 0);
+  double nl_bound = 0;
+  for (int a = 0; a < n_atoms; ++a) {
+    const tddft_atom& A = atoms[a];
+    if (A.npts < 1 || A.n_proj < 1 || A.n_proj > kMaxProj || !A.idx || !A.x || !A.beta || !A.e_kb)
+      return fail(c, TDDFT_EINVAL, "atom " + std::to_string(a) + ": bad projector table");
+    double ebound = 0;
+    for (int p = 0; p < kMaxProj; ++p) {
+      const double E = p < A.n_proj ? A.e_kb[p] : 0.0;
+      if (!std::isfinite(E)) return fail(c, TDDFT_EINVAL, "KB energy not finite");
+      atom_E.push_back(E);
+      ebound += std::fabs(E);
+    }
+    nl_bound = std::max(nl_bound, ebound);
+    std::vector<char> seen(N, 0);
+    for (int i = 0; i < A.npts; ++i) {
+      const int idx = A.idx[i];
+      if (idx < 0 || (size_t)idx >= N) return fail(c, TDDFT_EINVAL, "projector index out of range");
+      if (seen[idx]) return fail(c, TDDFT_EINVAL, "duplicate projector index within an atom");
+      seen[idx] = 1;
+      cover[idx]++;
+      ent_idx.push_back(idx);
+      ent_atom.push_back(a);
+      const double x[3] = {A.x[3 * i], A.x[3 * i + 1], A.x[3 * i + 2]};
+      for (int d = 0; d < 3; ++d) {
+        if (!std::isfinite(x[d])) return fail(c, TDDFT_EINVAL, "projector offset not finite");
+        ent_x.push_back(x[d]);
+      }
+      for (int p = 0; p < kMaxProj; ++p) {
+        const double b = p < A.n_proj ? A.beta[(size_t)p * A.npts + i] : 0.0;
+        if (!std::isfinite(b)) return fail(c, TDDFT_EINVAL, "projector value not finite");
+        ent_B.push_back(b);
+        ent_B.push_back(b * x[0]);
+        ent_B.push_back(b * x[1]);
+        ent_B.push_back(b * x[2]);
+      }
+    }
+    atom_start.push_back((int)ent_idx.size());
+  }
+  const int S = (int)ent_idx.size();
+  int max_overlap = 0;
+  std::vector<int> pt_ptr(N + 1, 0);
+  for (size_t p = 0; p < N; ++p) {
+    pt_ptr[p + 1] = pt_ptr[p] + cover[p];
+    max_overlap = std::max(max_overlap, cover[p]);
+  }
+  std::vector<int> pt_ent(std::max(S, 1)), fillpos(pt_ptr.begin(), pt_ptr.end() - 1);
+  for (int e = 0; e < S; ++e) pt_ent[fillpos[ent_idx[e]]++] = e;
+  c->nl_bound = nl_bound * std::max(1, max_overlap);
+  c->max_overlap = max_overlap;
+  // exp(i k . x_e)
+  std::vector<double2> phk((size_t)c->cfg.n_k * std::max(S, 1));
+  for (int k = 0; k < c->cfg.n_k; ++k)
+    for (int e = 0; e < S; ++e) {
+      const double arg = c->kpt[3 * k] * ent_x[3 * e] + c->kpt[3 * k + 1] * ent_x[3 * e + 1] +
+                         c->kpt[3 * k + 2] * ent_x[3 * e + 2];
+      phk[(size_t)k * S + e] = make_double2(std::cos(arg), std::sin(arg));
+    }
+  // stability: |lambda| dt <= 2 sqrt 2 for the truncated fourth-order Taylor step
+  c->vabs = std::max(std::fabs(vmin), std::fabs(vmax));
+  const double lam = spectral_bound(c, 0.0, vmin, vmax);
+  if (std::fabs(c->cfg.dt) * lam > 2.0 * std::sqrt(2.0) && !(c->cfg.flags & TDDFT_FLAG_ALLOW_UNSTABLE)) {
+    char buf[200];
+    std::snprintf(buf, sizeof buf, "unstable: |dt| * lambda_max = %.4g > 2 sqrt 2 (lambda_max <= %.4g Ha)",
+                  std::fabs(c->cfg.dt) * lam, lam);
+    return fail(c, TDDFT_EUNSTABLE, buf);
+  }
+  // ---- device copies (replace any previous tables)
+  invalidate_graph(c);
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  tddft_status st;
+  int *d_atom_start, *d_ent_idx, *d_ent_atom, *d_pt_ptr, *d_pt_ent;
+  double *d_ent_B, *d_atom_E, *d_ent_x;
+  double2 *d_phk, *d_phA, *d_phAJ, *d_Eu;
+  double* d_jnl;
+  const int nA = std::max(n_atoms, 1);
+  const int Sx = std::max(S, 1);
+  if ((st = dalloc_t(c, atom_start.size(), &d_atom_start)) || (st = dalloc_t(c, Sx, &d_ent_idx)) ||
+      (st = dalloc_t(c, Sx, &d_ent_atom)) || (st = dalloc_t(c, N + 1, &d_pt_ptr)) ||
+      (st = dalloc_t(c, pt_ent.size(), &d_pt_ent)) || (st = dalloc_t(c, (size_t)Sx * kCols, &d_ent_B)) ||
+      (st = dalloc_t(c, (size_t)nA * kMaxProj, &d_atom_E)) || (st = dalloc_t(c, (size_t)Sx * 3, &d_ent_x)) ||
+      (st = dalloc_t(c, phk.size(), &d_phk)) || (st = dalloc_t(c, Sx, &d_phA)) ||
+      (st = dalloc_t(c, Sx, &d_phAJ)) ||
+      (st = dalloc_t(c, c->n_orb_tot * nA * kMaxProj, &d_Eu)) || (st = dalloc_t(c, c->n_orb_tot * 4, &d_jnl)))
+    return st;
+  auto up = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
+    if (bytes == 0) return hipSuccess;
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->stream);
+  };
+  HIP_TRY(up(d_atom_start, atom_start.data(), atom_start.size() * sizeof(int)));
+  HIP_TRY(up(d_ent_idx, ent_idx.data(), S * sizeof(int)));
+  HIP_TRY(up(d_ent_atom, ent_atom.data(), S * sizeof(int)));
+  HIP_TRY(up(d_pt_ptr, pt_ptr.data(), (N + 1) * sizeof(int)));
+  HIP_TRY(up(d_pt_ent, pt_ent.data(), S * sizeof(int)));
+  HIP_TRY(up(d_ent_B, ent_B.data(), ent_B.size() * sizeof(double)));
+  HIP_TRY(up(d_atom_E, atom_E.data(), atom_E.size() * sizeof(double)));
+  HIP_TRY(up(d_ent_x, ent_x.data(), ent_x.size() * sizeof(double)));
+  HIP_TRY(up(d_phk, phk.data(), (size_t)c->cfg.n_k * S * sizeof(double2)));
+  HIP_TRY(up(c->Vloc, v_loc, N * sizeof(double)));
+  c->nl.n_atoms = n_atoms;
+  c->nl.n_ent = S;
+  c->nl.atom_start = d_atom_start;
+  c->nl.ent_idx = d_ent_idx;
+  c->nl.ent_atom = d_ent_atom;
+  c->nl.ent_B = d_ent_B;
+  c->nl.atom_E = d_atom_E;
+  c->nl.pt_ptr = d_pt_ptr;
+  c->nl.pt_ent = d_pt_ent;
+  c->nl.phk = d_phk;
+  c->ent_x = d_ent_x;
+  c->phA = d_phA;
+  c->phAJ = d_phAJ;
+  c->Eu = d_Eu;
+  c->jnl = d_jnl;
+  // ---- Hartree kernel in Fourier space
+  if (c->cfg.hartree) {
+    const size_t Mt = (size_t)c->M[0] * c->M[1] * c->M[2];
+    const Geometry& g = c->g;
+    if (g.periodic) {
+      std::vector<double> K(Mt);
+      for (int z = 0; z < c->M[2]; ++z)
+        for (int y = 0; y < c->M[1]; ++y)
+          for (int x = 0; x < c->M[0]; ++x) {
+            const int mi[3] = {x, y, z};
+            double G2 = 0;
+            for (int d = 0; d < 3; ++d) {
+              int m = mi[d];
+              if (m > c->M[d] / 2) m -= c->M[d];
+              if (2 * m == c->M[d]) m = -m;  // Nyquist: same |G|
+              const double G = 2.0 * M_PI * m / c->cfg.cell[d];
+              G2 += G * G;
+            }
+            K[((size_t)z * c->M[1] + y) * c->M[0] + x] = G2 > 0 ? 4.0 * M_PI / G2 : 0.0;
+          }
+      HIP_TRY(up(c->Kfft, K.data(), Mt * sizeof(double)));
+      c->vh_scale = 1.0 / (double)Mt;
+    } else {
+      // g on the doubled box: 1/|d| for d != 0 and the cell average of 1/r at 0
+      const double g0 = self_cell_inverse_r(g.h1, g.h2, g.h3);
+      std::vector<double2> gk(Mt);
+      for (int z = 0; z < c->M[2]; ++z)
+        for (int y = 0; y < c->M[1]; ++y)
+          for (int x = 0; x < c->M[0]; ++x) {
+            const int ii[3] = {x, y, z};
+            double r2 = 0;
+            for (int d = 0; d < 3; ++d) {
+              const int n = c->cfg.n[d];
+              const int off = ii[d] < n ? ii[d] : ii[d] - 2 * n;
+              const double hh = c->cfg.cell[d] / n;
+              r2 += (off * hh) * (off * hh);
+            }
+            gk[((size_t)z * c->M[1] + y) * c->M[0] + x] = make_double2(r2 > 0 ? 1.0 / std::sqrt(r2) : g0, 0.0);
+          }
+      HIP_TRY(up(c->fft, gk.data(), Mt * sizeof(double2)));
+      for (int ax = 0; ax < 3; ++ax)
+        LAUNCH(launch_fft_axis(c->fft, c->M[0], c->M[1], c->M[2], ax, -1, c->stream), "fft kernel");
+      LAUNCH(launch_real_part(c->fft, c->Kfft, Mt, c->stream), "fft kernel real part");
+      c->vh_scale = c->dV / (double)Mt;
+    }
+  }
+  c->potential_set = true;
+  st = potential_dispatch(c);
+  if (st != TDDFT_OK) return st;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return TDDFT_OK;
+}
+
+tddft_status tddft_propagate(tddft_ctx* c, int32_t nsteps, const double* A, double* J_out) {
+  if (!c) return TDDFT_EINVAL;
+  if (c->poisoned) return fail(c, TDDFT_ESTATE, "context poisoned: " + c->err);
+  if (!c->potential_set) return fail(c, TDDFT_ESTATE, "propagate before set_potential");
+  if (nsteps < 0 || (nsteps > 0 && !A)) return fail(c, TDDFT_EINVAL, "bad propagate arguments");
+  if (nsteps == 0) return TDDFT_OK;
+  double amax = 0;
+  for (size_t i = 0; i < 3 * (size_t)(nsteps + 1); ++i) {
+    if (!std::isfinite(A[i])) return fail(c, TDDFT_EINVAL, "A table not finite");
+    amax = std::max(amax, std::fabs(A[i]));
+  }
+  if (c->cfg.gauge == TDDFT_VELOCITY && !(c->cfg.flags & TDDFT_FLAG_ALLOW_UNSTABLE)) {
+    // the potential part was checked in set_potential; recheck the kinetic part with |A|
+    const double lam = spectral_bound(c, amax, -c->vabs, c->vabs);
+    if (std::fabs(c->cfg.dt) * lam > 2.0 * std::sqrt(2.0))
+      return fail(c, TDDFT_EUNSTABLE, "unstable for this A table: |dt| lambda_max > 2 sqrt 2");
+  }
+  if (nsteps > c->cap_steps) {
+    invalidate_graph(c);
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    int cap = std::max(nsteps, 2 * c->cap_steps);
+    tddft_status st;
+    if ((st = dalloc_t(c, 3 * (size_t)(cap + 1), &c->Atab)) || (st = dalloc_t(c, 3 * (size_t)cap, &c->Jtab)))
+      return st;
+    c->cap_steps = cap;
+  }
+  HIP_TRY(hipMemcpyAsync(c->Atab, A, 3 * sizeof(double) * (nsteps + 1), hipMemcpyHostToDevice, c->stream));
+  LAUNCH(launch_set_int(c->counter, 0, c->stream), "counter reset");
+  const bool use_graph = !(c->cfg.flags & (TDDFT_FLAG_NO_GRAPH | TDDFT_FLAG_DEBUG_SYNC));
+  if (use_graph && !c->graph) {
+    hipGraph_t gr;
+    HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    tddft_status st = step_dispatch(c);
+    hipError_t e = hipStreamEndCapture(c->stream, &gr);
+    if (st != TDDFT_OK) return st;
+    if (e != hipSuccess) return fail(c, TDDFT_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&c->graph, gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
+    if (e != hipSuccess) return fail(c, TDDFT_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+  }
+  HIP_TRY(hipEventRecord(c->ev0, c->stream));
+  for (int n = 0; n < nsteps; ++n) {
+    if (use_graph) {
+      HIP_TRY(hipGraphLaunch(c->graph, c->stream));
+    } else {
+      tddft_status st = step_dispatch(c);
+      if (st != TDDFT_OK) return st;
+    }
+  }
+  HIP_TRY(hipEventRecord(c->ev1, c->stream));
+  if (J_out)
+    HIP_TRY(hipMemcpyAsync(J_out, c->Jtab, 3 * sizeof(double) * nsteps, hipMemcpyDeviceToHost, c->stream));
+  int flag = 0;
+  HIP_TRY(hipMemcpyAsync(&flag, c->nanflag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  float ms = 0;
+  HIP_TRY(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+  c->last_ms = ms / nsteps;
+  for (int i = 0; i < 3; ++i) c->A_last[i] = A[3 * (size_t)nsteps + i];
+  if (flag) return fail(c, TDDFT_ENUMERIC, "NaN or Inf in the orbital norms or current");
+  return TDDFT_OK;
+}
+
+tddft_status tddft_density_current(tddft_ctx* c, double* rho, double* J) {
+  if (!c) return TDDFT_EINVAL;
+  if (c->poisoned) return fail(c, TDDFT_ESTATE, "context poisoned: " + c->err);
+  if (rho) {
+    HIP_TRY(hipMemcpyAsync(rho, c->rho, c->N * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+  }
+  if (J) {
+    tddft_status st = observe_now(c);
+    if (st != TDDFT_OK) return st;
+    HIP_TRY(hipMemcpy(J, c->scalars, 3 * sizeof(double), hipMemcpyDeviceToHost));
+  }
+  return TDDFT_OK;
+}
+
+tddft_status tddft_get_orbitals(tddft_ctx* c, double* psi) {
+  if (!c || !psi) return c ? fail(c, TDDFT_EINVAL, "null psi") : TDDFT_EINVAL;
+  if (c->poisoned) return fail(c, TDDFT_ESTATE, "context poisoned: " + c->err);
+  const size_t total = c->n_orb_tot * c->N;
+  if (!c->mixed) {
+    HIP_TRY(hipMemcpyAsync(psi, c->W, total * sizeof(double2), hipMemcpyDeviceToHost, c->stream));
+  } else {
+    LAUNCH(launch_convert_out<float>(as2<float>(c->W), static_cast<double2*>(c->U0), total, c->stream),
+           "convert_out");
+    HIP_TRY(hipMemcpyAsync(psi, c->U0, total * sizeof(double2), hipMemcpyDeviceToHost, c->stream));
+  }
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return TDDFT_OK;
+}
+
+tddft_status tddft_set_orbitals(tddft_ctx* c, const double* psi) {
+  if (!c || !psi) return c ? fail(c, TDDFT_EINVAL, "null psi") : TDDFT_EINVAL;
+  if (c->poisoned) return fail(c, TDDFT_ESTATE, "context poisoned: " + c->err);
+  tddft_status st = upload_orbitals(c, psi);
+  if (st != TDDFT_OK) return st;
+  st = potential_dispatch(c);
+  if (st != TDDFT_OK) return st;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return TDDFT_OK;
+}
+
+tddft_status tddft_energy(tddft_ctx* c, double* E) {
+  if (!c || !E) return c ? fail(c, TDDFT_EINVAL, "null E") : TDDFT_EINVAL;
+  if (c->poisoned) return fail(c, TDDFT_ESTATE, "context poisoned: " + c->err);
+  if (!c->potential_set) return fail(c, TDDFT_ESTATE, "energy before set_potential");
+  tddft_status st = observe_now(c);
+  if (st != TDDFT_OK) return st;
+  LAUNCH(launch_grid_sums(c->rho, c->rho0, c->vh, c->exc, c->g, c->sums, c->stream), "grid_sums");
+  double sc[8], gs[8];
+  HIP_TRY(hipMemcpyAsync(sc, c->scalars, sizeof(sc), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipMemcpyAsync(gs, c->sums, sizeof(gs), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  *E = sc[3] + (c->cfg.hartree ? gs[0] : 0.0) + (c->cfg.xc ? gs[1] : 0.0);
+  return TDDFT_OK;
+}
+
+tddft_status tddft_norms(tddft_ctx* c, double* norms) {
+  if (!c || !norms) return c ? fail(c, TDDFT_EINVAL, "null norms") : TDDFT_EINVAL;
+  if (c->poisoned) return fail(c, TDDFT_ESTATE, "context poisoned: " + c->err);
+  tddft_status st = observe_now(c);
+  if (st != TDDFT_OK) return st;
+  const int tiles = c->g.tiles_x * c->g.tiles_y;
+  std::vector<double> obs(c->n_orb_tot * tiles * 8);
+  HIP_TRY(hipMemcpy(obs.data(), c->obs, obs.size() * sizeof(double), hipMemcpyDeviceToHost));
+  for (size_t o = 0; o < c->n_orb_tot; ++o) {
+    double s = 0;
+    for (int t = 0; t < tiles; ++t) s += obs[(o * tiles + t) * 8];
+    norms[o] = s * c->dV;
+  }
+  return TDDFT_OK;
+}
+
+tddft_status tddft_dipole(tddft_ctx* c, double d[3]) {
+  if (!c || !d) return c ? fail(c, TDDFT_EINVAL, "null d") : TDDFT_EINVAL;
+  if (c->poisoned) return fail(c, TDDFT_ESTATE, "context poisoned: " + c->err);
+  LAUNCH(launch_grid_sums(c->rho, c->rho0, c->vh, c->exc, c->g, c->sums, c->stream), "grid_sums");
+  double gs[8];
+  HIP_TRY(hipMemcpyAsync(gs, c->sums, sizeof(gs), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  for (int i = 0; i < 3; ++i) d[i] = gs[2 + i];
+  return TDDFT_OK;
+}
+
+tddft_status tddft_kick(tddft_ctx* c, double F0, int32_t axis) {
+  if (!c) return TDDFT_EINVAL;
+  if (c->poisoned) return fail(c, TDDFT_ESTATE, "context poisoned: " + c->err);
+  if (c->g.periodic) return fail(c, TDDFT_EINVAL, "kick needs an isolated box (periodic: use the A table)");
+  if (axis < 0 || axis > 2 || !std::isfinite(F0)) return fail(c, TDDFT_EINVAL, "bad kick arguments");
+  if (c->mixed)
+    LAUNCH(launch_kick<float>(as2<float>(c->W), c->g, F0, axis, c->n_orb_tot, c->stream), "kick");
+  else
+    LAUNCH(launch_kick<double>(as2<double>(c->W), c->g, F0, axis, c->n_orb_tot, c->stream), "kick");
+  tddft_status st = potential_dispatch(c);
+  if (st != TDDFT_OK) return st;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return TDDFT_OK;
+}
+
+tddft_status tddft_last_timing(tddft_ctx* c, double* ms) {
+  if (!c || !ms) return TDDFT_EINVAL;
+  *ms = c->last_ms;
+  return TDDFT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,143 @@
+// Internal declarations shared by the kernels and the C ABI layer.
+// Device layout (all in HBM, owned by the context):
+//   W, U0, U1   orbitals and the two Horner stage buffers,
+//               [n_k][n_orb][n3][n2][n1] of T2 (double2 or float2)
+//   V           total Kohn-Sham potential [N] in double and in float
+//   NL tables   sphere entries grouped by atom (see NLTables)
+//   per-step    kappa [n_k][3], kappaJ [n_k][3], E [3], phA [S], phAJ [S]
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace td {
+
+constexpr double kC = 137.035999084;   // speed of light, atomic units
+constexpr int kHalf = 4;               // stencil half width (9 points per axis)
+constexpr int kMaxProj = 4;            // projectors per atom
+constexpr int kMoments = 4;            // beta, x beta, y beta, z beta
+constexpr int kCols = kMaxProj * kMoments;  // MFMA B-matrix columns (16)
+
+enum StageMode { kFirst = 0, kMid = 1, kLast = 2 };
+enum BcKind { kPeriodicPlane = 0, kPeriodicTile = 1, kIsolatedTile = 2 };
+
+// Nonlocal tables on the device. Entries e = 0..S-1 are grouped by atom:
+// atom a owns entries [atom_start[a], atom_start[a+1]).
+struct NLTables {
+  int n_atoms = 0;
+  int n_ent = 0;
+  const int* atom_start = nullptr;   // [n_atoms + 1]
+  const int* ent_idx = nullptr;      // [S] flat grid index
+  const int* ent_atom = nullptr;     // [S]
+  const double* ent_B = nullptr;     // [S][16]: column 4p+m = beta_p * (1, x, y, z)[m]
+  const double* atom_E = nullptr;    // [n_atoms][4] KB energies (0 where absent)
+  const int* pt_ptr = nullptr;       // [N + 1] per grid point: entries covering it
+  const int* pt_ent = nullptr;       // [nnz]
+  const double2* phk = nullptr;      // [n_k][S] exp(i k . x_e)
+};
+
+struct Geometry {
+  int n1, n2, n3;
+  double h1, h2, h3;
+  int periodic;
+  int n_orb, n_k;         // orbitals per k-point, k-points
+  // tiling of the stage kernels
+  int TX, TY, tiles_x, tiles_y;
+};
+
+template <typename T> struct Vec2;
+template <> struct Vec2<double> { using type = double2; };
+template <> struct Vec2<float> { using type = float2; };
+
+template <typename T>
+struct StageArgs {
+  using T2 = typename Vec2<T>::type;
+  const T2* in;            // u_s (the first stage reads W here)
+  const T2* w;             // W (Horner base), unused by the first stage
+  T2* out;                 // u_{s-1}; the last stage writes W in place
+  const T* V;              // total potential in the stage precision
+  const double* kappa;     // [n_k][3] for this step
+  const double* efield;    // [3] length gauge field, or nullptr
+  const double2* Eu;       // [n_orb_tot][n_atoms][4] E_p u_p, or nullptr
+  const double2* phA;      // [S] exp(i A.x/c) for this step
+  NLTables nl;
+  Geometry g;
+  double lap[3][5];        // -1/2 c_m / h_mu^2
+  double dh[3][4];         // d_m / h_mu
+  double cdiag;            // sum_mu -1/2 c_0 / h_mu^2
+  double tau;              // dt / s
+};
+
+template <typename T>
+struct ObserveArgs {
+  using T2 = typename Vec2<T>::type;
+  const T2* w;
+  const double* Vloc;      // [N]
+  Geometry g;
+  double dh[3][4];
+  double lap[3][5];
+  double cdiag;
+  double* out;             // [n_orb_tot][tiles][8]: norm, p_x, p_y, p_z, kin, vloc
+};
+
+template <typename T>
+struct ProjArgs {
+  using T2 = typename Vec2<T>::type;
+  const T2* u;             // [n_orb_tot][N]
+  const double2* phA;      // [S]
+  NLTables nl;
+  int N;
+  int n_orb, n_orb_tot;
+  double dV;
+  int moments;             // 0: stage projections -> Eu; 1: all 16 columns -> proj
+  double2* Eu;             // [n_orb_tot][n_atoms][4]
+  double* jnl;             // moments: [n_orb_tot][4]: nonlocal current (3) and energy
+};
+
+// ---- launchers (defined in the .hip files) --------------------------------
+template <typename T>
+hipError_t launch_stage(int mode, int bc, const StageArgs<T>& a, hipStream_t s);
+template <typename T>
+hipError_t launch_observe(int bc, const ObserveArgs<T>& a, hipStream_t s);
+template <typename T>
+hipError_t launch_project(const ProjArgs<T>& a, hipStream_t s);
+
+hipError_t launch_step_params(const double* A, const int* counter, int use_counter,
+                              const double* kpt, int n_k, const double* ent_x, int S, int gauge,
+                              double dt, double* kappa, double* kappaJ, double* efield, double2* phA,
+                              double2* phAJ, double* Alast, hipStream_t s);
+
+template <typename T>
+hipError_t launch_rho_partial(const typename Vec2<T>::type* w, const double* kw, int n_orb, int n_k,
+                              int N, int chunk, double* part, hipStream_t s);
+hipError_t launch_rho_reduce(const double* part, int nchunks, int N, double* rho, hipStream_t s);
+
+hipError_t launch_fft_axis(double2* data, int M1, int M2, int M3, int axis, int sign, hipStream_t s);
+hipError_t launch_pack_rho(const double* rho, int n1, int n2, int n3, int M1, int M2, int M3,
+                           double2* data, hipStream_t s);
+hipError_t launch_scale_real(double2* data, const double* K, size_t total, hipStream_t s);
+hipError_t launch_xc_assemble(const double2* data, int n1, int n2, int n3, int M1, int M2, int M3,
+                              double vh_scale, const double* rho, const double* Vloc, int hartree,
+                              int xc, double* Vd, float* Vf, double* vh, double* exc,
+                              hipStream_t s);
+
+hipError_t launch_finish(const double* obs, int tiles, const double* jnl, int use_nl,
+                         const double* kw, const double* kappaJ, int n_orb, int n_k, double dV,
+                         double volume, int* counter, int bump, double* Jtab, double* scalars,
+                         int* nanflag, hipStream_t s);
+
+hipError_t launch_grid_sums(const double* rho, const double* rho0, const double* vh,
+                            const double* exc, Geometry g, double* out, hipStream_t s);
+
+template <typename T>
+hipError_t launch_convert_in(const double2* src, typename Vec2<T>::type* dst, size_t n, hipStream_t s);
+template <typename T>
+hipError_t launch_convert_out(const typename Vec2<T>::type* src, double2* dst, size_t n, hipStream_t s);
+template <typename T>
+hipError_t launch_kick(typename Vec2<T>::type* w, Geometry g, double F0, int axis, size_t n_orb_tot,
+                       hipStream_t s);
+hipError_t launch_set_int(int* p, int v, hipStream_t s);
+hipError_t launch_real_part(const double2* src, double* dst, size_t n, hipStream_t s);
+hipError_t launch_fill(double* p, double v, size_t n, hipStream_t s);
+
+}  // namespace td

@@ -1,0 +1,611 @@
+// Grid-side kernels of one time step: per-step field parameters, the density
+// (Eq. rho), the Hartree potential by FFT (periodic 4 pi / G^2; isolated
+// free-space convolution on a doubled box), the adiabatic PZ81 LDA (Sec. 3.1),
+// the macroscopic current reduction (Eq. macro_current) and the step counter.
+// Every reduction runs in a fixed order, so two runs give identical bits.
+#include "internal.h"
+
+namespace td {
+
+// ---------------------------------------------------------------- parameters
+// A: table [..][3]; the step index n is *counter (or 0). Velocity gauge:
+// kappa = k + (A_n + A_{n+1}) / (2c), kappaJ = k + A_{n+1} / c, and the
+// matching sphere phases exp(i A.x / c). Length gauge: kappa = kappaJ = k,
+// unit phases, E_n = -(A_{n+1} - A_n) / (c dt).
+__global__ void k_step_params(const double* A, const int* counter, int use_counter,
+                              const double* kpt, int n_k, const double* ent_x, int S, int gauge,
+                              double dt, double* kappa, double* kappaJ, double* efield,
+                              double2* phA, double2* phAJ, double* Alast) {
+  const int n = use_counter ? *counter : 0;
+  const double* A0 = A + 3 * (size_t)n;
+  const double* A1 = A0 + 3;
+  double ab[3], a1[3];
+  for (int i = 0; i < 3; ++i) {
+    ab[i] = 0.5 * (A0[i] + A1[i]);
+    a1[i] = A1[i];
+  }
+  const bool vel = (gauge == 0);
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (blockIdx.x == 0) {
+    for (int k = threadIdx.x; k < n_k; k += blockDim.x) {
+      for (int i = 0; i < 3; ++i) {
+        kappa[3 * k + i] = kpt[3 * k + i] + (vel ? ab[i] / kC : 0.0);
+        kappaJ[3 * k + i] = kpt[3 * k + i] + (vel ? a1[i] / kC : 0.0);
+      }
+    }
+    if (threadIdx.x < 3) {
+      efield[threadIdx.x] = vel ? 0.0 : -(A1[threadIdx.x] - A0[threadIdx.x]) / (kC * dt);
+      Alast[threadIdx.x] = a1[threadIdx.x];
+    }
+  }
+  if (t < S) {
+    const double* x = ent_x + 3 * (size_t)t;
+    if (vel) {
+      double s, c;
+      sincos((ab[0] * x[0] + ab[1] * x[1] + ab[2] * x[2]) / kC, &s, &c);
+      phA[t] = make_double2(c, s);
+      sincos((a1[0] * x[0] + a1[1] * x[1] + a1[2] * x[2]) / kC, &s, &c);
+      phAJ[t] = make_double2(c, s);
+    } else {
+      phA[t] = make_double2(1.0, 0.0);
+      phAJ[t] = make_double2(1.0, 0.0);
+    }
+  }
+}
+
+hipError_t launch_step_params(const double* A, const int* counter, int use_counter,
+                              const double* kpt, int n_k, const double* ent_x, int S, int gauge,
+                              double dt, double* kappa, double* kappaJ, double* efield, double2* phA,
+                              double2* phAJ, double* Alast, hipStream_t s) {
+  const int blocks = S > 0 ? (S + 255) / 256 : 1;
+  hipLaunchKernelGGL(k_step_params, dim3(blocks), dim3(256), 0, s, A, counter, use_counter, kpt, n_k,
+                     ent_x, S, gauge, dt, kappa, kappaJ, efield, phA, phAJ, Alast);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- density
+// part[c][p] = sum over orbitals o in chunk c of 2 w_k |w_o(p)|^2, in order.
+template <typename T>
+__global__ void k_rho_partial(const typename Vec2<T>::type* w, const double* kw, int n_orb, int n_k,
+                              int N, int chunk, double* part) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (p >= N) return;
+  const int n_tot = n_orb * n_k;
+  const int o0 = c * chunk;
+  const int o1 = min(n_tot, o0 + chunk);
+  double acc = 0.0;
+  for (int o = o0; o < o1; ++o) {
+    const auto v = w[(size_t)o * N + p];
+    const double re = (double)v.x, im = (double)v.y;
+    acc += 2.0 * kw[o / n_orb] * (re * re + im * im);
+  }
+  part[(size_t)c * N + p] = acc;
+}
+
+template <typename T>
+hipError_t launch_rho_partial(const typename Vec2<T>::type* w, const double* kw, int n_orb, int n_k,
+                              int N, int chunk, double* part, hipStream_t s) {
+  const int nchunks = (n_orb * n_k + chunk - 1) / chunk;
+  hipLaunchKernelGGL((k_rho_partial<T>), dim3((N + 255) / 256, nchunks), dim3(256), 0, s, w, kw,
+                     n_orb, n_k, N, chunk, part);
+  return hipGetLastError();
+}
+template hipError_t launch_rho_partial<double>(const double2*, const double*, int, int, int, int,
+                                               double*, hipStream_t);
+template hipError_t launch_rho_partial<float>(const float2*, const double*, int, int, int, int,
+                                              double*, hipStream_t);
+
+__global__ void k_rho_reduce(const double* part, int nchunks, int N, double* rho) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= N) return;
+  double acc = 0.0;
+  for (int c = 0; c < nchunks; ++c) acc += part[(size_t)c * N + p];
+  rho[p] = acc;
+}
+
+hipError_t launch_rho_reduce(const double* part, int nchunks, int N, double* rho, hipStream_t s) {
+  hipLaunchKernelGGL(k_rho_reduce, dim3((N + 255) / 256), dim3(256), 0, s, part, nchunks, N, rho);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- FFT
+// In-place FP64 complex FFT of every line along one axis of an M1 x M2 x M3
+// array (M1 fastest), unnormalised, sign -1 forward / +1 inverse. A workgroup
+// stages B lines in LDS and runs a Stockham mixed-radix (4, 2, 3, 5)
+// transform: for radix R and Ns = product of the radices already applied,
+// butterfly j reads in[j + r M/R], multiplies by exp(sign 2 pi i r (j mod Ns) / (Ns R)),
+// does a length-R DFT and writes out[(j / Ns) Ns R + (j mod Ns) + r Ns].
+struct FFTPlan {
+  int M, nf;
+  int f[12];
+};
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// o_s = sum_q v_q exp(sign 2 pi i q s / R) for R = 2, 3, 4, 5
+template <int R>
+__device__ __forceinline__ void dft_small(double2* v, int sign);
+
+template <>
+__device__ __forceinline__ void dft_small<2>(double2* v, int) {
+  const double2 a = v[0], b = v[1];
+  v[0] = make_double2(a.x + b.x, a.y + b.y);
+  v[1] = make_double2(a.x - b.x, a.y - b.y);
+}
+
+template <>
+__device__ __forceinline__ void dft_small<4>(double2* v, int sign) {
+  // omega = exp(sign i pi / 2) = sign * i
+  const double2 a = v[0], b = v[1], c = v[2], d = v[3];
+  const double2 s02 = make_double2(a.x + c.x, a.y + c.y), d02 = make_double2(a.x - c.x, a.y - c.y);
+  const double2 s13 = make_double2(b.x + d.x, b.y + d.y), d13 = make_double2(b.x - d.x, b.y - d.y);
+  // i * sign * d13
+  const double2 r13 = make_double2(-sign * d13.y, sign * d13.x);
+  v[0] = make_double2(s02.x + s13.x, s02.y + s13.y);
+  v[1] = make_double2(d02.x + r13.x, d02.y + r13.y);
+  v[2] = make_double2(s02.x - s13.x, s02.y - s13.y);
+  v[3] = make_double2(d02.x - r13.x, d02.y - r13.y);
+}
+
+template <>
+__device__ __forceinline__ void dft_small<3>(double2* v, int sign) {
+  const double c1 = -0.5, s1 = sign * 0.86602540378443864676;  // exp(sign 2 pi i / 3)
+  const double2 a = v[0], b = v[1], c = v[2];
+  const double2 sbc = make_double2(b.x + c.x, b.y + c.y), dbc = make_double2(b.x - c.x, b.y - c.y);
+  v[0] = make_double2(a.x + sbc.x, a.y + sbc.y);
+  const double2 m = make_double2(a.x + c1 * sbc.x, a.y + c1 * sbc.y);
+  // omega b + conj(omega) c = c1 (b + c) + i s1 (b - c)
+  v[1] = make_double2(m.x - s1 * dbc.y, m.y + s1 * dbc.x);
+  v[2] = make_double2(m.x + s1 * dbc.y, m.y - s1 * dbc.x);
+}
+
+template <>
+__device__ __forceinline__ void dft_small<5>(double2* v, int sign) {
+  const double cs[5] = {1.0, 0.30901699437494742410, -0.80901699437494742410, -0.80901699437494742410,
+                        0.30901699437494742410};
+  const double sn[5] = {0.0, 0.95105651629515357212, 0.58778525229247312917, -0.58778525229247312917,
+                        -0.95105651629515357212};
+  double2 o[5];
+#pragma unroll
+  for (int s = 0; s < 5; ++s) {
+    double re = 0.0, im = 0.0;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      const int e = (q * s) % 5;
+      const double c = cs[e], sv = sign * sn[e];
+      re += v[q].x * c - v[q].y * sv;
+      im += v[q].x * sv + v[q].y * c;
+    }
+    o[s] = make_double2(re, im);
+  }
+#pragma unroll
+  for (int s = 0; s < 5; ++s) v[s] = o[s];
+}
+
+template <int R>
+__device__ void stockham_stage(const double2* in, double2* out, int B, int M, int Ns, int sign) {
+  const int nb = M / R;
+  for (int t = threadIdx.x; t < B * nb; t += blockDim.x) {
+    const int line = t / nb;
+    const int jj = t - line * nb;
+    const double2* li = in + (size_t)line * M;
+    double2* lo = out + (size_t)line * M;
+    double2 v[R];
+    const int jm = jj % Ns;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      v[r] = li[jj + r * nb];
+      if (r > 0 && jm != 0) {
+        double sn, cs;
+        sincospi(2.0 * sign * (double)(r * jm) / (double)(Ns * R), &sn, &cs);
+        v[r] = cmul(v[r], make_double2(cs, sn));
+      }
+    }
+    dft_small<R>(v, sign);
+    const int d = (jj / Ns) * Ns * R + jm;
+#pragma unroll
+    for (int r = 0; r < R; ++r) lo[d + r * Ns] = v[r];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_fft_axis(double2* data, int M1, int M2, int M3, int axis,
+                                                  int sign, int B, FFTPlan plan) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double2* buf0 = reinterpret_cast<double2*>(smem_raw);
+  const int M = plan.M;
+  double2* buf1 = buf0 + (size_t)B * M;
+  const long total = (long)M1 * M2 * M3;
+  const long nlines = total / M;
+  const long L0 = (long)blockIdx.x * B;
+  const int nl = (int)min((long)B, nlines - L0);
+  const long stride = (axis == 0) ? 1 : (axis == 1 ? M1 : (long)M1 * M2);
+  auto line_base = [&](long L) -> long {
+    if (axis == 0) return L * M1;
+    if (axis == 1) {
+      const long z = L / M1, x = L - z * M1;
+      return z * (long)M1 * M2 + x;
+    }
+    return L;  // axis 2: L = y * M1 + x
+  };
+  // load
+  for (int i = threadIdx.x; i < nl * M; i += blockDim.x) {
+    int line, e;
+    if (axis == 0) {
+      line = i / M;
+      e = i - line * M;
+    } else {
+      e = i / nl;
+      line = i - e * nl;
+    }
+    buf0[line * M + e] = data[line_base(L0 + line) + (long)e * stride];
+  }
+  __syncthreads();
+  double2* in = buf0;
+  double2* out = buf1;
+  int Ns = 1;
+  for (int f = 0; f < plan.nf; ++f) {
+    const int R = plan.f[f];
+    if (R == 4) stockham_stage<4>(in, out, nl, M, Ns, sign);
+    else if (R == 2) stockham_stage<2>(in, out, nl, M, Ns, sign);
+    else if (R == 3) stockham_stage<3>(in, out, nl, M, Ns, sign);
+    else stockham_stage<5>(in, out, nl, M, Ns, sign);
+    __syncthreads();
+    Ns *= R;
+    double2* t = in;
+    in = out;
+    out = t;
+  }
+  for (int i = threadIdx.x; i < nl * M; i += blockDim.x) {
+    int line, e;
+    if (axis == 0) {
+      line = i / M;
+      e = i - line * M;
+    } else {
+      e = i / nl;
+      line = i - e * nl;
+    }
+    data[line_base(L0 + line) + (long)e * stride] = in[line * M + e];
+  }
+}
+
+hipError_t launch_fft_axis(double2* data, int M1, int M2, int M3, int axis, int sign, hipStream_t s) {
+  FFTPlan plan;
+  plan.M = axis == 0 ? M1 : (axis == 1 ? M2 : M3);
+  plan.nf = 0;
+  int rem = plan.M;
+  const int radices[4] = {4, 2, 3, 5};
+  for (int r : radices) {
+    while (rem % r == 0 && plan.nf < 12) {
+      plan.f[plan.nf++] = r;
+      rem /= r;
+    }
+  }
+  if (rem != 1) return hipErrorInvalidValue;
+  const int B = max(1, min(256, 2048 / plan.M));
+  const long nlines = (long)M1 * M2 * M3 / plan.M;
+  const size_t lds = (size_t)2 * B * plan.M * sizeof(double2);
+  hipLaunchKernelGGL(k_fft_axis, dim3((unsigned)((nlines + B - 1) / B)), dim3(256), lds, s, data, M1,
+                     M2, M3, axis, sign, B, plan);
+  return hipGetLastError();
+}
+
+// rho (n1 x n2 x n3) into the corner of the M-box, zero elsewhere
+__global__ void k_pack_rho(const double* rho, int n1, int n2, int n3, int M1, int M2, int M3,
+                           double2* data) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long total = (long)M1 * M2 * M3;
+  if (i >= total) return;
+  const int x = (int)(i % M1);
+  const int y = (int)((i / M1) % M2);
+  const int z = (int)(i / ((long)M1 * M2));
+  double v = 0.0;
+  if (x < n1 && y < n2 && z < n3) v = rho[((size_t)z * n2 + y) * n1 + x];
+  data[i] = make_double2(v, 0.0);
+}
+
+hipError_t launch_pack_rho(const double* rho, int n1, int n2, int n3, int M1, int M2, int M3,
+                           double2* data, hipStream_t s) {
+  const long total = (long)M1 * M2 * M3;
+  hipLaunchKernelGGL(k_pack_rho, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, rho, n1, n2,
+                     n3, M1, M2, M3, data);
+  return hipGetLastError();
+}
+
+__global__ void k_scale_real(double2* data, const double* K, size_t total) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const double k = K[i];
+  data[i] = make_double2(data[i].x * k, data[i].y * k);
+}
+
+hipError_t launch_scale_real(double2* data, const double* K, size_t total, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_real, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, data, K,
+                     total);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- LDA + V
+// Perdew-Zunger 1981, spin-unpolarised; r_s >= 1 uses the Pade form in
+// sqrt(r_s), r_s < 1 the high-density logarithmic form; rho < 1e-30 -> 0.
+__device__ void pz81(double rho, double* v, double* e) {
+  if (!(rho >= 1e-30)) {
+    *v = 0.0;
+    *e = 0.0;
+    return;
+  }
+  const double third = 1.0 / 3.0;
+  const double pi = 3.14159265358979323846;
+  const double rs = cbrt(3.0 / (4.0 * pi * rho));
+  const double vx = -cbrt(3.0 * rho / pi);
+  const double ex = 0.75 * vx;
+  double ec, vc;
+  if (rs >= 1.0) {
+    const double g = -0.1423, b1 = 1.0529, b2 = 0.3334;
+    const double sq = sqrt(rs);
+    const double den = 1.0 + b1 * sq + b2 * rs;
+    ec = g / den;
+    vc = ec * (1.0 + 7.0 / 6.0 * b1 * sq + 4.0 / 3.0 * b2 * rs) / den;
+  } else {
+    const double A = 0.0311, B = -0.048, C = 0.0020, D = -0.0116;
+    const double l = log(rs);
+    ec = A * l + B + C * rs * l + D * rs;
+    vc = A * l + (B - A * third) + 2.0 * third * C * rs * l + (2.0 * D - C) * third * rs;
+  }
+  *v = vx + vc;
+  *e = ex + ec;
+}
+
+__global__ void k_xc_assemble(const double2* data, int n1, int n2, int n3, int M1, int M2,
+                              double vh_scale, const double* rho, const double* Vloc, int hartree,
+                              int xc, double* Vd, float* Vf, double* vh_out, double* exc) {
+  const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t N = (size_t)n1 * n2 * n3;
+  if (p >= N) return;
+  const int x = (int)(p % n1);
+  const int y = (int)((p / n1) % n2);
+  const int z = (int)(p / ((size_t)n1 * n2));
+  double vh = 0.0;
+  if (hartree) vh = data[((size_t)z * M2 + y) * M1 + x].x * vh_scale;
+  double vxc = 0.0, e = 0.0;
+  if (xc) pz81(rho[p], &vxc, &e);
+  const double v = Vloc[p] + vh + vxc;
+  Vd[p] = v;
+  Vf[p] = (float)v;
+  vh_out[p] = vh;
+  exc[p] = e;
+}
+
+hipError_t launch_xc_assemble(const double2* data, int n1, int n2, int n3, int M1, int M2, int M3,
+                              double vh_scale, const double* rho, const double* Vloc, int hartree,
+                              int xc, double* Vd, float* Vf, double* vh, double* exc,
+                              hipStream_t s) {
+  (void)M3;
+  const size_t N = (size_t)n1 * n2 * n3;
+  hipLaunchKernelGGL(k_xc_assemble, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, data, n1, n2,
+                     n3, M1, M2, vh_scale, rho, Vloc, hartree, xc, Vd, Vf, vh, exc);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- finish
+// One workgroup: I = -(1/Omega) sum_o f_o [p_o + kappaJ_k norm_o + jNL_o],
+// the orbital energy sum_o f_o [kin + kappaJ.p + 1/2 |kappaJ|^2 norm + vloc + E_NL],
+// and the occupied norm; f_o = 2 w_k. Thread t sums orbitals t, t+1024, ...
+// in order, then a fixed pairwise tree combines the threads.
+__global__ __launch_bounds__(1024) void k_finish(const double* obs, int tiles, const double* jnl,
+                                                 int use_nl, const double* kw, const double* kappaJ,
+                                                 int n_orb, int n_k, double dV, double volume,
+                                                 int* counter, int bump, double* Jtab,
+                                                 double* scalars, int* nanflag) {
+  __shared__ double red[1024][5];
+  const int t = threadIdx.x;
+  const int n_tot = n_orb * n_k;
+  double cx = 0, cy = 0, cz = 0, en = 0, nr = 0;
+  int bad = 0;
+  for (int o = t; o < n_tot; o += blockDim.x) {
+    const int k = o / n_orb;
+    double s[6] = {0, 0, 0, 0, 0, 0};
+    for (int tl = 0; tl < tiles; ++tl)
+      for (int i = 0; i < 6; ++i) s[i] += obs[((size_t)o * tiles + tl) * 8 + i];
+    for (int i = 0; i < 6; ++i) s[i] *= dV;
+    const double f = 2.0 * kw[k];
+    const double kx = kappaJ[3 * k], ky = kappaJ[3 * k + 1], kz = kappaJ[3 * k + 2];
+    double jx = 0, jy = 0, jz = 0, enl = 0;
+    if (use_nl) {
+      jx = jnl[4 * (size_t)o];
+      jy = jnl[4 * (size_t)o + 1];
+      jz = jnl[4 * (size_t)o + 2];
+      enl = jnl[4 * (size_t)o + 3];
+    }
+    cx += f * (s[1] + kx * s[0] + jx);
+    cy += f * (s[2] + ky * s[0] + jy);
+    cz += f * (s[3] + kz * s[0] + jz);
+    en += f * (s[4] + kx * s[1] + ky * s[2] + kz * s[3] + 0.5 * (kx * kx + ky * ky + kz * kz) * s[0] +
+               s[5] + enl);
+    nr += f * s[0];
+    if (!isfinite(s[0]) || !isfinite(s[1]) || !isfinite(s[2]) || !isfinite(s[3])) bad = 1;
+  }
+  red[t][0] = cx;
+  red[t][1] = cy;
+  red[t][2] = cz;
+  red[t][3] = en;
+  red[t][4] = nr;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if (t < w)
+      for (int i = 0; i < 5; ++i) red[t][i] += red[t + w][i];
+    __syncthreads();
+  }
+  if (bad) atomicOr(nanflag, 1);
+  if (t == 0) {
+    const double J[3] = {-red[0][0] / volume, -red[0][1] / volume, -red[0][2] / volume};
+    for (int i = 0; i < 3; ++i) scalars[i] = J[i];
+    scalars[3] = red[0][3];
+    scalars[4] = red[0][4];
+    if (bump) {
+      const int n = *counter;
+      for (int i = 0; i < 3; ++i) Jtab[3 * (size_t)n + i] = J[i];
+      *counter = n + 1;
+    }
+  }
+}
+
+hipError_t launch_finish(const double* obs, int tiles, const double* jnl, int use_nl,
+                         const double* kw, const double* kappaJ, int n_orb, int n_k, double dV,
+                         double volume, int* counter, int bump, double* Jtab, double* scalars,
+                         int* nanflag, hipStream_t s) {
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, obs, tiles, jnl, use_nl, kw, kappaJ, n_orb,
+                     n_k, dV, volume, counter, bump, Jtab, scalars, nanflag);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- grid sums
+// out[0] = 1/2 h^3 sum rho V_H, out[1] = h^3 sum rho eps_xc,
+// out[2..4] = -h^3 sum (r - centre)(rho - rho0), out[5] = h^3 sum rho.
+__global__ __launch_bounds__(1024) void k_grid_sums(const double* rho, const double* rho0,
+                                                    const double* vh, const double* exc, Geometry g,
+                                                    double* out) {
+  __shared__ double red[1024][6];
+  const int t = threadIdx.x;
+  const size_t N = (size_t)g.n1 * g.n2 * g.n3;
+  double s[6] = {0, 0, 0, 0, 0, 0};
+  for (size_t p = t; p < N; p += blockDim.x) {
+    const int x = (int)(p % g.n1);
+    const int y = (int)((p / g.n1) % g.n2);
+    const int z = (int)(p / ((size_t)g.n1 * g.n2));
+    const double r = rho[p];
+    const double dr = r - rho0[p];
+    s[0] += r * vh[p];
+    s[1] += r * exc[p];
+    s[2] += (x - 0.5 * (g.n1 - 1)) * g.h1 * dr;
+    s[3] += (y - 0.5 * (g.n2 - 1)) * g.h2 * dr;
+    s[4] += (z - 0.5 * (g.n3 - 1)) * g.h3 * dr;
+    s[5] += r;
+  }
+  for (int i = 0; i < 6; ++i) red[t][i] = s[i];
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if (t < w)
+      for (int i = 0; i < 6; ++i) red[t][i] += red[t + w][i];
+    __syncthreads();
+  }
+  if (t == 0) {
+    const double dV = g.h1 * g.h2 * g.h3;
+    out[0] = 0.5 * dV * red[0][0];
+    out[1] = dV * red[0][1];
+    out[2] = -dV * red[0][2];
+    out[3] = -dV * red[0][3];
+    out[4] = -dV * red[0][4];
+    out[5] = dV * red[0][5];
+  }
+}
+
+hipError_t launch_grid_sums(const double* rho, const double* rho0, const double* vh,
+                            const double* exc, Geometry g, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_grid_sums, dim3(1), dim3(1024), 0, s, rho, rho0, vh, exc, g, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- conversions
+template <typename T>
+__global__ void k_convert_in(const double2* src, typename Vec2<T>::type* dst, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double2 v = src[i];
+  typename Vec2<T>::type o;
+  o.x = (T)v.x;
+  o.y = (T)v.y;
+  dst[i] = o;
+}
+template <typename T>
+__global__ void k_convert_out(const typename Vec2<T>::type* src, double2* dst, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const auto v = src[i];
+  dst[i] = make_double2((double)v.x, (double)v.y);
+}
+template <typename T>
+hipError_t launch_convert_in(const double2* src, typename Vec2<T>::type* dst, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL((k_convert_in<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_convert_out(const typename Vec2<T>::type* src, double2* dst, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL((k_convert_out<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+template hipError_t launch_convert_in<double>(const double2*, double2*, size_t, hipStream_t);
+template hipError_t launch_convert_in<float>(const double2*, float2*, size_t, hipStream_t);
+template hipError_t launch_convert_out<double>(const double2*, double2*, size_t, hipStream_t);
+template hipError_t launch_convert_out<float>(const float2*, double2*, size_t, hipStream_t);
+
+// w <- exp(-i F0 r_axis) w with r from the box centre (isolated kick, Sec. 3.1)
+template <typename T>
+__global__ void k_kick(typename Vec2<T>::type* w, Geometry g, double F0, int axis, size_t total) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const size_t N = (size_t)g.n1 * g.n2 * g.n3;
+  const size_t p = i % N;
+  int c;
+  double h;
+  int n;
+  if (axis == 0) {
+    c = (int)(p % g.n1);
+    h = g.h1;
+    n = g.n1;
+  } else if (axis == 1) {
+    c = (int)((p / g.n1) % g.n2);
+    h = g.h2;
+    n = g.n2;
+  } else {
+    c = (int)(p / ((size_t)g.n1 * g.n2));
+    h = g.h3;
+    n = g.n3;
+  }
+  const double r = (c - 0.5 * (n - 1)) * h;
+  double sn, cs;
+  sincos(-F0 * r, &sn, &cs);
+  auto v = w[i];
+  const double re = (double)v.x, im = (double)v.y;
+  v.x = (T)(re * cs - im * sn);
+  v.y = (T)(re * sn + im * cs);
+  w[i] = v;
+}
+template <typename T>
+hipError_t launch_kick(typename Vec2<T>::type* w, Geometry g, double F0, int axis, size_t n_orb_tot,
+                       hipStream_t s) {
+  const size_t total = n_orb_tot * (size_t)g.n1 * g.n2 * g.n3;
+  hipLaunchKernelGGL((k_kick<T>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, w, g, F0,
+                     axis, total);
+  return hipGetLastError();
+}
+template hipError_t launch_kick<double>(double2*, Geometry, double, int, size_t, hipStream_t);
+template hipError_t launch_kick<float>(float2*, Geometry, double, int, size_t, hipStream_t);
+
+__global__ void k_real_part(const double2* src, double* dst, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i].x;
+}
+hipError_t launch_real_part(const double2* src, double* dst, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_real_part, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+
+__global__ void k_fill(double* p, double v, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+hipError_t launch_fill(double* p, double v, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+__global__ void k_set_int(int* p, int v) { *p = v; }
+hipError_t launch_set_int(int* p, int v, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, p, v);
+  return hipGetLastError();
+}
+
+}  // namespace td

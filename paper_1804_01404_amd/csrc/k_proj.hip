@@ -1,0 +1,165 @@
+// Kleinman-Bylander projections on the matrix cores (Sec. 3.1, separable
+// nonlocal pseudopotential; Sec. 4.1, phase exp(-i kappa.x) for gauge
+// invariance):
+//
+//   u_{o,a,p}^{(m)} = h^3 sum_{e in sphere(a)} B[e][4p+m] exp(i kappa_k . x_e) t_o(idx_e)
+//
+// with B[e][4p+m] = beta_p(x_e) * (1, x, y, z)[m]. For one atom and a group of
+// eight orbitals this is a real product D[16 x 16] = A[16 x K] B[K x 16]
+// where row 2j/2j+1 of A holds the real/imaginary part of the phase-shifted
+// gathered value of orbital j, K runs over the sphere entries in steps of 4,
+// and column 4p+m of B is the moment m of projector p. One wavefront
+// accumulates D with v_mfma_f64_16x16x4f64 (FP64 inputs: FP32 orbitals are
+// upcast, so the inner products stay FP64 in the mixed-precision path).
+//
+// Lane layout of v_mfma_f64_16x16x4f64 (checked by a GPU unit test):
+//   A: lane l holds A[l % 16][l / 16];  B: lane l holds B[l / 16][l % 16];
+//   D: register r of lane l holds D[l / 16 + 4 r][l % 16], r = 0..3.
+//
+// Stage mode writes E_p u_p (m = 0) for the add-back of the next stage.
+// Moment mode loops over all atoms of an orbital group and reduces the
+// nonlocal current sum_p 2 E_p Im(conj(v_p) u_p) (v = moments 1..3) and the
+// nonlocal energy sum_p E_p |u_p|^2 per orbital.
+#include "internal.h"
+
+namespace td {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_project(ProjArgs<T> a) {
+  using T2 = typename Vec2<T>::type;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int n_groups = (a.n_orb_tot + 7) / 8;
+  const int n_atoms = a.nl.n_atoms;
+  const int item = blockIdx.x * 4 + wave;
+  const int total = a.moments ? n_groups : n_groups * n_atoms;
+  if (item >= total) return;  // wave-uniform
+  int grp, at0, at1;
+  if (a.moments) {
+    grp = item;
+    at0 = 0;
+    at1 = n_atoms;
+  } else {
+    grp = item / n_atoms;
+    at0 = item - grp * n_atoms;
+    at1 = at0 + 1;
+  }
+  const int row = lane & 15;   // A row / B and D column
+  const int kk = lane >> 4;    // A column / B row / D row block
+  const int o_row = grp * 8 + (row >> 1);
+  const int part = row & 1;
+  const bool row_ok = o_row < a.n_orb_tot;
+  const int k_row = row_ok ? o_row / a.n_orb : 0;
+  const T2* __restrict__ urow = a.u + (size_t)(row_ok ? o_row : 0) * a.N;
+  const double2* __restrict__ phk = a.nl.phk + (size_t)k_row * a.nl.n_ent;
+
+  const int j = row;
+  const int p = j >> 2, m = j & 3;
+  double acc_moment[4] = {0.0, 0.0, 0.0, 0.0};  // moment mode: per owned orbital
+
+  for (int at = at0; at < at1; ++at) {
+    const int e0 = a.nl.atom_start[at], e1 = a.nl.atom_start[at + 1];
+    d4_t acc = {0.0, 0.0, 0.0, 0.0};
+    for (int eb = e0; eb < e1; eb += 4) {
+      const int e = eb + kk;
+      double av = 0.0, bv = 0.0;
+      if (e < e1) {
+        bv = a.nl.ent_B[(size_t)e * kCols + j];
+        if (row_ok) {
+          const int idx = a.nl.ent_idx[e];
+          const T2 uv = urow[idx];
+          const double2 p1 = phk[e];
+          const double2 p2 = a.phA[e];
+          const double pr = p1.x * p2.x - p1.y * p2.y;
+          const double pim = p1.x * p2.y + p1.y * p2.x;
+          const double ur = (double)uv.x, ui = (double)uv.y;
+          av = part ? (pr * ui + pim * ur) : (pr * ur - pim * ui);
+        }
+      }
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+    }
+    // acc[r] = D[kk + 4r][j]: orbital (kk >> 1) + 2r of the group, real part
+    // for even kk, imaginary part for odd kk; the partner lane l ^ 16 holds
+    // the other part of the same orbital.
+    const double E = a.nl.atom_E[at * kMaxProj + p];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const double mine = a.dV * acc[r];
+      const double other = __shfl_xor(mine, 16, 64);
+      const double ure = (kk & 1) ? other : mine;
+      const double uim = (kk & 1) ? mine : other;
+      const int o = grp * 8 + (kk >> 1) + 2 * r;
+      if (!a.moments) {
+        if (m == 0 && (kk & 1) == 0 && o < a.n_orb_tot)
+          a.Eu[((size_t)o * n_atoms + at) * kMaxProj + p] = make_double2(E * ure, E * uim);
+      } else {
+        // u_p lives in the lane of column 4p (same row block): fetch it
+        const int src = kk * 16 + 4 * p;
+        const double u0r = __shfl(ure, src, 64);
+        const double u0i = __shfl(uim, src, 64);
+        if (m == 0)
+          acc_moment[r] += E * (u0r * u0r + u0i * u0i);           // E_p |u_p|^2
+        else
+          acc_moment[r] += 2.0 * E * (ure * u0i - uim * u0r);     // 2 E_p Im(conj(v) u)
+      }
+    }
+  }
+  if (a.moments) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      // sum over p: lanes 4p+m of the same row block (xor over bits 2 and 3)
+      double v = acc_moment[r];
+      v += __shfl_xor(v, 4, 64);
+      v += __shfl_xor(v, 8, 64);
+      const int o = grp * 8 + (kk >> 1) + 2 * r;
+      if (p == 0 && (kk & 1) == 0 && o < a.n_orb_tot) {
+        const int slot = (m == 0) ? 3 : m - 1;
+        a.jnl[(size_t)o * 4 + slot] = v;
+      }
+    }
+  }
+}
+
+template <typename T>
+hipError_t launch_project(const ProjArgs<T>& a, hipStream_t s) {
+  const int n_groups = (a.n_orb_tot + 7) / 8;
+  const long total = a.moments ? n_groups : (long)n_groups * a.nl.n_atoms;
+  if (total == 0) return hipSuccess;
+  const dim3 grid((unsigned)((total + 3) / 4));
+  hipLaunchKernelGGL((k_project<T>), grid, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template hipError_t launch_project<double>(const ProjArgs<double>&, hipStream_t);
+template hipError_t launch_project<float>(const ProjArgs<float>&, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Unit check of the MFMA lane layout: D = A B for A [16 x 4], B [4 x 16]
+// given row-major on the device; used only by a test entry point.
+__global__ void k_mfma_layout(const double* A, const double* B, double* D) {
+  const int l = threadIdx.x;
+  const double av = A[(l % 16) * 4 + l / 16];
+  const double bv = B[(l / 16) * 16 + l % 16];
+  d4_t acc = {0.0, 0.0, 0.0, 0.0};
+  acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+  for (int r = 0; r < 4; ++r) D[(l / 16 + 4 * r) * 16 + l % 16] = acc[r];
+}
+
+}  // namespace td
+
+extern "C" int tddft_test_mfma_layout(const double* A, const double* B, double* D) {
+  double *dA, *dB, *dD;
+  if (hipMalloc(&dA, 64 * sizeof(double)) != hipSuccess) return 1;
+  if (hipMalloc(&dB, 64 * sizeof(double)) != hipSuccess) return 1;
+  if (hipMalloc(&dD, 256 * sizeof(double)) != hipSuccess) return 1;
+  hipMemcpy(dA, A, 64 * sizeof(double), hipMemcpyHostToDevice);
+  hipMemcpy(dB, B, 64 * sizeof(double), hipMemcpyHostToDevice);
+  hipLaunchKernelGGL(td::k_mfma_layout, dim3(1), dim3(64), 0, 0, dA, dB, dD);
+  hipError_t e = hipMemcpy(D, dD, 256 * sizeof(double), hipMemcpyDeviceToHost);
+  hipFree(dA);
+  hipFree(dB);
+  hipFree(dD);
+  return e == hipSuccess ? 0 : 2;
+}

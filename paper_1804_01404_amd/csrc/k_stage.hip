@@ -1,0 +1,402 @@
+// Horner stage of the fourth-order Taylor step and the orbital observables.
+//
+// One stage computes u_{s-1} = w + (-i dt / s) h u_s for one orbital
+// (Program Summary: truncated Taylor expansion of exp(-i dt h); Sec. 4.1,
+// Eq. TDKS_solid for h). h is applied in the expanded form
+//   h u = -1/2 Lap_h u - i kappa . grad_h u + (1/2 |kappa|^2 + V) u + V_NL u,
+// with 9-point central differences along each axis.
+//
+// Work decomposition: one workgroup owns one orbital and one xy-tile and
+// marches along z. Each thread owns one (x, y) column: the nine z-neighbours
+// of the current plane live in a register queue, the x/y neighbours come
+// from the current plane staged in LDS (double-buffered, one barrier per
+// plane). Periodic cells whose plane fits one workgroup (n1 n2 <= 1024) use
+// the whole plane as the tile and wrap x/y inside LDS; other grids use tiles
+// with a 4-point halo loaded from HBM (wrap or zero).
+//
+// HBM traffic per orbital point and stage: read u_s once, read w once (not in
+// the first stage, where u_4 = w), write u_{s-1} once.
+#include "internal.h"
+
+namespace td {
+
+template <typename T2>
+__device__ __forceinline__ T2 zero2() {
+  T2 z;
+  z.x = 0;
+  z.y = 0;
+  return z;
+}
+
+template <typename T, int MODE, int BC>
+__global__ __launch_bounds__(1024) void k_stage(StageArgs<T> a) {
+  using T2 = typename Vec2<T>::type;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T2* lds = reinterpret_cast<T2*>(smem_raw);
+
+  const Geometry& g = a.g;
+  const int n1 = g.n1, n2 = g.n2, n3 = g.n3;
+  const int plane = n1 * n2;
+  const size_t N = (size_t)plane * n3;
+  const int ntiles = g.tiles_x * g.tiles_y;
+  const int o = blockIdx.x / ntiles;
+  const int tile = blockIdx.x - o * ntiles;
+  const int k = o / g.n_orb;
+  const int TX = g.TX, TY = g.TY;
+  const int tid = threadIdx.x;
+  const int tx = tid % TX, ty = tid / TX;
+  const bool active = ty < TY;
+  const int gx = (tile % g.tiles_x) * TX + tx;
+  const int gy = (tile / g.tiles_x) * TY + ty;
+
+  const int LW = (BC == kPeriodicPlane) ? n1 : TX + 8;
+  const int LH = (BC == kPeriodicPlane) ? n2 : TY + 8;
+  const int lsz = LW * LH;
+  const int lx = (BC == kPeriodicPlane) ? tx : tx + 4;
+  const int ly = (BC == kPeriodicPlane) ? ty : ty + 4;
+  const int lc = ly * LW + lx;
+
+  int oxp[4], oxm[4], oyp[4], oym[4];
+#pragma unroll
+  for (int m = 1; m <= 4; ++m) {
+    if (BC == kPeriodicPlane) {
+      oxp[m - 1] = ly * LW + (tx + m) % n1;
+      oxm[m - 1] = ly * LW + (tx - m + n1) % n1;
+      oyp[m - 1] = ((ty + m) % n2) * LW + lx;
+      oym[m - 1] = ((ty - m + n2) % n2) * LW + lx;
+    } else {
+      oxp[m - 1] = lc + m;
+      oxm[m - 1] = lc - m;
+      oyp[m - 1] = lc + m * LW;
+      oym[m - 1] = lc - m * LW;
+    }
+  }
+
+  const size_t base = (size_t)o * N;
+  const int col = gy * n1 + gx;
+  const T2* __restrict__ src = a.in + base;
+  const T2 z2 = zero2<T2>();
+  const bool periodic = (BC != kIsolatedTile);
+
+  auto load_col = [&](int z) -> T2 {
+    if (!active) return z2;
+    if (!periodic && (z < 0 || z >= n3)) return z2;
+    int zz = z;
+    if (periodic) {
+      zz = z % n3;
+      if (zz < 0) zz += n3;
+    }
+    return src[(size_t)zz * plane + col];
+  };
+  auto load_xy = [&](int x, int y, int z) -> T2 {
+    if (periodic) {
+      x = (x % n1 + n1) % n1;
+      y = (y % n2 + n2) % n2;
+    } else if (x < 0 || x >= n1 || y < 0 || y >= n2) {
+      return z2;
+    }
+    return src[(size_t)z * plane + y * n1 + x];
+  };
+
+  // per-step, per-k coefficients (uniform across the workgroup)
+  const double kx = a.kappa[3 * k + 0], ky = a.kappa[3 * k + 1], kz = a.kappa[3 * k + 2];
+  T cx[4], cy[4], cz[4], bx[4], by[4], bz[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    cx[m] = (T)a.lap[0][m + 1];
+    cy[m] = (T)a.lap[1][m + 1];
+    cz[m] = (T)a.lap[2][m + 1];
+    bx[m] = (T)(kx * a.dh[0][m]);
+    by[m] = (T)(ky * a.dh[1][m]);
+    bz[m] = (T)(kz * a.dh[2][m]);
+  }
+  const double diag_d = a.cdiag + 0.5 * (kx * kx + ky * ky + kz * kz);
+  const T tau = (T)a.tau;
+  T ext = 0, ez = 0;
+  if (a.efield) {
+    const double xr = (gx - 0.5 * (n1 - 1)) * g.h1;
+    const double yr = (gy - 0.5 * (n2 - 1)) * g.h2;
+    ext = (T)(a.efield[0] * xr + a.efield[1] * yr);
+    ez = (T)(a.efield[2] * g.h3);
+  }
+  const T zc = (T)(0.5 * (n3 - 1));
+  const bool has_nl = (a.Eu != nullptr);
+  const int S = a.nl.n_ent;
+  const int n_atoms = a.nl.n_atoms;
+
+  T2 q[9];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) q[i] = load_col(i - 4);
+  T2 nxt = load_col(4);
+
+  for (int z = 0; z < n3; ++z) {
+    q[8] = nxt;
+    if (z + 1 < n3) nxt = load_col(z + 5);
+    const size_t pz = (size_t)z * plane + col;
+    T2 wv = q[4];
+    if (MODE != kFirst && active) wv = a.w[base + pz];
+    T vv = 0;
+    if (active) vv = a.V[pz];
+
+    T2* buf = lds + (z & 1) * lsz;
+    if (active) {
+      buf[lc] = q[4];
+      if (BC != kPeriodicPlane) {
+        if (tx < 4) buf[lc - 4] = load_xy(gx - 4, gy, z);
+        if (tx >= TX - 4) buf[lc + 4] = load_xy(gx + 4, gy, z);
+        if (ty < 4) buf[lc - 4 * LW] = load_xy(gx, gy - 4, z);
+        if (ty >= TY - 4) buf[lc + 4 * LW] = load_xy(gx, gy + 4, z);
+      }
+    }
+    __syncthreads();
+
+    if (active) {
+      const T2 u = q[4];
+      T dg = (T)diag_d + vv;
+      if (a.efield) dg += ext + ez * ((T)z - zc);
+      T hr = dg * u.x;
+      T hi = dg * u.y;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        T2 p = buf[oxp[m]], n = buf[oxm[m]];
+        hr += cx[m] * (p.x + n.x) + bx[m] * (p.y - n.y);
+        hi += cx[m] * (p.y + n.y) - bx[m] * (p.x - n.x);
+        p = buf[oyp[m]];
+        n = buf[oym[m]];
+        hr += cy[m] * (p.x + n.x) + by[m] * (p.y - n.y);
+        hi += cy[m] * (p.y + n.y) - by[m] * (p.x - n.x);
+        p = q[5 + m];
+        n = q[3 - m];
+        hr += cz[m] * (p.x + n.x) + bz[m] * (p.y - n.y);
+        hi += cz[m] * (p.y + n.y) - bz[m] * (p.x - n.x);
+      }
+      if (has_nl) {
+        const int e0 = a.nl.pt_ptr[pz], e1 = a.nl.pt_ptr[pz + 1];
+        for (int t = e0; t < e1; ++t) {
+          const int e = a.nl.pt_ent[t];
+          const int at = a.nl.ent_atom[e];
+          const double2 p1 = a.nl.phk[(size_t)k * S + e];
+          const double2 p2 = a.phA[e];
+          const double pr = p1.x * p2.x - p1.y * p2.y;
+          const double pim = p1.x * p2.y + p1.y * p2.x;
+          const double2* eu = a.Eu + ((size_t)o * n_atoms + at) * kMaxProj;
+          const double* B = a.nl.ent_B + (size_t)e * kCols;
+          double sr = 0.0, si = 0.0;
+#pragma unroll
+          for (int pp = 0; pp < kMaxProj; ++pp) {
+            const double b = B[pp * kMoments];
+            sr += b * eu[pp].x;
+            si += b * eu[pp].y;
+          }
+          hr += (T)(pr * sr + pim * si);
+          hi += (T)(pr * si - pim * sr);
+        }
+      }
+      T2 res;
+      res.x = wv.x + tau * hi;
+      res.y = wv.y - tau * hr;
+      a.out[base + pz] = res;
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) q[i] = q[i + 1];
+  }
+}
+
+// Per-orbital sums used by the current and the energy, all in FP64:
+// norm = sum |w|^2, p_mu = sum Im(conj(w) d_mu w), kin = sum Re(conj(w)(-1/2 Lap w)),
+// vloc = sum V_loc |w|^2 (the caller multiplies by h1 h2 h3).
+template <typename T, int BC>
+__global__ __launch_bounds__(1024) void k_observe(ObserveArgs<T> a) {
+  using T2 = typename Vec2<T>::type;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double2* lds = reinterpret_cast<double2*>(smem_raw);
+  __shared__ double red[16][6];
+
+  const Geometry& g = a.g;
+  const int n1 = g.n1, n2 = g.n2, n3 = g.n3;
+  const int plane = n1 * n2;
+  const size_t N = (size_t)plane * n3;
+  const int ntiles = g.tiles_x * g.tiles_y;
+  const int o = blockIdx.x / ntiles;
+  const int tile = blockIdx.x - o * ntiles;
+  const int TX = g.TX, TY = g.TY;
+  const int tid = threadIdx.x;
+  const int tx = tid % TX, ty = tid / TX;
+  const bool active = ty < TY;
+  const int gx = (tile % g.tiles_x) * TX + tx;
+  const int gy = (tile / g.tiles_x) * TY + ty;
+  const int LW = (BC == kPeriodicPlane) ? n1 : TX + 8;
+  const int LH = (BC == kPeriodicPlane) ? n2 : TY + 8;
+  const int lsz = LW * LH;
+  const int lx = (BC == kPeriodicPlane) ? tx : tx + 4;
+  const int ly = (BC == kPeriodicPlane) ? ty : ty + 4;
+  const int lc = ly * LW + lx;
+  int oxp[4], oxm[4], oyp[4], oym[4];
+#pragma unroll
+  for (int m = 1; m <= 4; ++m) {
+    if (BC == kPeriodicPlane) {
+      oxp[m - 1] = ly * LW + (tx + m) % n1;
+      oxm[m - 1] = ly * LW + (tx - m + n1) % n1;
+      oyp[m - 1] = ((ty + m) % n2) * LW + lx;
+      oym[m - 1] = ((ty - m + n2) % n2) * LW + lx;
+    } else {
+      oxp[m - 1] = lc + m;
+      oxm[m - 1] = lc - m;
+      oyp[m - 1] = lc + m * LW;
+      oym[m - 1] = lc - m * LW;
+    }
+  }
+  const size_t base = (size_t)o * N;
+  const int col = gy * n1 + gx;
+  const T2* __restrict__ src = a.w + base;
+  const bool periodic = (BC != kIsolatedTile);
+  auto up = [](T2 v) { return make_double2((double)v.x, (double)v.y); };
+  auto load_col = [&](int z) -> double2 {
+    if (!active) return make_double2(0.0, 0.0);
+    if (!periodic && (z < 0 || z >= n3)) return make_double2(0.0, 0.0);
+    int zz = z;
+    if (periodic) {
+      zz = z % n3;
+      if (zz < 0) zz += n3;
+    }
+    return up(src[(size_t)zz * plane + col]);
+  };
+  auto load_xy = [&](int x, int y, int z) -> double2 {
+    if (periodic) {
+      x = (x % n1 + n1) % n1;
+      y = (y % n2 + n2) % n2;
+    } else if (x < 0 || x >= n1 || y < 0 || y >= n2) {
+      return make_double2(0.0, 0.0);
+    }
+    return up(src[(size_t)z * plane + y * n1 + x]);
+  };
+
+  double s_norm = 0, s_px = 0, s_py = 0, s_pz = 0, s_kin = 0, s_v = 0;
+  double2 q[9];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) q[i] = load_col(i - 4);
+  for (int z = 0; z < n3; ++z) {
+    q[8] = load_col(z + 4);
+    double2* buf = lds + (z & 1) * lsz;
+    if (active) {
+      buf[lc] = q[4];
+      if (BC != kPeriodicPlane) {
+        if (tx < 4) buf[lc - 4] = load_xy(gx - 4, gy, z);
+        if (tx >= TX - 4) buf[lc + 4] = load_xy(gx + 4, gy, z);
+        if (ty < 4) buf[lc - 4 * LW] = load_xy(gx, gy - 4, z);
+        if (ty >= TY - 4) buf[lc + 4 * LW] = load_xy(gx, gy + 4, z);
+      }
+    }
+    __syncthreads();
+    if (active) {
+      const double2 u = q[4];
+      double lr = a.cdiag * u.x, li = a.cdiag * u.y;
+      double dxr = 0, dxi = 0, dyr = 0, dyi = 0, dzr = 0, dzi = 0;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        double2 p = buf[oxp[m]], n = buf[oxm[m]];
+        lr += a.lap[0][m + 1] * (p.x + n.x);
+        li += a.lap[0][m + 1] * (p.y + n.y);
+        dxr += a.dh[0][m] * (p.x - n.x);
+        dxi += a.dh[0][m] * (p.y - n.y);
+        p = buf[oyp[m]];
+        n = buf[oym[m]];
+        lr += a.lap[1][m + 1] * (p.x + n.x);
+        li += a.lap[1][m + 1] * (p.y + n.y);
+        dyr += a.dh[1][m] * (p.x - n.x);
+        dyi += a.dh[1][m] * (p.y - n.y);
+        p = q[5 + m];
+        n = q[3 - m];
+        lr += a.lap[2][m + 1] * (p.x + n.x);
+        li += a.lap[2][m + 1] * (p.y + n.y);
+        dzr += a.dh[2][m] * (p.x - n.x);
+        dzi += a.dh[2][m] * (p.y - n.y);
+      }
+      const double nn = u.x * u.x + u.y * u.y;
+      s_norm += nn;
+      s_px += u.x * dxi - u.y * dxr;
+      s_py += u.x * dyi - u.y * dyr;
+      s_pz += u.x * dzi - u.y * dzr;
+      s_kin += u.x * lr + u.y * li;
+      s_v += a.Vloc[(size_t)z * plane + col] * nn;
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) q[i] = q[i + 1];
+  }
+  double v[6] = {s_norm, s_px, s_py, s_pz, s_kin, s_v};
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v[i] += __shfl_down(v[i], off, 64);
+  }
+  const int lane = tid & 63, wave = tid >> 6;
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < 6; ++i) red[wave][i] = v[i];
+  }
+  __syncthreads();
+  if (tid < 6) {
+    const int nw = (blockDim.x + 63) / 64;
+    double s = 0;
+    for (int w = 0; w < nw; ++w) s += red[w][tid];
+    a.out[((size_t)o * ntiles + tile) * 8 + tid] = s;
+  }
+}
+
+static int block_threads(const Geometry& g) { return ((g.TX * g.TY + 63) / 64) * 64; }
+static size_t lds_elems(int bc, const Geometry& g) {
+  return (bc == kPeriodicPlane) ? (size_t)2 * g.n1 * g.n2 : (size_t)2 * (g.TX + 8) * (g.TY + 8);
+}
+
+template <typename T, int MODE>
+static hipError_t stage_bc(int bc, const StageArgs<T>& a, hipStream_t s) {
+  using T2 = typename Vec2<T>::type;
+  const dim3 grid((unsigned)((size_t)a.g.n_orb * a.g.n_k * a.g.tiles_x * a.g.tiles_y));
+  const dim3 block(block_threads(a.g));
+  const size_t lds = lds_elems(bc, a.g) * sizeof(T2);
+  switch (bc) {
+    case kPeriodicPlane:
+      hipLaunchKernelGGL((k_stage<T, MODE, kPeriodicPlane>), grid, block, lds, s, a);
+      break;
+    case kPeriodicTile:
+      hipLaunchKernelGGL((k_stage<T, MODE, kPeriodicTile>), grid, block, lds, s, a);
+      break;
+    default:
+      hipLaunchKernelGGL((k_stage<T, MODE, kIsolatedTile>), grid, block, lds, s, a);
+      break;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_stage(int mode, int bc, const StageArgs<T>& a, hipStream_t s) {
+  if (mode == kFirst) return stage_bc<T, kFirst>(bc, a, s);
+  if (mode == kMid) return stage_bc<T, kMid>(bc, a, s);
+  return stage_bc<T, kLast>(bc, a, s);
+}
+
+template <typename T>
+hipError_t launch_observe(int bc, const ObserveArgs<T>& a, hipStream_t s) {
+  const dim3 grid((unsigned)((size_t)a.g.n_orb * a.g.n_k * a.g.tiles_x * a.g.tiles_y));
+  const dim3 block(block_threads(a.g));
+  const size_t lds = lds_elems(bc, a.g) * sizeof(double2);
+  switch (bc) {
+    case kPeriodicPlane:
+      hipLaunchKernelGGL((k_observe<T, kPeriodicPlane>), grid, block, lds, s, a);
+      break;
+    case kPeriodicTile:
+      hipLaunchKernelGGL((k_observe<T, kPeriodicTile>), grid, block, lds, s, a);
+      break;
+    default:
+      hipLaunchKernelGGL((k_observe<T, kIsolatedTile>), grid, block, lds, s, a);
+      break;
+  }
+  return hipGetLastError();
+}
+
+template hipError_t launch_stage<double>(int, int, const StageArgs<double>&, hipStream_t);
+template hipError_t launch_stage<float>(int, int, const StageArgs<float>&, hipStream_t);
+template hipError_t launch_observe<double>(int, const ObserveArgs<double>&, hipStream_t);
+template hipError_t launch_observe<float>(int, const ObserveArgs<float>&, hipStream_t);
+
+}  // namespace td

@@ -1,0 +1,102 @@
+"""CPU-side checks of the boundary: the library loads, exports every symbol
+the public header declares, its struct layouts match the header, and
+configuration errors are reported before any device work."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tddft.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(tddft_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1804_01404_amd import binding
+    lib = binding.load_library()
+    names = _declared_functions()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(binding.EXPORTED) <= set(names)
+
+
+def test_struct_layout_matches_header(tmp_path):
+    from paper_1804_01404_amd import binding
+    src = tmp_path / "sz.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "tddft.h"\n'
+                   'int main(){printf("%zu %zu %zu %zu %zu\\n", sizeof(tddft_config), sizeof(tddft_atom),'
+                   ' offsetof(tddft_config, dt), offsetof(tddft_config, stream),'
+                   ' offsetof(tddft_atom, beta));return 0;}\n')
+    exe = tmp_path / "sz"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
+    assert got == [C.sizeof(binding.Config), C.sizeof(binding.Atom), binding.Config.dt.offset,
+                   binding.Config.stream.offset, binding.Atom.beta.offset]
+
+
+def _cfg(**kw):
+    from paper_1804_01404_amd import binding
+    cfg = binding.Config()
+    cfg.abi_version = binding.ABI_VERSION
+    cfg.struct_size = C.sizeof(binding.Config)
+    cfg.n[:] = [16, 16, 16]
+    cfg.cell[:] = [10.0, 10.0, 10.0]
+    cfg.n_orb = 2
+    cfg.n_k = 1
+    k = np.zeros(3)
+    w = np.ones(1)
+    cfg.kpt = k.ctypes.data_as(C.POINTER(C.c_double))
+    cfg.kw = w.ctypes.data_as(C.POINTER(C.c_double))
+    cfg.dt = 0.02
+    for key, v in kw.items():
+        if key == "n":
+            cfg.n[:] = v
+        else:
+            setattr(cfg, key, v)
+    return cfg, (k, w)
+
+
+@pytest.mark.parametrize("bad", [dict(n=[7, 16, 16]), dict(dt=0.0), dict(precision=7),
+                                 dict(gauge=1), dict(n_orb=0), dict(abi_version=99),
+                                 dict(struct_size=8), dict(xc=3), dict(boundary=5)])
+def test_init_rejects_bad_config_without_device(bad):
+    from paper_1804_01404_amd import binding
+    lib = binding.load_library()
+    cfg, keep = _cfg(**bad)
+    psi = np.zeros(2 * 16 ** 3 * 2)
+    h = C.c_void_p()
+    st = lib.tddft_init(C.byref(cfg), psi.ctypes.data_as(C.POINTER(C.c_double)), C.byref(h))
+    assert st == binding.EINVAL
+    assert not h.value
+
+
+def test_null_arguments():
+    from paper_1804_01404_amd import binding
+    lib = binding.load_library()
+    cfg, keep = _cfg()
+    h = C.c_void_p()
+    assert lib.tddft_init(C.byref(cfg), None, C.byref(h)) == binding.EINVAL
+    assert lib.tddft_init(None, None, C.byref(h)) == binding.EINVAL
+    assert lib.tddft_propagate(None, 1, None, None) == binding.EINVAL
+    assert lib.tddft_energy(None, None) == binding.EINVAL
+    lib.tddft_free(None)
+    assert lib.tddft_last_error(None) == b"null context"
+
+
+def test_product_path_has_no_oracle_dependency():
+    """The package never imports the oracle or the input generator."""
+    pkg = os.path.join(ROOT, "paper_1804_01404_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "oracle" not in re.sub(r"#.*|//.*", "", text).replace("oracles", ""), f
+                assert "import synth" not in text and "from synth" not in text, f

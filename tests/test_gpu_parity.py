@@ -1,0 +1,290 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle and
+closed forms, on the same seeded inputs.
+
+Tolerances (derivation in the design notes):
+* complex128 path: relative density L2 <= 1e-10 (the target), orbitals
+  <= 1e-10, current series <= 1e-8 of its maximum;
+* mixed path (complex FP32 orbitals and stencil, FP64 reductions): FP32
+  rounding of the stored orbitals, 2^-24 ~ 6e-8 per component and step,
+  accumulated over n steps and amplified by the current's cancellation:
+  orbitals and density <= 2e-6 * sqrt(n) relative, current <= 1e-4 of its
+  maximum over the windows used here.
+"""
+import numpy as np
+import pytest
+
+import synth
+from synth.systems import build_system, rng_for
+from oracle import tdks
+from gpu_helpers import announce, gpu_run, max_rel_series, oracle_run, rel_l2
+
+pytestmark = pytest.mark.gpu
+C = 137.035999084
+
+
+def _p4(z):
+    return 1 + z + z ** 2 / 2 + z ** 3 / 6 + z ** 4 / 24
+
+
+def test_mfma_lane_layout():
+    from paper_1804_01404_amd.binding import mfma_layout_check
+    rng = np.random.default_rng(1)
+    A = rng.normal(size=(16, 4))
+    B = rng.normal(size=(4, 16))
+    announce("mfma_f64_16x16x4 layout")
+    D = mfma_layout_check(A, B)
+    assert np.max(np.abs(D - A @ B)) < 1e-14
+
+
+@pytest.mark.parametrize("prec", ["c128", "mixed"])
+def test_plane_waves_closed_form(prec):
+    """Plane waves with Hartree + LDA on: exact scalar recursion per orbital."""
+    n, cell = (12, 10, 16), (7.2, 6.5, 9.6)
+    grid = tdks.Grid(n, cell, "periodic")
+    x, y, z = grid.r_fields()
+    ms = [(0, 0, 0), (1, 0, 0), (0, -1, 2), (2, 1, -1), (-3, 2, 4)]
+    kpt = np.array([[0.11, -0.04, 0.07]])
+    nsteps, dt = 12, 0.03
+    A = np.tile(np.array([0.9, -0.4, 0.3]), (nsteps + 1, 1))
+    A[6:] *= 1.5
+    V0 = -0.21
+    psi = np.empty((1, len(ms)) + grid.shape, dtype=np.complex128)
+    Gs = []
+    for j, m in enumerate(ms):
+        G = np.array([2 * np.pi * m[i] / cell[i] for i in range(3)])
+        Gs.append(G)
+        psi[0, j] = np.exp(1j * (G[0] * x + G[1] * y + G[2] * z)) / np.sqrt(grid.volume)
+    s = build_system(name="planewaves", n=n, cell=cell, boundary="periodic", n_orb=len(ms),
+                     kpts=kpt, kw=np.ones(1), atoms=np.zeros((0, 3)), rng=rng_for(9), n_proj=0,
+                     dt=dt, nsteps=nsteps, A=A, with_orbitals=False)
+    s.psi0 = psi
+    s.v_loc = V0 * np.ones(grid.shape)
+    out = gpu_run(s, precision=prec)
+    hv = np.array(grid.h)
+    c, d = tdks.C2, tdks.D1
+    a = np.ones(len(ms), dtype=np.complex128)
+    Jref = np.zeros((nsteps, 3))
+    for step in range(nsteps):
+        rho = 2 * np.sum(np.abs(a) ** 2) / grid.volume
+        vxc = tdks.lda_pz81(np.array([rho]))[0][0]
+        kap = kpt[0] + 0.5 * (A[step] + A[step + 1]) / C
+        for j, G in enumerate(Gs):
+            th = G * hv
+            K2 = -c[0] - 2 * sum(c[m] * np.cos(m * th) for m in range(1, 5))
+            K1 = 2 * sum(d[m - 1] * np.sin(m * th) for m in range(1, 5))
+            eps = 0.5 * np.sum(K2 / hv ** 2) + np.sum(kap * K1 / hv) + 0.5 * kap @ kap + V0 + vxc
+            a[j] *= _p4(-1j * eps * dt)
+        kap1 = kpt[0] + A[step + 1] / C
+        for j, G in enumerate(Gs):
+            th = G * hv
+            K1 = 2 * sum(d[m - 1] * np.sin(m * th) for m in range(1, 5))
+            Jref[step] += 2 * np.abs(a[j]) ** 2 * (K1 / hv + kap1)
+    Jref *= -1 / grid.volume
+    ref = a[None, :, None, None, None] * psi
+    tol = 1e-12 if prec == "c128" else 2e-6
+    assert rel_l2(out["psi"], ref) < tol
+    assert max_rel_series(out["J"], Jref) < (1e-11 if prec == "c128" else 1e-5)
+
+
+def test_diamond16_gamma_full_run_c128():
+    """The 16^3 Gamma workload, all 200 steps, complex128 against the oracle."""
+    s = synth.single_cell_config(0)
+    g = gpu_run(s)
+    o = oracle_run(s)
+    assert rel_l2(g["rho"], o["rho"]) < 1e-10
+    assert rel_l2(g["psi"], o["psi"]) < 1e-10
+    assert max_rel_series(g["J"], o["J"]) < 1e-8
+    assert abs(g["E"] - o["E"]) < 1e-10 * abs(o["E"])
+    assert np.max(np.abs(g["norms"] - o["norms"])) < 1e-12
+
+
+@pytest.mark.parametrize("prec", ["c128", "mixed"])
+def test_diamond20_kpoints(prec):
+    """20^3 cell, 2^3 Monkhorst-Pack k-points, s+p projectors, x kick."""
+    nsteps = 12
+    s = synth.single_cell_config(1, nk=2, nsteps=nsteps)
+    g = gpu_run(s, precision=prec)
+    o = oracle_run(s)
+    if prec == "c128":
+        assert rel_l2(g["rho"], o["rho"]) < 1e-10
+        assert rel_l2(g["psi"], o["psi"]) < 1e-10
+        assert max_rel_series(g["J"], o["J"]) < 1e-8
+        assert abs(g["E"] - o["E"]) < 1e-10 * abs(o["E"])
+    else:
+        tol = 2e-6 * np.sqrt(nsteps)
+        assert rel_l2(g["rho"], o["rho"]) < tol
+        assert rel_l2(g["psi"], o["psi"]) < tol
+        assert max_rel_series(g["J"], o["J"]) < 1e-4
+        assert abs(g["E"] - o["E"]) < 1e-6 * abs(o["E"])
+
+
+@pytest.mark.parametrize("prec", ["c128", "mixed"])
+def test_isolated_cluster_length_gauge(prec):
+    """Isolated box (zero halo), Hockney Hartree, length-gauge pulse."""
+    nsteps = 10
+    s = synth.single_cell_config(2, n=24, n_fcc=1, n_orb=8, nsteps=nsteps)
+    # a stronger field than the workload's so that it shows within 10 steps
+    s.A = synth.gauss_pulse_table(nsteps, s.dt, 0.05, 0.3, 0.1, 0.1, [0.3, 0.2, 1.0])
+    g = gpu_run(s, precision=prec)
+    o = oracle_run(s)
+    tol = 1e-10 if prec == "c128" else 2e-6 * np.sqrt(nsteps)
+    assert rel_l2(g["rho"], o["rho"]) < tol
+    assert rel_l2(g["psi"], o["psi"]) < tol
+    dscale = max(np.max(np.abs(o["dipole"])), 1e-12)
+    assert np.max(np.abs(g["dipole"] - o["dipole"])) < (1e-9 if prec == "c128" else 1e-4) * dscale
+
+
+def test_isolated_multi_tile():
+    """A 40^3 isolated box is split into x-tiles with zero halos."""
+    rng = rng_for(77)
+    n, h = 40, 0.45
+    L = n * h
+    atoms = rng.uniform(-3, 3, size=(3, 3))
+    nsteps = 4
+    s = build_system(name="iso40", n=(n, n, n), cell=(L, L, L), boundary="isolated", n_orb=3,
+                     kpts=np.zeros((1, 3)), kw=np.ones(1), atoms=atoms, rng=rng, n_proj=4,
+                     dt=0.02, nsteps=nsteps, A=synth.gauss_pulse_table(nsteps, 0.02, 0.05, 0.3, 0.0,
+                                                                        0.1, [1, 0, 0]),
+                     gauge="length")
+    g = gpu_run(s)
+    o = oracle_run(s)
+    assert rel_l2(g["psi"], o["psi"]) < 1e-10
+    assert rel_l2(g["rho"], o["rho"]) < 1e-10
+
+
+def test_periodic_multi_tile_noncubic():
+    """A 36 x 36 x 10 periodic plane is too large for one workgroup: tiles
+    with wrapped halos; anisotropic spacing."""
+    rng = rng_for(78)
+    n, cell = (36, 36, 10), (18.0, 19.8, 6.0)
+    atoms = rng.uniform(0, 6, size=(2, 3))
+    kpts = np.array([[0.05, -0.1, 0.2], [-0.07, 0.02, -0.3]])
+    nsteps = 4
+    s = build_system(name="per36", n=n, cell=cell, boundary="periodic", n_orb=3, kpts=kpts,
+                     kw=np.full(2, 0.5), atoms=atoms, rng=rng, n_proj=4, dt=0.02, nsteps=nsteps,
+                     A=synth.kick_table(nsteps, [0.3, -0.2, 0.1]))
+    g = gpu_run(s)
+    o = oracle_run(s)
+    assert rel_l2(g["psi"], o["psi"]) < 1e-10
+    assert max_rel_series(g["J"], o["J"]) < 1e-8
+
+
+def test_ragged_orbital_count_and_minimum_grid():
+    """n_orb * n_k = 15 (not a multiple of the 8-orbital MFMA group), s-only
+    projectors, a non-cubic 12 x 10 x 9 grid, and the minimum 8^3 grid."""
+    for n, cell, n_orb, n_k, n_proj in [((12, 10, 9), (7.0, 6.1, 5.5), 5, 3, 1),
+                                        ((8, 8, 8), (5.2, 5.2, 5.2), 3, 1, 4)]:
+        rng = rng_for(79)
+        atoms = rng.uniform(0, 5, size=(2, 3))
+        kpts = rng.uniform(-0.3, 0.3, size=(n_k, 3))
+        nsteps = 5
+        s = build_system(name=f"ragged{n}", n=n, cell=cell, boundary="periodic", n_orb=n_orb,
+                         kpts=kpts, kw=np.full(n_k, 1.0 / n_k), atoms=atoms, rng=rng,
+                         n_proj=n_proj, dt=0.02, nsteps=nsteps,
+                         A=synth.cos2_pulse_table(nsteps, 0.02, 0.05, 0.4, 0.1, 0.0, [1, 1, 0]),
+                         r_c=1.6)
+        g = gpu_run(s)
+        o = oracle_run(s)
+        assert rel_l2(g["psi"], o["psi"]) < 1e-10
+        assert max_rel_series(g["J"], o["J"]) < 1e-8
+        assert abs(g["E"] - o["E"]) < 1e-10 * abs(o["E"])
+
+
+def test_time_reversal_and_determinism():
+    s = synth.single_cell_config(0, nsteps=8, kick=0.0)
+    a = gpu_run(s)
+    b = gpu_run(s)
+    assert np.array_equal(a["psi"], b["psi"]) and np.array_equal(a["J"], b["J"])
+    s.dt = -s.dt
+    r = gpu_run(s)
+    assert np.max(np.abs(r["psi"] - np.conj(a["psi"]))) < 1e-14
+    assert np.max(np.abs(r["rho"] - a["rho"])) < 1e-14
+
+
+@pytest.mark.parametrize("prec", ["c128", "mixed"])
+def test_resume_is_bitwise(prec):
+    from paper_1804_01404_amd.binding import TDDFT
+    s = synth.single_cell_config(1, nk=1, nsteps=6)
+    announce(f"resume {prec}")
+    with TDDFT(s, precision=prec) as t:
+        t.set_potential()
+        J_full = t.propagate(s.A)
+        psi_full = t.orbitals()
+    with TDDFT(s, precision=prec) as t:
+        t.set_potential()
+        J1 = t.propagate(s.A[:4])
+        saved = t.orbitals()
+    with TDDFT(s, precision=prec, psi0=saved) as t:
+        t.set_potential()
+        J2 = t.propagate(s.A[3:])
+        psi_res = t.orbitals()
+    assert np.array_equal(np.concatenate([J1, J2]), J_full)
+    assert np.array_equal(psi_res, psi_full)
+
+
+def test_isolated_kick_matches_oracle():
+    from paper_1804_01404_amd.binding import TDDFT
+    s = synth.single_cell_config(2, n=20, n_fcc=1, n_orb=4, nsteps=5)
+    s.A = np.zeros((6, 3))
+    announce("isolated kick")
+    with TDDFT(s, precision="c128") as t:
+        t.set_potential()
+        t.kick(1e-2, 2)
+        t.propagate(s.A)
+        d = t.dipole()
+        psi = t.orbitals()
+    o = tdks.TDKS.from_system(s)
+    x, y, z = o.grid.r_fields()
+    o.psi = o.psi * np.exp(-1j * 1e-2 * z)[None, None]
+    o.propagate(s.A)
+    assert rel_l2(psi, o.psi) < 1e-10
+    assert np.max(np.abs(d - o.dipole())) < 1e-9 * np.max(np.abs(o.dipole()))
+
+
+def test_error_paths():
+    from paper_1804_01404_amd.binding import EINVAL, ESTATE, EUNSTABLE, TDDFT, TDDFTError
+    s = synth.single_cell_config(1, nk=1, nsteps=2, dt=0.08)
+    announce("error paths")
+    with TDDFT(s) as t:
+        with pytest.raises(TDDFTError) as e:
+            t.propagate(s.A)
+        assert e.value.status == ESTATE
+        with pytest.raises(TDDFTError) as e:
+            t.set_potential()
+        assert e.value.status == EUNSTABLE               # 20^3 at dt = 0.08 exceeds 2 sqrt 2
+    s.dt = 0.04
+    with TDDFT(s) as t:
+        t.set_potential()
+        bad = s.A.copy()
+        bad[1, 0] = np.nan
+        with pytest.raises(TDDFTError) as e:
+            t.propagate(bad)
+        assert e.value.status == EINVAL
+        J = t.propagate(s.A)                             # still usable after EINVAL
+        assert np.all(np.isfinite(J))
+        with pytest.raises(TDDFTError) as e:
+            t.kick(1e-3, 0)                              # periodic: kick through A instead
+        assert e.value.status == EINVAL
+
+
+def test_full_size_diamond20_k512_sampled():
+    """The full 20^3 x 512 k-point workload, one step: sampled k-points are
+    recomputed by the oracle one by one (the potential is frozen at rho(t_0)
+    during the step, so each k evolves independently); the density is checked
+    against the downloaded orbitals."""
+    s = synth.single_cell_config(1, nsteps=1)
+    for prec in ("c128", "mixed"):
+        g = gpu_run(s, precision=prec)
+        # oracle potential from the full initial density
+        grid = tdks.Grid(s.n, s.cell, s.boundary)
+        rho0 = tdks.density(s.psi0, s.kw, grid)
+        V = s.v_loc + tdks.hartree_periodic(rho0, grid) + tdks.lda_pz81(rho0)[0]
+        projs = [tdks.Projector(p.idx, p.x, p.beta, p.e_kb) for p in s.projectors]
+        kappa_shift = 0.5 * (s.A[0] + s.A[1]) / C
+        tol = 1e-10 if prec == "c128" else 5e-6
+        for ik in (0, 77, 300, 511):
+            kap = s.kpts[ik] + kappa_shift
+            ref = tdks.taylor_step(s.psi0[ik], s.dt, lambda X: tdks.apply_h(X, kap, V, projs, grid))
+            assert rel_l2(g["psi"][ik], ref) < tol, ik
+        rho_host = tdks.density(g["psi"], s.kw, grid)
+        assert rel_l2(g["rho"], rho_host) < (1e-13 if prec == "c128" else 1e-7)
