@@ -1,0 +1,175 @@
+#!/usr/bin/env python3
+"""Throughput of the real-time TDKS time step on one MI355X.
+
+Workload: the 8-atom diamond cell on a 20^3 grid with 16 doubly occupied
+orbitals at 8^3 = 512 Monkhorst-Pack k-points, s+p Kleinman-Bylander
+projectors, Hartree + PZ81 LDA, x kick (|A0|/c = 1e-3), dt = 0.04 a.u.
+(the 0.08 of the run description exceeds the fourth-order Taylor stability
+bound on this grid; the library refuses it). Inputs are seeded synthetic
+arrays resident in HBM before the timed region.
+
+One step = the whole path: four Horner stages with the nonlocal projections,
+the observables and nonlocal current, the density, FFT Poisson, LDA and the
+current reduction. value = orbital x k-point x grid-point steps per second
+(og-steps/s) of the mixed path (complex FP32 orbitals and stencil, FP64
+reductions, Poisson and projector products); the complex128 path is timed
+beside it. The JSON line also carries the roofline of the dominant kernel
+(a middle Horner stage, HIP events around back-to-back launches) and the
+CPU oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "orbital·gridpoint Taylor steps/s (FP64 vs mixed/batched), % HBM peak"
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+FP64_MFMA_PEAK_TFLOPS = 78.6   # MI355X dense FP64 matrix
+
+
+def time_path(system, precision, steps, warmup):
+    import torch
+    from paper_1804_01404_amd.binding import (KERNEL_DENSITY, KERNEL_OBSERVE, KERNEL_PROJECT,
+                                              KERNEL_STAGE, TDDFT)
+    A = system.A
+    with TDDFT(system, precision=precision) as t:
+        t.set_potential()
+        if warmup:
+            t.propagate(A[: warmup + 1])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        J = t.propagate(A[warmup: warmup + steps + 1])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        dev_ms = t.last_timing_ms()
+        kern = {
+            "stage_ms": t.time_kernel(KERNEL_STAGE, 50),
+            "project_ms": t.time_kernel(KERNEL_PROJECT, 50),
+            "observe_ms": t.time_kernel(KERNEL_OBSERVE, 20),
+            "density_ms": t.time_kernel(KERNEL_DENSITY, 20),
+        }
+    return (t1 - t0) / steps * 1e3, dev_ms, kern, J
+
+
+def cpu_baseline(system, target_s=12.0):
+    """The oracle as it stands, on a bounded sample: the same cell, grid,
+    orbitals and projectors with a subset of the k-points, one BLAS thread."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle import tdks
+    s = system
+    nk = 2
+    with threadpool_limits(limits=1):
+        while True:
+            kw = np.full(nk, 1.0 / nk)
+            o = tdks.TDKS(s.n, s.cell, s.boundary, s.kpts[:nk], kw, s.psi0[:nk], s.dt, s.v_loc,
+                          s.projectors, hartree=s.hartree, xc=s.xc, gauge=s.gauge)
+            t0 = time.perf_counter()
+            o.step(s.A[0], s.A[1])
+            o.current()
+            one = time.perf_counter() - t0
+            if one * 3 >= target_s or nk >= s.n_k:
+                break
+            nk = min(s.n_k, max(nk + 1, int(nk * target_s / (3 * one))))
+        steps = max(1, min(5, int(target_s / max(one, 1e-3))))
+        t0 = time.perf_counter()
+        for n in range(steps):
+            o.step(s.A[n], s.A[n + 1])
+            o.current()
+        el = time.perf_counter() - t0
+    og = s.n_orb * nk * s.n_grid
+    return {"value": og * steps / el, "unit": "og-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{nk} of {s.n_k} k-points x {s.n_orb} orbitals x {s.n_grid} points, "
+                      f"{steps} full steps (Taylor + density + current + Hartree + LDA), "
+                      f"{el:.1f} s, NumPy FP64 with one BLAS thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "c128"])
+    ap.add_argument("--no-twin", action="store_true", help="skip the complex128 comparison run")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the multi-GPU sharding of the step is a design "
+              "(orbital/k-point split, density all-reduce) and is not built; run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import synth
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+
+    total = args.steps + args.warmup
+    s = synth.single_cell_config(1, nsteps=total)
+    og = s.og
+    ms, dev_ms, kern, J = time_path(s, args.precision, args.steps, args.warmup)
+    value = og / (ms * 1e-3)
+    esz = 8 if args.precision == "mixed" else 16
+    # algorithmic bytes of one middle Horner stage: read u_s, read w, write u_{s-1}
+    stage_bytes = 3 * esz * og
+    achieved = stage_bytes / (kern["stage_ms"] * 1e-3) / 1e9
+    # issued MFMA work of one projection launch: one 16x16x4 FP64 MFMA per four
+    # sphere entries, per atom and group of eight orbitals
+    n_groups = (s.n_orb * s.n_k + 7) // 8
+    mfma_flops = sum(n_groups * -(-p.npts // 4) * 2 * 16 * 16 * 4 for p in s.projectors)
+    mfma_tflops = mfma_flops / (kern["project_ms"] * 1e-3) / 1e12
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "og-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64+f64" if args.precision == "mixed" else "c128",
+        "data": "synthetic",
+        "config": {
+            "workload": "diamond-20^3-k512: 8-atom diamond cell, 20^3 grid, 16 orbitals, "
+                        "8^3 k-points, s+p projectors, Hartree+PZ81, x kick, dt 0.04",
+            "og_per_step": og,
+            "precision": args.precision,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_stage (middle Horner stage)",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "bytes_per_launch": stage_bytes,
+            "ms_per_launch": kern["stage_ms"],
+        },
+        "device_ms_per_step": dev_ms,
+        "kernels_ms": kern,
+        "mfma_projection": {"issued_tflops": mfma_tflops, "peak": FP64_MFMA_PEAK_TFLOPS,
+                            "frac": mfma_tflops / FP64_MFMA_PEAK_TFLOPS},
+        "current_finite": bool(np.all(np.isfinite(J))),
+    }
+    if not args.no_twin:
+        other = "c128" if args.precision == "mixed" else "mixed"
+        ms2, dev2, kern2, _ = time_path(s, other, args.steps, args.warmup)
+        out["twin"] = {"precision": other, "value": og / (ms2 * 1e-3), "ms_per_step": ms2,
+                       "kernels_ms": kern2,
+                       "stage_GBs": 3 * (16 if other == "c128" else 8) * og / (kern2["stage_ms"] * 1e-3) / 1e9}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(s)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -64,6 +64,8 @@ enum { TDDFT_XC_NONE = 0, TDDFT_XC_PZ81 = 1 };
 #define TDDFT_FLAG_ALLOW_UNSTABLE 0x1u /* skip the Taylor stability refusal      */
 #define TDDFT_FLAG_DEBUG_SYNC 0x2u     /* synchronise and check after each kernel */
 #define TDDFT_FLAG_NO_GRAPH 0x4u       /* launch kernels directly, no hipGraph    */
+#define TDDFT_FLAG_STREAMING 0x8u      /* one kernel per Horner stage even when the
+                                          orbital fits in LDS (the fused step) */
 
 typedef struct {
   uint32_t abi_version;   /* TDDFT_ABI_VERSION                                  */
@@ -152,6 +154,18 @@ tddft_status tddft_kick(tddft_ctx *ctx, double F0, int32_t axis);
 
 /* Mean device time per step of the last propagate, from HIP events (ms). */
 tddft_status tddft_last_timing(tddft_ctx *ctx, double *ms_per_step);
+
+/* Kernels of one step that tddft_time_kernel can time in isolation. */
+enum { TDDFT_KERNEL_STAGE = 0, TDDFT_KERNEL_PROJECT = 1, TDDFT_KERNEL_OBSERVE = 2,
+       TDDFT_KERNEL_DENSITY = 3 };
+
+/* Launch one kernel of the step `reps` times back to back on the context's
+ * stream and return the mean duration per launch from HIP events around the
+ * launches (ms). TDDFT_KERNEL_STAGE is a middle Horner stage (reads u_s and w,
+ * writes u_{s-1}); it and the projection use the two stage buffers, whose
+ * contents are scratch between steps, so the state is unchanged. Requires
+ * set_potential; EINVAL for an unknown kernel or reps < 1. */
+tddft_status tddft_time_kernel(tddft_ctx *ctx, int32_t which, int32_t reps, double *ms_per_launch);
 
 const char *tddft_last_error(const tddft_ctx *ctx);
 void tddft_free(tddft_ctx *ctx);

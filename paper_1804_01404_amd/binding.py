@@ -24,12 +24,13 @@ PERIODIC, ISOLATED = 0, 1
 C128, MIXED = 0, 1
 VELOCITY, LENGTH = 0, 1
 XC_NONE, XC_PZ81 = 0, 1
-FLAG_ALLOW_UNSTABLE, FLAG_DEBUG_SYNC, FLAG_NO_GRAPH = 1, 2, 4
+FLAG_ALLOW_UNSTABLE, FLAG_DEBUG_SYNC, FLAG_NO_GRAPH, FLAG_STREAMING = 1, 2, 4, 8
 
 EXPORTED = ["tddft_abi_version", "tddft_init", "tddft_set_potential", "tddft_propagate",
             "tddft_density_current", "tddft_get_orbitals", "tddft_set_orbitals", "tddft_energy",
-            "tddft_norms", "tddft_dipole", "tddft_kick", "tddft_last_timing", "tddft_last_error",
-            "tddft_free"]
+            "tddft_norms", "tddft_dipole", "tddft_kick", "tddft_last_timing", "tddft_time_kernel",
+            "tddft_last_error", "tddft_free"]
+KERNEL_STAGE, KERNEL_PROJECT, KERNEL_OBSERVE, KERNEL_DENSITY = 0, 1, 2, 3
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
@@ -87,13 +88,14 @@ def load_library(path: str = LIB_PATH):
     lib.tddft_dipole.argtypes = [C.c_void_p, _dp]
     lib.tddft_kick.argtypes = [C.c_void_p, C.c_double, C.c_int32]
     lib.tddft_last_timing.argtypes = [C.c_void_p, _dp]
+    lib.tddft_time_kernel.argtypes = [C.c_void_p, C.c_int32, C.c_int32, _dp]
     lib.tddft_last_error.argtypes = [C.c_void_p]
     lib.tddft_last_error.restype = C.c_char_p
     lib.tddft_free.argtypes = [C.c_void_p]
     lib.tddft_free.restype = None
     for name in ("tddft_init", "tddft_set_potential", "tddft_propagate", "tddft_density_current",
                  "tddft_get_orbitals", "tddft_set_orbitals", "tddft_energy", "tddft_norms",
-                 "tddft_dipole", "tddft_kick", "tddft_last_timing"):
+                 "tddft_dipole", "tddft_kick", "tddft_last_timing", "tddft_time_kernel"):
         getattr(lib, name).restype = C.c_int
     if lib.tddft_abi_version() != ABI_VERSION:
         raise RuntimeError("libtddft.so ABI version mismatch")
@@ -245,6 +247,13 @@ class TDDFT:
     def last_timing_ms(self) -> float:
         ms = C.c_double()
         self._check(self.lib.tddft_last_timing(self.h, C.byref(ms)))
+        return ms.value
+
+    def time_kernel(self, which: int, reps: int = 50) -> float:
+        """Mean duration (ms) of one kernel of the step, launched alone
+        ``reps`` times on the context's stream between HIP events."""
+        ms = C.c_double()
+        self._check(self.lib.tddft_time_kernel(self.h, int(which), int(reps), C.byref(ms)))
         return ms.value
 
     def close(self):

@@ -66,6 +66,10 @@ struct tddft_ctx {
   // nonlocal
   NLTables nl{};
   double* ent_x = nullptr;
+  double* ent_beta = nullptr;  // [S][4]
+  int n_colors = 0;
+  int *color_start = nullptr, *color_atoms = nullptr;
+  bool fused = false;          // whole step per orbital in LDS
   double2* Eu = nullptr;
   double* jnl = nullptr;
   double nl_bound = 0;
@@ -323,6 +327,36 @@ tddft_status enqueue_step(tddft_ctx* c) {
                             c->cfg.gauge, c->cfg.dt, c->kappa, c->kappaJ, c->efield, c->phA, c->phAJ,
                             c->Alast, c->stream),
          "step_params");
+  if (c->fused) {
+    FusedArgs<T> f{};
+    f.w = as2<T>(c->W);
+    f.V = vpot<T>(c);
+    f.Vloc = c->Vloc;
+    f.kappa = c->kappa;
+    f.phA = c->phA;
+    f.phAJ = c->phAJ;
+    f.efield = (c->cfg.gauge == TDDFT_LENGTH) ? c->efield : nullptr;
+    f.nl = c->nl;
+    f.ent_beta = c->ent_beta;
+    f.ent_x = c->ent_x;
+    f.n_colors = c->n_colors;
+    f.color_start = c->color_start;
+    f.color_atoms = c->color_atoms;
+    f.g = c->g;
+    std::memcpy(f.lap, c->lap, sizeof(f.lap));
+    std::memcpy(f.dh, c->dh, sizeof(f.dh));
+    f.cdiag = c->cdiag;
+    f.dt = c->cfg.dt;
+    f.dV = c->dV;
+    f.obs = c->obs;
+    f.jnl = c->jnl;
+    LAUNCH(launch_fused<T>(f, c->stream), "fused step");
+    LAUNCH(launch_finish(c->obs, 1, c->jnl, c->nl.n_atoms > 0 ? 1 : 0, c->kw_d, c->kappaJ, c->cfg.n_orb,
+                         c->cfg.n_k, c->dV, c->volume, c->counter, 1, c->Jtab, c->scalars, c->nanflag,
+                         c->stream),
+           "finish");
+    return enqueue_density_potential<T>(c);
+  }
   StageArgs<T> a = stage_args<T>(c);
   a.V = vpot<T>(c);
   void* bufs_in[4] = {c->W, c->U0, c->U1, c->U0};
@@ -423,6 +457,48 @@ double spectral_bound(const tddft_ctx* c, double amax, double vmin, double vmax)
   lam += 0.5 * kk;
   const double vabs = std::max(std::fabs(vmin), std::fabs(vmax));
   return lam + vabs + c->nl_bound;
+}
+
+template <typename T>
+tddft_status launch_one(tddft_ctx* c, int which) {
+  if (which == TDDFT_KERNEL_STAGE) {
+    StageArgs<T> a = stage_args<T>(c);
+    a.V = vpot<T>(c);
+    a.in = as2<T>(c->U0);
+    a.w = as2<T>(c->W);
+    a.out = as2<T>(c->U1);
+    a.tau = c->cfg.dt / 2;
+    LAUNCH(launch_stage<T>(kMid, c->bc, a, c->stream), "stage");
+  } else if (which == TDDFT_KERNEL_PROJECT) {
+    if (c->nl.n_atoms == 0) return TDDFT_OK;
+    ProjArgs<T> pa{};
+    pa.u = as2<T>(c->U0);
+    pa.phA = c->phA;
+    pa.nl = c->nl;
+    pa.N = (int)c->N;
+    pa.n_orb = c->cfg.n_orb;
+    pa.n_orb_tot = (int)c->n_orb_tot;
+    pa.dV = c->dV;
+    pa.moments = 0;
+    pa.Eu = c->Eu;
+    pa.jnl = c->jnl;
+    LAUNCH(launch_project<T>(pa, c->stream), "project");
+  } else if (which == TDDFT_KERNEL_OBSERVE) {
+    ObserveArgs<T> oa{};
+    oa.w = as2<T>(c->W);
+    oa.Vloc = c->Vloc;
+    oa.g = c->g;
+    std::memcpy(oa.dh, c->dh, sizeof(oa.dh));
+    std::memcpy(oa.lap, c->lap, sizeof(oa.lap));
+    oa.cdiag = c->cdiag;
+    oa.out = c->obs;
+    LAUNCH(launch_observe<T>(c->bc, oa, c->stream), "observe");
+  } else {
+    LAUNCH(launch_rho_partial<T>(as2<T>(c->W), c->kw_d, c->cfg.n_orb, c->cfg.n_k, (int)c->N, c->rho_chunk,
+                                 c->rho_part, c->stream),
+           "rho_partial");
+  }
+  return TDDFT_OK;
 }
 
 }  // namespace
@@ -658,6 +734,31 @@ tddft_status tddft_set_potential(tddft_ctx* c, const double* v_loc, int32_t n_at
   std::vector<int> pt_ent(std::max(S, 1)), fillpos(pt_ptr.begin(), pt_ptr.end() - 1);
   for (int e = 0; e < S; ++e) pt_ent[fillpos[ent_idx[e]]++] = e;
   c->nl_bound = nl_bound * std::max(1, max_overlap);
+  // greedy colouring: atoms sharing a grid point get different colours
+  std::vector<int> color(n_atoms, -1);
+  int n_colors = 0;
+  {
+    for (int a = 0; a < n_atoms; ++a) {
+      std::vector<char> used(n_colors + 1, 0);
+      for (int e = atom_start[a]; e < atom_start[a + 1]; ++e) {
+        const int p = ent_idx[e];
+        for (int t = pt_ptr[p]; t < pt_ptr[p + 1]; ++t) {
+          const int b = ent_atom[pt_ent[t]];
+          if (b != a && color[b] >= 0) used[color[b]] = 1;
+        }
+      }
+      int cl = 0;
+      while (cl < n_colors && used[cl]) ++cl;
+      color[a] = cl;
+      n_colors = std::max(n_colors, cl + 1);
+    }
+  }
+  std::vector<int> color_start(n_colors + 1, 0), color_atoms;
+  for (int cl = 0; cl < n_colors; ++cl) {
+    for (int a = 0; a < n_atoms; ++a)
+      if (color[a] == cl) color_atoms.push_back(a);
+    color_start[cl + 1] = (int)color_atoms.size();
+  }
   c->max_overlap = max_overlap;
   // exp(i k . x_e)
   std::vector<double2> phk((size_t)c->cfg.n_k * std::max(S, 1));
@@ -681,7 +782,7 @@ tddft_status tddft_set_potential(tddft_ctx* c, const double* v_loc, int32_t n_at
   HIP_TRY(hipStreamSynchronize(c->stream));
   tddft_status st;
   int *d_atom_start, *d_ent_idx, *d_ent_atom, *d_pt_ptr, *d_pt_ent;
-  double *d_ent_B, *d_atom_E, *d_ent_x;
+  double *d_ent_B, *d_atom_E, *d_ent_x, *d_ent_beta;
   double2 *d_phk, *d_phA, *d_phAJ, *d_Eu;
   double* d_jnl;
   const int nA = std::max(n_atoms, 1);
@@ -690,6 +791,8 @@ tddft_status tddft_set_potential(tddft_ctx* c, const double* v_loc, int32_t n_at
       (st = dalloc_t(c, Sx, &d_ent_atom)) || (st = dalloc_t(c, N + 1, &d_pt_ptr)) ||
       (st = dalloc_t(c, pt_ent.size(), &d_pt_ent)) || (st = dalloc_t(c, (size_t)Sx * kCols, &d_ent_B)) ||
       (st = dalloc_t(c, (size_t)nA * kMaxProj, &d_atom_E)) || (st = dalloc_t(c, (size_t)Sx * 3, &d_ent_x)) ||
+      (st = dalloc_t(c, (size_t)Sx * kMaxProj, &d_ent_beta)) ||
+      (st = dalloc_t(c, (size_t)n_colors + 1, &c->color_start)) || (st = dalloc_t(c, (size_t)nA, &c->color_atoms)) ||
       (st = dalloc_t(c, phk.size(), &d_phk)) || (st = dalloc_t(c, Sx, &d_phA)) ||
       (st = dalloc_t(c, Sx, &d_phAJ)) ||
       (st = dalloc_t(c, c->n_orb_tot * nA * kMaxProj, &d_Eu)) || (st = dalloc_t(c, c->n_orb_tot * 4, &d_jnl)))
@@ -706,6 +809,13 @@ tddft_status tddft_set_potential(tddft_ctx* c, const double* v_loc, int32_t n_at
   HIP_TRY(up(d_ent_B, ent_B.data(), ent_B.size() * sizeof(double)));
   HIP_TRY(up(d_atom_E, atom_E.data(), atom_E.size() * sizeof(double)));
   HIP_TRY(up(d_ent_x, ent_x.data(), ent_x.size() * sizeof(double)));
+  std::vector<double> ent_beta((size_t)S * kMaxProj);
+  for (int e = 0; e < S; ++e)
+    for (int p = 0; p < kMaxProj; ++p) ent_beta[(size_t)e * kMaxProj + p] = ent_B[(size_t)e * kCols + p * kMoments];
+  HIP_TRY(up(d_ent_beta, ent_beta.data(), ent_beta.size() * sizeof(double)));
+  HIP_TRY(up(c->color_start, color_start.data(), color_start.size() * sizeof(int)));
+  HIP_TRY(up(c->color_atoms, color_atoms.data(), color_atoms.size() * sizeof(int)));
+  c->n_colors = n_colors;
   HIP_TRY(up(d_phk, phk.data(), (size_t)c->cfg.n_k * S * sizeof(double2)));
   HIP_TRY(up(c->Vloc, v_loc, N * sizeof(double)));
   c->nl.n_atoms = n_atoms;
@@ -719,6 +829,9 @@ tddft_status tddft_set_potential(tddft_ctx* c, const double* v_loc, int32_t n_at
   c->nl.pt_ent = d_pt_ent;
   c->nl.phk = d_phk;
   c->ent_x = d_ent_x;
+  c->ent_beta = d_ent_beta;
+  c->fused = !(c->cfg.flags & TDDFT_FLAG_STREAMING) &&
+             fused_supported(c->g, n_atoms, c->mixed ? sizeof(float2) : sizeof(double2));
   c->phA = d_phA;
   c->phAJ = d_phAJ;
   c->Eu = d_Eu;
@@ -934,6 +1047,33 @@ tddft_status tddft_kick(tddft_ctx* c, double F0, int32_t axis) {
   tddft_status st = potential_dispatch(c);
   if (st != TDDFT_OK) return st;
   HIP_TRY(hipStreamSynchronize(c->stream));
+  return TDDFT_OK;
+}
+
+tddft_status tddft_time_kernel(tddft_ctx* c, int32_t which, int32_t reps, double* ms) {
+  if (!c || !ms) return TDDFT_EINVAL;
+  if (c->poisoned) return fail(c, TDDFT_ESTATE, "context poisoned: " + c->err);
+  if (!c->potential_set) return fail(c, TDDFT_ESTATE, "time_kernel before set_potential");
+  if (reps < 1 || which < 0 || which > TDDFT_KERNEL_DENSITY) return fail(c, TDDFT_EINVAL, "bad kernel or reps");
+  double Ab[6];
+  for (int i = 0; i < 3; ++i) Ab[i] = Ab[3 + i] = c->A_last[i];
+  HIP_TRY(hipMemcpyAsync(c->Aobs, Ab, sizeof(Ab), hipMemcpyHostToDevice, c->stream));
+  LAUNCH(launch_step_params(c->Aobs, c->counter, 0, c->kpt_d, c->cfg.n_k, c->ent_x, c->nl.n_ent,
+                            c->cfg.gauge, c->cfg.dt, c->kappa, c->kappaJ, c->efield, c->phA, c->phAJ,
+                            c->Alast, c->stream),
+         "step_params");
+  tddft_status st = c->mixed ? launch_one<float>(c, which) : launch_one<double>(c, which);  // warm-up
+  if (st != TDDFT_OK) return st;
+  HIP_TRY(hipEventRecord(c->ev0, c->stream));
+  for (int r = 0; r < reps; ++r) {
+    st = c->mixed ? launch_one<float>(c, which) : launch_one<double>(c, which);
+    if (st != TDDFT_OK) return st;
+  }
+  HIP_TRY(hipEventRecord(c->ev1, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  float t = 0;
+  HIP_TRY(hipEventElapsedTime(&t, c->ev0, c->ev1));
+  *ms = t / reps;
   return TDDFT_OK;
 }
 

@@ -94,6 +94,31 @@ struct ProjArgs {
   double* jnl;             // moments: [n_orb_tot][4]: nonlocal current (3) and energy
 };
 
+template <typename T>
+struct FusedArgs {
+  using T2 = typename Vec2<T>::type;
+  T2* w;                   // [n_orb_tot][N], updated in place
+  const T* V;              // [N] total potential, stage precision
+  const double* Vloc;      // [N]
+  const double* kappa;     // [n_k][3] at the step midpoint
+  const double2* phA;      // [S] exp(i A_mid . x / c)
+  const double2* phAJ;     // [S] exp(i A_{n+1} . x / c)
+  const double* efield;    // [3] length gauge or nullptr
+  NLTables nl;
+  const double* ent_beta;  // [S][4] beta_p (0 beyond n_proj)
+  const double* ent_x;     // [S][3]
+  int n_colors;            // atoms grouped so that spheres within a group are disjoint
+  const int* color_start;  // [n_colors + 1] into color_atoms
+  const int* color_atoms;  // [n_atoms]
+  Geometry g;
+  double lap[3][5];
+  double dh[3][4];
+  double cdiag;
+  double dt, dV;
+  double* obs;             // [n_orb_tot][8]
+  double* jnl;             // [n_orb_tot][4]
+};
+
 // ---- launchers (defined in the .hip files) --------------------------------
 template <typename T>
 hipError_t launch_stage(int mode, int bc, const StageArgs<T>& a, hipStream_t s);
@@ -101,6 +126,9 @@ template <typename T>
 hipError_t launch_observe(int bc, const ObserveArgs<T>& a, hipStream_t s);
 template <typename T>
 hipError_t launch_project(const ProjArgs<T>& a, hipStream_t s);
+template <typename T>
+hipError_t launch_fused(const FusedArgs<T>& a, hipStream_t s);
+bool fused_supported(const Geometry& g, int n_atoms, size_t elem);
 
 hipError_t launch_step_params(const double* A, const int* counter, int use_counter,
                               const double* kpt, int n_k, const double* ent_x, int S, int gauge,

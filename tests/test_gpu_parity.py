@@ -20,6 +20,8 @@ from gpu_helpers import announce, gpu_run, max_rel_series, oracle_run, rel_l2
 
 pytestmark = pytest.mark.gpu
 C = 137.035999084
+STREAMING = 8   # one kernel per Horner stage instead of the fused LDS-resident step
+PATHS = [pytest.param(0, id="fused"), pytest.param(STREAMING, id="streaming")]
 
 
 def _p4(z):
@@ -36,8 +38,9 @@ def test_mfma_lane_layout():
     assert np.max(np.abs(D - A @ B)) < 1e-14
 
 
+@pytest.mark.parametrize("flags", PATHS)
 @pytest.mark.parametrize("prec", ["c128", "mixed"])
-def test_plane_waves_closed_form(prec):
+def test_plane_waves_closed_form(prec, flags):
     """Plane waves with Hartree + LDA on: exact scalar recursion per orbital."""
     n, cell = (12, 10, 16), (7.2, 6.5, 9.6)
     grid = tdks.Grid(n, cell, "periodic")
@@ -59,7 +62,7 @@ def test_plane_waves_closed_form(prec):
                      dt=dt, nsteps=nsteps, A=A, with_orbitals=False)
     s.psi0 = psi
     s.v_loc = V0 * np.ones(grid.shape)
-    out = gpu_run(s, precision=prec)
+    out = gpu_run(s, precision=prec, flags=flags)
     hv = np.array(grid.h)
     c, d = tdks.C2, tdks.D1
     a = np.ones(len(ms), dtype=np.complex128)
@@ -86,10 +89,11 @@ def test_plane_waves_closed_form(prec):
     assert max_rel_series(out["J"], Jref) < (1e-11 if prec == "c128" else 1e-5)
 
 
-def test_diamond16_gamma_full_run_c128():
+@pytest.mark.parametrize("flags", PATHS)
+def test_diamond16_gamma_full_run_c128(flags):
     """The 16^3 Gamma workload, all 200 steps, complex128 against the oracle."""
     s = synth.single_cell_config(0)
-    g = gpu_run(s)
+    g = gpu_run(s, flags=flags)
     o = oracle_run(s)
     assert rel_l2(g["rho"], o["rho"]) < 1e-10
     assert rel_l2(g["psi"], o["psi"]) < 1e-10
@@ -98,12 +102,13 @@ def test_diamond16_gamma_full_run_c128():
     assert np.max(np.abs(g["norms"] - o["norms"])) < 1e-12
 
 
+@pytest.mark.parametrize("flags", PATHS)
 @pytest.mark.parametrize("prec", ["c128", "mixed"])
-def test_diamond20_kpoints(prec):
+def test_diamond20_kpoints(prec, flags):
     """20^3 cell, 2^3 Monkhorst-Pack k-points, s+p projectors, x kick."""
     nsteps = 12
     s = synth.single_cell_config(1, nk=2, nsteps=nsteps)
-    g = gpu_run(s, precision=prec)
+    g = gpu_run(s, precision=prec, flags=flags)
     o = oracle_run(s)
     if prec == "c128":
         assert rel_l2(g["rho"], o["rho"]) < 1e-10
@@ -118,11 +123,13 @@ def test_diamond20_kpoints(prec):
         assert abs(g["E"] - o["E"]) < 1e-6 * abs(o["E"])
 
 
+@pytest.mark.parametrize("n", [20, 24])
 @pytest.mark.parametrize("prec", ["c128", "mixed"])
-def test_isolated_cluster_length_gauge(prec):
-    """Isolated box (zero halo), Hockney Hartree, length-gauge pulse."""
+def test_isolated_cluster_length_gauge(prec, n):
+    """Isolated box (zero halo), Hockney Hartree, length-gauge pulse; the
+    20^3 box runs the fused step, the 24^3 box the per-stage kernels."""
     nsteps = 10
-    s = synth.single_cell_config(2, n=24, n_fcc=1, n_orb=8, nsteps=nsteps)
+    s = synth.single_cell_config(2, n=n, n_fcc=1, n_orb=8, nsteps=nsteps)
     # a stronger field than the workload's so that it shows within 10 steps
     s.A = synth.gauss_pulse_table(nsteps, s.dt, 0.05, 0.3, 0.1, 0.1, [0.3, 0.2, 1.0])
     g = gpu_run(s, precision=prec)
@@ -190,13 +197,14 @@ def test_ragged_orbital_count_and_minimum_grid():
         assert abs(g["E"] - o["E"]) < 1e-10 * abs(o["E"])
 
 
-def test_time_reversal_and_determinism():
+@pytest.mark.parametrize("flags", PATHS)
+def test_time_reversal_and_determinism(flags):
     s = synth.single_cell_config(0, nsteps=8, kick=0.0)
-    a = gpu_run(s)
-    b = gpu_run(s)
+    a = gpu_run(s, flags=flags)
+    b = gpu_run(s, flags=flags)
     assert np.array_equal(a["psi"], b["psi"]) and np.array_equal(a["J"], b["J"])
     s.dt = -s.dt
-    r = gpu_run(s)
+    r = gpu_run(s, flags=flags)
     assert np.max(np.abs(r["psi"] - np.conj(a["psi"]))) < 1e-14
     assert np.max(np.abs(r["rho"] - a["rho"])) < 1e-14
 
@@ -267,14 +275,15 @@ def test_error_paths():
         assert e.value.status == EINVAL
 
 
-def test_full_size_diamond20_k512_sampled():
+@pytest.mark.parametrize("flags", PATHS)
+def test_full_size_diamond20_k512_sampled(flags):
     """The full 20^3 x 512 k-point workload, one step: sampled k-points are
     recomputed by the oracle one by one (the potential is frozen at rho(t_0)
     during the step, so each k evolves independently); the density is checked
     against the downloaded orbitals."""
     s = synth.single_cell_config(1, nsteps=1)
     for prec in ("c128", "mixed"):
-        g = gpu_run(s, precision=prec)
+        g = gpu_run(s, precision=prec, flags=flags)
         # oracle potential from the full initial density
         grid = tdks.Grid(s.n, s.cell, s.boundary)
         rho0 = tdks.density(s.psi0, s.kw, grid)
