@@ -96,6 +96,9 @@ def main():
     ap.add_argument("--precision", default="mixed", choices=["mixed", "c128"])
     ap.add_argument("--no-twin", action="store_true", help="skip the complex128 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="also run a plain device copy of this many MB (a known-size "
+                         "reference for the HBM byte counters of a profiler run)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the multi-GPU sharding of the step is a design "
@@ -109,6 +112,14 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
 
+    if args.copy_probe_mb:
+        n = args.copy_probe_mb * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     total = args.steps + args.warmup
     s = synth.single_cell_config(1, nsteps=total)
     og = s.og

@@ -170,6 +170,42 @@ tddft_status tddft_time_kernel(tddft_ctx *ctx, int32_t which, int32_t reps, doub
 const char *tddft_last_error(const tddft_ctx *ctx);
 void tddft_free(tddft_ctx *ctx);
 
+/* ---- Batches of independent cells -------------------------------------
+ * Many cells with their own grid, orbital and k-point counts, atoms and
+ * field tables advance together: one hipGraph-captured batch step holds, per
+ * group of cells with the same cubic grid (12, 16 or 20 points per axis), one
+ * persistent launch of the fused step whose workgroups pull (cell, orbital)
+ * items from a device queue, largest cells first; other cells run the
+ * per-stage kernels on forked streams inside the same graph. The persistent
+ * grid of every group is chosen by timing candidates on the first steps
+ * (every candidate computes identical bits), unless
+ * TDDFT_FLAG_NO_TUNE is set in cfgs[0].flags. Every cell behaves as its own
+ * context would alone; the current of a cell is its own. */
+#define TDDFT_FLAG_NO_TUNE 0x10u
+
+typedef struct tddft_batch tddft_batch;
+
+/* n_cells configurations and initial orbitals (layout as in tddft_init).
+ * All cells use cfgs[0].precision, cfgs[0].stream (NULL: a stream owned by
+ * the batch) and cfgs[0].flags. Errors as tddft_init; on failure *out = NULL. */
+tddft_status tddft_batch_create(int32_t n_cells, const tddft_config *cfgs, const double *const *psi0,
+                                tddft_batch **out);
+/* As tddft_set_potential for one cell (0 <= cell < n_cells). */
+tddft_status tddft_batch_set_potential(tddft_batch *b, int32_t cell, const double *v_loc, int32_t n_atoms,
+                                       const tddft_atom *atoms);
+/* Advance every cell nsteps steps; A[c] is cell c's table [nsteps + 1][3],
+ * J_out (may be NULL, or hold NULL entries) receives [nsteps][3] per cell. */
+tddft_status tddft_batch_propagate(tddft_batch *b, int32_t nsteps, const double *const *A, double *const *J_out);
+/* The context of one cell, for tddft_get_orbitals, tddft_density_current,
+ * tddft_energy, tddft_norms; owned by the batch (do not free). NULL if out of range. */
+tddft_ctx *tddft_batch_cell(tddft_batch *b, int32_t cell);
+/* Mean device time per batch step of the last propagate (ms). */
+tddft_status tddft_batch_last_timing(tddft_batch *b, double *ms_per_step);
+/* JSON text of the plan and the tuner's measurements, NUL-terminated in buf. */
+tddft_status tddft_batch_report(tddft_batch *b, char *buf, size_t len);
+const char *tddft_batch_last_error(const tddft_batch *b);
+void tddft_batch_free(tddft_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -24,12 +24,14 @@ PERIODIC, ISOLATED = 0, 1
 C128, MIXED = 0, 1
 VELOCITY, LENGTH = 0, 1
 XC_NONE, XC_PZ81 = 0, 1
-FLAG_ALLOW_UNSTABLE, FLAG_DEBUG_SYNC, FLAG_NO_GRAPH, FLAG_STREAMING = 1, 2, 4, 8
+FLAG_ALLOW_UNSTABLE, FLAG_DEBUG_SYNC, FLAG_NO_GRAPH, FLAG_STREAMING, FLAG_NO_TUNE = 1, 2, 4, 8, 16
 
 EXPORTED = ["tddft_abi_version", "tddft_init", "tddft_set_potential", "tddft_propagate",
             "tddft_density_current", "tddft_get_orbitals", "tddft_set_orbitals", "tddft_energy",
             "tddft_norms", "tddft_dipole", "tddft_kick", "tddft_last_timing", "tddft_time_kernel",
-            "tddft_last_error", "tddft_free"]
+            "tddft_last_error", "tddft_free", "tddft_batch_create", "tddft_batch_set_potential",
+            "tddft_batch_propagate", "tddft_batch_cell", "tddft_batch_last_timing", "tddft_batch_report",
+            "tddft_batch_last_error", "tddft_batch_free"]
 KERNEL_STAGE, KERNEL_PROJECT, KERNEL_OBSERVE, KERNEL_DENSITY = 0, 1, 2, 3
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -96,6 +98,20 @@ def load_library(path: str = LIB_PATH):
     for name in ("tddft_init", "tddft_set_potential", "tddft_propagate", "tddft_density_current",
                  "tddft_get_orbitals", "tddft_set_orbitals", "tddft_energy", "tddft_norms",
                  "tddft_dipole", "tddft_kick", "tddft_last_timing", "tddft_time_kernel"):
+        getattr(lib, name).restype = C.c_int
+    lib.tddft_batch_create.argtypes = [C.c_int32, C.POINTER(Config), C.POINTER(_dp), C.POINTER(C.c_void_p)]
+    lib.tddft_batch_set_potential.argtypes = [C.c_void_p, C.c_int32, _dp, C.c_int32, C.POINTER(Atom)]
+    lib.tddft_batch_propagate.argtypes = [C.c_void_p, C.c_int32, C.POINTER(_dp), C.POINTER(_dp)]
+    lib.tddft_batch_cell.argtypes = [C.c_void_p, C.c_int32]
+    lib.tddft_batch_cell.restype = C.c_void_p
+    lib.tddft_batch_last_timing.argtypes = [C.c_void_p, _dp]
+    lib.tddft_batch_report.argtypes = [C.c_void_p, C.c_char_p, C.c_size_t]
+    lib.tddft_batch_last_error.argtypes = [C.c_void_p]
+    lib.tddft_batch_last_error.restype = C.c_char_p
+    lib.tddft_batch_free.argtypes = [C.c_void_p]
+    lib.tddft_batch_free.restype = None
+    for name in ("tddft_batch_create", "tddft_batch_set_potential", "tddft_batch_propagate",
+                 "tddft_batch_last_timing", "tddft_batch_report"):
         getattr(lib, name).restype = C.c_int
     if lib.tddft_abi_version() != ABI_VERSION:
         raise RuntimeError("libtddft.so ABI version mismatch")
@@ -287,3 +303,142 @@ def mfma_layout_check(A: np.ndarray, B: np.ndarray) -> np.ndarray:
     if fn(_ptr(A), _ptr(B), _ptr(D)) != 0:
         raise RuntimeError("mfma layout check failed to run")
     return D
+
+
+def _config_for(system, precision, flags):
+    s = system
+    cfg = Config()
+    cfg.abi_version = ABI_VERSION
+    cfg.struct_size = C.sizeof(Config)
+    cfg.n[:] = list(s.n)
+    cfg.cell[:] = list(s.cell)
+    cfg.boundary = PERIODIC if s.boundary == "periodic" else ISOLATED
+    cfg.n_orb = s.n_orb
+    cfg.n_k = s.n_k
+    kpt = np.ascontiguousarray(s.kpts, dtype=np.float64)
+    kw = np.ascontiguousarray(s.kw, dtype=np.float64)
+    cfg.kpt = _ptr(kpt)
+    cfg.kw = _ptr(kw)
+    cfg.dt = s.dt
+    cfg.precision = MIXED if precision == "mixed" else C128
+    cfg.hartree = int(bool(s.hartree))
+    cfg.xc = XC_PZ81 if s.xc else XC_NONE
+    cfg.gauge = LENGTH if s.gauge == "length" else VELOCITY
+    cfg.flags = flags
+    return cfg, (kpt, kw)
+
+
+def _atoms_for(projs):
+    keep = []
+    atoms = (Atom * max(1, len(projs)))()
+    for i, p in enumerate(projs):
+        idx = np.ascontiguousarray(p.idx, dtype=np.int32)
+        x = np.ascontiguousarray(p.x, dtype=np.float64)
+        beta = np.ascontiguousarray(p.beta, dtype=np.float64)
+        ekb = np.ascontiguousarray(p.e_kb, dtype=np.float64)
+        keep += [idx, x, beta, ekb]
+        atoms[i].npts = idx.shape[0]
+        atoms[i].n_proj = beta.shape[0]
+        atoms[i].idx = _ptr(idx, C.c_int32)
+        atoms[i].x = _ptr(x)
+        atoms[i].beta = _ptr(beta)
+        atoms[i].e_kb = _ptr(ekb)
+    return atoms, keep
+
+
+class TDDFTBatch:
+    """Many independent cells advanced together (tddft_batch_* entry points).
+
+    Device memory comes from the library's own allocator; the stream is a
+    torch stream so that torch work can be ordered against the batch."""
+
+    def __init__(self, systems, *, precision: str = "mixed", flags: int = 0):
+        import torch
+        self.lib = load_library()
+        self.systems = list(systems)
+        n = len(self.systems)
+        self._stream = torch.cuda.Stream()
+        cfgs = (Config * n)()
+        keep = []
+        psis = []
+        for i, s in enumerate(self.systems):
+            cfg, k = _config_for(s, precision, flags)
+            keep.append(k)
+            cfgs[i] = cfg
+            psi = np.ascontiguousarray(s.psi0, dtype=np.complex128)
+            psis.append(psi)
+        cfgs[0].stream = C.c_void_p(self._stream.cuda_stream)
+        ptrs = (_dp * n)(*[_ptr(p.view(np.float64)) for p in psis])
+        h = C.c_void_p()
+        st = self.lib.tddft_batch_create(n, cfgs, ptrs, C.byref(h))
+        if st != OK:
+            raise TDDFTError(st, "tddft_batch_create failed")
+        self.h = h
+        for i, s in enumerate(self.systems):
+            atoms, kp = _atoms_for(s.projectors)
+            v = np.ascontiguousarray(s.v_loc, dtype=np.float64)
+            self._check(self.lib.tddft_batch_set_potential(self.h, i, _ptr(v), len(s.projectors),
+                                                           atoms if s.projectors else None))
+
+    def _check(self, st):
+        if st != OK:
+            msg = self.lib.tddft_batch_last_error(self.h)
+            raise TDDFTError(st, msg.decode() if msg else "")
+
+    def propagate(self, tables):
+        """tables: one A table [nsteps + 1, 3] per cell; returns the J tables."""
+        n = len(self.systems)
+        tabs = [np.ascontiguousarray(t, dtype=np.float64) for t in tables]
+        nsteps = tabs[0].shape[0] - 1
+        assert all(t.shape == (nsteps + 1, 3) for t in tabs)
+        Js = [np.zeros((nsteps, 3)) for _ in range(n)]
+        A = (_dp * n)(*[_ptr(t) for t in tabs])
+        Jp = (_dp * n)(*[_ptr(j) for j in Js])
+        self._check(self.lib.tddft_batch_propagate(self.h, nsteps, A, Jp))
+        return Js
+
+    def orbitals(self, cell):
+        s = self.systems[cell]
+        c = self.lib.tddft_batch_cell(self.h, cell)
+        psi = np.empty((s.n_k, s.n_orb, s.n[2], s.n[1], s.n[0]), dtype=np.complex128)
+        st = self.lib.tddft_get_orbitals(c, _ptr(psi.view(np.float64)))
+        if st != OK:
+            raise TDDFTError(st, self.lib.tddft_last_error(c).decode())
+        return psi
+
+    def density(self, cell):
+        s = self.systems[cell]
+        c = self.lib.tddft_batch_cell(self.h, cell)
+        rho = np.empty((s.n[2], s.n[1], s.n[0]))
+        st = self.lib.tddft_density_current(c, _ptr(rho), None)
+        if st != OK:
+            raise TDDFTError(st, self.lib.tddft_last_error(c).decode())
+        return rho
+
+    def last_timing_ms(self) -> float:
+        ms = C.c_double()
+        self._check(self.lib.tddft_batch_last_timing(self.h, C.byref(ms)))
+        return ms.value
+
+    def report(self) -> dict:
+        import json
+        buf = C.create_string_buffer(1 << 16)
+        self._check(self.lib.tddft_batch_report(self.h, buf, len(buf)))
+        return json.loads(buf.value.decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.tddft_batch_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

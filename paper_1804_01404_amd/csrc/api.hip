@@ -321,42 +321,54 @@ tddft_status enqueue_observe(tddft_ctx* c, int bump) {
   return TDDFT_OK;
 }
 
-template <typename T>
-tddft_status enqueue_step(tddft_ctx* c) {
+tddft_status enqueue_params(tddft_ctx* c) {
   LAUNCH(launch_step_params(c->Atab, c->counter, 1, c->kpt_d, c->cfg.n_k, c->ent_x, c->nl.n_ent,
                             c->cfg.gauge, c->cfg.dt, c->kappa, c->kappaJ, c->efield, c->phA, c->phAJ,
                             c->Alast, c->stream),
          "step_params");
-  if (c->fused) {
-    FusedArgs<T> f{};
-    f.w = as2<T>(c->W);
-    f.V = vpot<T>(c);
-    f.Vloc = c->Vloc;
-    f.kappa = c->kappa;
-    f.phA = c->phA;
-    f.phAJ = c->phAJ;
-    f.efield = (c->cfg.gauge == TDDFT_LENGTH) ? c->efield : nullptr;
-    f.nl = c->nl;
-    f.ent_beta = c->ent_beta;
-    f.ent_x = c->ent_x;
-    f.n_colors = c->n_colors;
-    f.color_start = c->color_start;
-    f.color_atoms = c->color_atoms;
-    f.g = c->g;
-    std::memcpy(f.lap, c->lap, sizeof(f.lap));
-    std::memcpy(f.dh, c->dh, sizeof(f.dh));
-    f.cdiag = c->cdiag;
-    f.dt = c->cfg.dt;
-    f.dV = c->dV;
-    f.obs = c->obs;
-    f.jnl = c->jnl;
-    LAUNCH(launch_fused<T>(f, c->stream), "fused step");
-    LAUNCH(launch_finish(c->obs, 1, c->jnl, c->nl.n_atoms > 0 ? 1 : 0, c->kw_d, c->kappaJ, c->cfg.n_orb,
-                         c->cfg.n_k, c->dV, c->volume, c->counter, 1, c->Jtab, c->scalars, c->nanflag,
-                         c->stream),
-           "finish");
-    return enqueue_density_potential<T>(c);
-  }
+  return TDDFT_OK;
+}
+
+template <typename T>
+FusedArgs<T> fused_args(tddft_ctx* c) {
+  FusedArgs<T> f{};
+  f.w = as2<T>(c->W);
+  f.V = vpot<T>(c);
+  f.Vloc = c->Vloc;
+  f.kappa = c->kappa;
+  f.phA = c->phA;
+  f.phAJ = c->phAJ;
+  f.efield = (c->cfg.gauge == TDDFT_LENGTH) ? c->efield : nullptr;
+  f.nl = c->nl;
+  f.ent_beta = c->ent_beta;
+  f.ent_x = c->ent_x;
+  f.n_colors = c->n_colors;
+  f.color_start = c->color_start;
+  f.color_atoms = c->color_atoms;
+  f.g = c->g;
+  std::memcpy(f.lap, c->lap, sizeof(f.lap));
+  std::memcpy(f.dh, c->dh, sizeof(f.dh));
+  f.cdiag = c->cdiag;
+  f.dt = c->cfg.dt;
+  f.dV = c->dV;
+  f.obs = c->obs;
+  f.jnl = c->jnl;
+  return f;
+}
+
+// after the fused orbital update: current, density and the new potential
+template <typename T>
+tddft_status enqueue_fused_tail(tddft_ctx* c) {
+  LAUNCH(launch_finish(c->obs, 1, c->jnl, c->nl.n_atoms > 0 ? 1 : 0, c->kw_d, c->kappaJ, c->cfg.n_orb,
+                       c->cfg.n_k, c->dV, c->volume, c->counter, 1, c->Jtab, c->scalars, c->nanflag,
+                       c->stream),
+         "finish");
+  return enqueue_density_potential<T>(c);
+}
+
+// one kernel per Horner stage, then observables, current, density, potential
+template <typename T>
+tddft_status enqueue_streaming_update(tddft_ctx* c) {
   StageArgs<T> a = stage_args<T>(c);
   a.V = vpot<T>(c);
   void* bufs_in[4] = {c->W, c->U0, c->U1, c->U0};
@@ -387,6 +399,17 @@ tddft_status enqueue_step(tddft_ctx* c) {
   tddft_status st = enqueue_observe<T>(c, 1);
   if (st != TDDFT_OK) return st;
   return enqueue_density_potential<T>(c);
+}
+
+template <typename T>
+tddft_status enqueue_step(tddft_ctx* c) {
+  tddft_status st = enqueue_params(c);
+  if (st != TDDFT_OK) return st;
+  if (c->fused) {
+    LAUNCH(launch_fused<T>(fused_args<T>(c), c->stream), "fused step");
+    return enqueue_fused_tail<T>(c);
+  }
+  return enqueue_streaming_update<T>(c);
 }
 
 tddft_status step_dispatch(tddft_ctx* c) { return c->mixed ? enqueue_step<float>(c) : enqueue_step<double>(c); }
@@ -498,6 +521,48 @@ tddft_status launch_one(tddft_ctx* c, int which) {
                                  c->rho_part, c->stream),
            "rho_partial");
   }
+  return TDDFT_OK;
+}
+
+// validation, table upload and counter reset shared by single-cell and batch runs
+tddft_status prepare_propagate(tddft_ctx* c, int32_t nsteps, const double* A) {
+  if (c->poisoned) return fail(c, TDDFT_ESTATE, "context poisoned: " + c->err);
+  if (!c->potential_set) return fail(c, TDDFT_ESTATE, "propagate before set_potential");
+  if (nsteps < 1 || !A) return fail(c, TDDFT_EINVAL, "bad propagate arguments");
+  double amax = 0;
+  for (size_t i = 0; i < 3 * (size_t)(nsteps + 1); ++i) {
+    if (!std::isfinite(A[i])) return fail(c, TDDFT_EINVAL, "A table not finite");
+    amax = std::max(amax, std::fabs(A[i]));
+  }
+  if (c->cfg.gauge == TDDFT_VELOCITY && !(c->cfg.flags & TDDFT_FLAG_ALLOW_UNSTABLE)) {
+    // the potential part was checked in set_potential; recheck the kinetic part with |A|
+    const double lam = spectral_bound(c, amax, -c->vabs, c->vabs);
+    if (std::fabs(c->cfg.dt) * lam > 2.0 * std::sqrt(2.0))
+      return fail(c, TDDFT_EUNSTABLE, "unstable for this A table: |dt| lambda_max > 2 sqrt 2");
+  }
+  if (nsteps > c->cap_steps) {
+    invalidate_graph(c);
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    int cap = std::max(nsteps, 2 * c->cap_steps);
+    tddft_status st;
+    if ((st = dalloc_t(c, 3 * (size_t)(cap + 1), &c->Atab)) || (st = dalloc_t(c, 3 * (size_t)cap, &c->Jtab)))
+      return st;
+    c->cap_steps = cap;
+  }
+  HIP_TRY(hipMemcpyAsync(c->Atab, A, 3 * sizeof(double) * (nsteps + 1), hipMemcpyHostToDevice, c->stream));
+  LAUNCH(launch_set_int(c->counter, 0, c->stream), "counter reset");
+  return TDDFT_OK;
+}
+
+// J table to the host, NaN check, remember the last A
+tddft_status collect_propagate(tddft_ctx* c, int32_t nsteps, const double* A, double* J_out) {
+  if (J_out)
+    HIP_TRY(hipMemcpyAsync(J_out, c->Jtab, 3 * sizeof(double) * nsteps, hipMemcpyDeviceToHost, c->stream));
+  int flag = 0;
+  HIP_TRY(hipMemcpyAsync(&flag, c->nanflag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  for (int i = 0; i < 3; ++i) c->A_last[i] = A[3 * (size_t)nsteps + i];
+  if (flag) return fail(c, TDDFT_ENUMERIC, "NaN or Inf in the orbital norms or current");
   return TDDFT_OK;
 }
 
@@ -891,37 +956,14 @@ tddft_status tddft_set_potential(tddft_ctx* c, const double* v_loc, int32_t n_at
 
 tddft_status tddft_propagate(tddft_ctx* c, int32_t nsteps, const double* A, double* J_out) {
   if (!c) return TDDFT_EINVAL;
-  if (c->poisoned) return fail(c, TDDFT_ESTATE, "context poisoned: " + c->err);
-  if (!c->potential_set) return fail(c, TDDFT_ESTATE, "propagate before set_potential");
-  if (nsteps < 0 || (nsteps > 0 && !A)) return fail(c, TDDFT_EINVAL, "bad propagate arguments");
-  if (nsteps == 0) return TDDFT_OK;
-  double amax = 0;
-  for (size_t i = 0; i < 3 * (size_t)(nsteps + 1); ++i) {
-    if (!std::isfinite(A[i])) return fail(c, TDDFT_EINVAL, "A table not finite");
-    amax = std::max(amax, std::fabs(A[i]));
-  }
-  if (c->cfg.gauge == TDDFT_VELOCITY && !(c->cfg.flags & TDDFT_FLAG_ALLOW_UNSTABLE)) {
-    // the potential part was checked in set_potential; recheck the kinetic part with |A|
-    const double lam = spectral_bound(c, amax, -c->vabs, c->vabs);
-    if (std::fabs(c->cfg.dt) * lam > 2.0 * std::sqrt(2.0))
-      return fail(c, TDDFT_EUNSTABLE, "unstable for this A table: |dt| lambda_max > 2 sqrt 2");
-  }
-  if (nsteps > c->cap_steps) {
-    invalidate_graph(c);
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    int cap = std::max(nsteps, 2 * c->cap_steps);
-    tddft_status st;
-    if ((st = dalloc_t(c, 3 * (size_t)(cap + 1), &c->Atab)) || (st = dalloc_t(c, 3 * (size_t)cap, &c->Jtab)))
-      return st;
-    c->cap_steps = cap;
-  }
-  HIP_TRY(hipMemcpyAsync(c->Atab, A, 3 * sizeof(double) * (nsteps + 1), hipMemcpyHostToDevice, c->stream));
-  LAUNCH(launch_set_int(c->counter, 0, c->stream), "counter reset");
+  if (nsteps == 0 && !c->poisoned && c->potential_set) return TDDFT_OK;
+  tddft_status st = prepare_propagate(c, nsteps, A);
+  if (st != TDDFT_OK) return st;
   const bool use_graph = !(c->cfg.flags & (TDDFT_FLAG_NO_GRAPH | TDDFT_FLAG_DEBUG_SYNC));
   if (use_graph && !c->graph) {
     hipGraph_t gr;
     HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-    tddft_status st = step_dispatch(c);
+    st = step_dispatch(c);
     hipError_t e = hipStreamEndCapture(c->stream, &gr);
     if (st != TDDFT_OK) return st;
     if (e != hipSuccess) return fail(c, TDDFT_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
@@ -934,21 +976,16 @@ tddft_status tddft_propagate(tddft_ctx* c, int32_t nsteps, const double* A, doub
     if (use_graph) {
       HIP_TRY(hipGraphLaunch(c->graph, c->stream));
     } else {
-      tddft_status st = step_dispatch(c);
+      st = step_dispatch(c);
       if (st != TDDFT_OK) return st;
     }
   }
   HIP_TRY(hipEventRecord(c->ev1, c->stream));
-  if (J_out)
-    HIP_TRY(hipMemcpyAsync(J_out, c->Jtab, 3 * sizeof(double) * nsteps, hipMemcpyDeviceToHost, c->stream));
-  int flag = 0;
-  HIP_TRY(hipMemcpyAsync(&flag, c->nanflag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(hipStreamSynchronize(c->stream));
+  st = collect_propagate(c, nsteps, A, J_out);
+  if (st != TDDFT_OK) return st;
   float ms = 0;
   HIP_TRY(hipEventElapsedTime(&ms, c->ev0, c->ev1));
   c->last_ms = ms / nsteps;
-  for (int i = 0; i < 3; ++i) c->A_last[i] = A[3 * (size_t)nsteps + i];
-  if (flag) return fail(c, TDDFT_ENUMERIC, "NaN or Inf in the orbital norms or current");
   return TDDFT_OK;
 }
 
@@ -1081,6 +1118,421 @@ tddft_status tddft_last_timing(tddft_ctx* c, double* ms) {
   if (!c || !ms) return TDDFT_EINVAL;
   *ms = c->last_ms;
   return TDDFT_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Batches of cells
+
+namespace {
+
+struct BatchGroup {
+  int n = 0;
+  bool periodic = true;
+  std::vector<int> cells;      // cell indices, largest first
+  void* d_args = nullptr;      // FusedArgs<T>[cells.size()]
+  int2* d_items = nullptr;
+  int n_items = 0;
+  int* d_queue = nullptr;
+  size_t lds = 0;
+  int zs = 1, wgs = 0;
+  std::vector<std::pair<int, int>> cand;  // (zs, workgroups)
+  std::vector<double> cand_ms;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+};
+
+}  // namespace
+
+struct tddft_batch {
+  std::vector<tddft_ctx*> cells;
+  std::string err;
+  bool poisoned = false;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  bool mixed = false;
+  uint32_t flags = 0;
+  int n_cu = 256;
+  bool planned = false;
+  int tune_next = 0;           // next candidate index while tuning
+  std::vector<BatchGroup> groups;
+  std::vector<std::vector<int>> lanes;  // per-stage cells per forked stream
+  std::vector<hipStream_t> side;
+  std::vector<hipEvent_t> side_done;
+  hipEvent_t fork = nullptr, ev0 = nullptr, ev1 = nullptr;
+  hipGraphExec_t graph = nullptr;
+  double last_ms = 0;
+  std::vector<void*> allocs;
+};
+
+namespace {
+
+tddft_status bfail(tddft_batch* b, tddft_status st, const std::string& m) {
+  if (b) {
+    b->err = m;
+    if (st == TDDFT_EDEVICE || st == TDDFT_ENUMERIC) b->poisoned = true;
+  }
+  return st;
+}
+
+#define BHIP(expr)                                                                          \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess) return bfail(b, TDDFT_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+tddft_status bcell(tddft_batch* b, tddft_status st, int i) {
+  if (st == TDDFT_OK) return st;
+  return bfail(b, st, "cell " + std::to_string(i) + ": " + b->cells[i]->err);
+}
+
+template <typename T>
+tddft_status batch_plan(tddft_batch* b) {
+  const int nc = (int)b->cells.size();
+  std::vector<int> streaming;
+  for (int i = 0; i < nc; ++i) {
+    tddft_ctx* c = b->cells[i];
+    if (!c->fused) {
+      streaming.push_back(i);
+      continue;
+    }
+    BatchGroup* g = nullptr;
+    for (auto& gg : b->groups)
+      if (gg.n == c->g.n3 && gg.periodic == (c->g.periodic != 0)) g = &gg;
+    if (!g) {
+      b->groups.emplace_back();
+      g = &b->groups.back();
+      g->n = c->g.n3;
+      g->periodic = c->g.periodic != 0;
+    }
+    g->cells.push_back(i);
+  }
+  // work of one orbital item: grid points plus sphere entries (nonlocal part)
+  auto cost = [&](int i) { return (double)b->cells[i]->N + 4.0 * b->cells[i]->nl.n_ent; };
+  for (auto& g : b->groups) {
+    std::stable_sort(g.cells.begin(), g.cells.end(), [&](int x, int y) { return cost(x) > cost(y); });
+    std::vector<FusedArgs<T>> args;
+    std::vector<int2> items;
+    for (size_t j = 0; j < g.cells.size(); ++j) {
+      tddft_ctx* c = b->cells[g.cells[j]];
+      args.push_back(fused_args<T>(c));
+      g.lds = std::max(g.lds, fused_lds_bytes(c->g, c->nl.n_atoms, sizeof(typename Vec2<T>::type)));
+      for (size_t o = 0; o < c->n_orb_tot; ++o) items.push_back(make_int2((int)j, (int)o));
+    }
+    g.n_items = (int)items.size();
+    void* p;
+    BHIP(hipMalloc(&p, args.size() * sizeof(FusedArgs<T>)));
+    b->allocs.push_back(p);
+    g.d_args = p;
+    BHIP(hipMalloc(&p, items.size() * sizeof(int2)));
+    b->allocs.push_back(p);
+    g.d_items = static_cast<int2*>(p);
+    BHIP(hipMalloc(&p, sizeof(int)));
+    b->allocs.push_back(p);
+    g.d_queue = static_cast<int*>(p);
+    BHIP(hipMemcpyAsync(g.d_args, args.data(), args.size() * sizeof(FusedArgs<T>), hipMemcpyHostToDevice, b->stream));
+    BHIP(hipMemcpyAsync(g.d_items, items.data(), items.size() * sizeof(int2), hipMemcpyHostToDevice, b->stream));
+    // the tuner only sizes the persistent grid: the column split is fixed per
+    // grid size, so no tuning decision changes a single bit of the result
+    g.zs = fused_column_split(g.n);
+    for (int per_cu : {1, 2, 3, 4}) g.cand.push_back({g.zs, per_cu * b->n_cu});
+    g.wgs = b->n_cu;
+    BHIP(hipEventCreate(&g.e0));
+    BHIP(hipEventCreate(&g.e1));
+  }
+  // per-stage cells: longest-processing-time-first over up to four streams
+  const int L = std::min<int>(4, (int)streaming.size());
+  b->lanes.assign(L, {});
+  std::vector<double> load(L, 0.0);
+  std::stable_sort(streaming.begin(), streaming.end(), [&](int x, int y) {
+    return (double)b->cells[x]->N * b->cells[x]->n_orb_tot > (double)b->cells[y]->N * b->cells[y]->n_orb_tot;
+  });
+  for (int i : streaming) {
+    const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    b->lanes[l].push_back(i);
+    load[l] += (double)b->cells[i]->N * b->cells[i]->n_orb_tot;
+  }
+  const int nside = (int)b->groups.size() + L;
+  for (int i = 0; i < nside; ++i) {
+    hipStream_t s;
+    hipEvent_t e;
+    BHIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    BHIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    b->side.push_back(s);
+    b->side_done.push_back(e);
+  }
+  BHIP(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
+  BHIP(hipStreamSynchronize(b->stream));
+  b->planned = true;
+  b->tune_next = (b->flags & TDDFT_FLAG_NO_TUNE) ? -1 : -2;  // -2: one unrecorded warm-up step first
+  return TDDFT_OK;
+}
+
+// One batch step. timing: bracket each group's persistent launch with events.
+template <typename T>
+tddft_status batch_step(tddft_batch* b, bool timing) {
+  for (size_t i = 0; i < b->cells.size(); ++i) {
+    tddft_ctx* c = b->cells[i];
+    c->stream = b->stream;
+    tddft_status st = enqueue_params(c);
+    if (st != TDDFT_OK) return bcell(b, st, (int)i);
+  }
+  BHIP(hipEventRecord(b->fork, b->stream));
+  int si = 0;
+  for (auto& g : b->groups) {
+    hipStream_t s = b->side[si];
+    BHIP(hipStreamWaitEvent(s, b->fork, 0));
+    BHIP(launch_set_int(g.d_queue, 0, s));
+    if (timing) BHIP(hipEventRecord(g.e0, s));
+    BHIP(launch_fused_persistent<T>(g.n, g.zs, g.periodic, static_cast<const FusedArgs<T>*>(g.d_args), g.d_items,
+                                    g.n_items, g.d_queue, g.wgs, g.lds, s));
+    if (timing) BHIP(hipEventRecord(g.e1, s));
+    for (int i : g.cells) {
+      tddft_ctx* c = b->cells[i];
+      c->stream = s;
+      tddft_status st = enqueue_fused_tail<T>(c);
+      c->stream = b->stream;
+      if (st != TDDFT_OK) return bcell(b, st, i);
+    }
+    BHIP(hipEventRecord(b->side_done[si], s));
+    ++si;
+  }
+  for (auto& lane : b->lanes) {
+    hipStream_t s = b->side[si];
+    BHIP(hipStreamWaitEvent(s, b->fork, 0));
+    for (int i : lane) {
+      tddft_ctx* c = b->cells[i];
+      c->stream = s;
+      tddft_status st = enqueue_streaming_update<T>(c);
+      c->stream = b->stream;
+      if (st != TDDFT_OK) return bcell(b, st, i);
+    }
+    BHIP(hipEventRecord(b->side_done[si], s));
+    ++si;
+  }
+  for (int i = 0; i < si; ++i) BHIP(hipStreamWaitEvent(b->stream, b->side_done[i], 0));
+  return TDDFT_OK;
+}
+
+template <typename T>
+tddft_status batch_propagate(tddft_batch* b, int32_t nsteps) {
+  if (!b->planned) {
+    tddft_status st = batch_plan<T>(b);
+    if (st != TDDFT_OK) return st;
+  }
+  int done = 0;
+  if (b->tune_next == -2) {  // warm-up step (first launches load code objects)
+    tddft_status st = batch_step<T>(b, false);
+    if (st != TDDFT_OK) return st;
+    b->tune_next = 0;
+    ++done;
+  }
+  // online tuning: each candidate runs one real step (identical results)
+  while (b->tune_next >= 0 && done < nsteps) {
+    size_t maxc = 0;
+    for (auto& g : b->groups) maxc = std::max(maxc, g.cand.size());
+    if ((size_t)b->tune_next >= maxc) {
+      for (auto& g : b->groups) {
+        size_t best = 0;
+        for (size_t i = 1; i < g.cand_ms.size(); ++i)
+          if (g.cand_ms[i] < g.cand_ms[best]) best = i;
+        if (!g.cand_ms.empty()) {
+          g.zs = g.cand[best].first;
+          g.wgs = g.cand[best].second;
+        }
+      }
+      b->tune_next = -1;
+      break;
+    }
+    for (auto& g : b->groups) {
+      const size_t ci = std::min((size_t)b->tune_next, g.cand.size() - 1);
+      g.zs = g.cand[ci].first;
+      g.wgs = g.cand[ci].second;
+    }
+    tddft_status st = batch_step<T>(b, true);
+    if (st != TDDFT_OK) return st;
+    BHIP(hipStreamSynchronize(b->stream));
+    for (auto& g : b->groups) {
+      if ((size_t)b->tune_next < g.cand.size()) {
+        float ms = 0;
+        BHIP(hipEventElapsedTime(&ms, g.e0, g.e1));
+        g.cand_ms.push_back(ms);
+      }
+    }
+    ++b->tune_next;
+    ++done;
+  }
+  if (done >= nsteps) return TDDFT_OK;
+  const bool use_graph = !(b->flags & (TDDFT_FLAG_NO_GRAPH | TDDFT_FLAG_DEBUG_SYNC));
+  if (use_graph && !b->graph) {
+    hipGraph_t gr;
+    BHIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    tddft_status st = batch_step<T>(b, false);
+    hipError_t e = hipStreamEndCapture(b->stream, &gr);
+    if (st != TDDFT_OK) return st;
+    if (e != hipSuccess) return bfail(b, TDDFT_EDEVICE, std::string("batch graph capture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&b->graph, gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
+    if (e != hipSuccess) return bfail(b, TDDFT_EDEVICE, std::string("batch graph: ") + hipGetErrorString(e));
+  }
+  BHIP(hipEventRecord(b->ev0, b->stream));
+  for (int n = done; n < nsteps; ++n) {
+    if (use_graph) {
+      BHIP(hipGraphLaunch(b->graph, b->stream));
+    } else {
+      tddft_status st = batch_step<T>(b, false);
+      if (st != TDDFT_OK) return st;
+    }
+  }
+  BHIP(hipEventRecord(b->ev1, b->stream));
+  BHIP(hipStreamSynchronize(b->stream));
+  float ms = 0;
+  BHIP(hipEventElapsedTime(&ms, b->ev0, b->ev1));
+  b->last_ms = ms / (nsteps - done);
+  return TDDFT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tddft_status tddft_batch_create(int32_t n_cells, const tddft_config* cfgs, const double* const* psi0,
+                                tddft_batch** out) {
+  if (!out) return TDDFT_EINVAL;
+  *out = nullptr;
+  if (n_cells < 1 || !cfgs || !psi0) return TDDFT_EINVAL;
+  auto* b = new tddft_batch();
+  b->mixed = cfgs[0].precision == TDDFT_MIXED;
+  b->flags = cfgs[0].flags;
+  if (cfgs[0].stream) {
+    b->stream = static_cast<hipStream_t>(cfgs[0].stream);
+  } else if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
+    delete b;
+    return TDDFT_EDEVICE;
+  } else {
+    b->own_stream = true;
+  }
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&b->n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+  for (int i = 0; i < n_cells; ++i) {
+    tddft_config cf = cfgs[i];
+    cf.precision = cfgs[0].precision;
+    cf.stream = b->stream;
+    cf.flags = cfgs[0].flags;
+    tddft_ctx* c = nullptr;
+    tddft_status st = tddft_init(&cf, psi0[i], &c);
+    if (st != TDDFT_OK) {
+      tddft_batch_free(b);
+      return st;
+    }
+    b->cells.push_back(c);
+  }
+  if (hipEventCreate(&b->ev0) != hipSuccess || hipEventCreate(&b->ev1) != hipSuccess) {
+    tddft_batch_free(b);
+    return TDDFT_EDEVICE;
+  }
+  *out = b;
+  return TDDFT_OK;
+}
+
+tddft_status tddft_batch_set_potential(tddft_batch* b, int32_t cell, const double* v_loc, int32_t n_atoms,
+                                       const tddft_atom* atoms) {
+  if (!b) return TDDFT_EINVAL;
+  if (b->poisoned) return bfail(b, TDDFT_ESTATE, "batch poisoned: " + b->err);
+  if (cell < 0 || cell >= (int)b->cells.size()) return bfail(b, TDDFT_EINVAL, "cell out of range");
+  if (b->planned) return bfail(b, TDDFT_ESTATE, "potentials are fixed once the batch has propagated");
+  return bcell(b, tddft_set_potential(b->cells[cell], v_loc, n_atoms, atoms), cell);
+}
+
+tddft_status tddft_batch_propagate(tddft_batch* b, int32_t nsteps, const double* const* A, double* const* J_out) {
+  if (!b) return TDDFT_EINVAL;
+  if (b->poisoned) return bfail(b, TDDFT_ESTATE, "batch poisoned: " + b->err);
+  if (nsteps < 0 || (nsteps > 0 && !A)) return bfail(b, TDDFT_EINVAL, "bad propagate arguments");
+  if (nsteps == 0) return TDDFT_OK;
+  for (size_t i = 0; i < b->cells.size(); ++i) {
+    tddft_ctx* c = b->cells[i];
+    c->stream = b->stream;
+    const bool had = c->cap_steps >= nsteps;
+    tddft_status st = prepare_propagate(c, nsteps, A[i]);
+    if (st != TDDFT_OK) return bcell(b, st, (int)i);
+    if (!had && b->graph) {  // a cell's A/J tables moved: the captured step must be rebuilt
+      (void)hipGraphExecDestroy(b->graph);
+      b->graph = nullptr;
+    }
+  }
+  tddft_status st = b->mixed ? batch_propagate<float>(b, nsteps) : batch_propagate<double>(b, nsteps);
+  if (st != TDDFT_OK) return st;
+  for (size_t i = 0; i < b->cells.size(); ++i) {
+    tddft_ctx* c = b->cells[i];
+    st = collect_propagate(c, nsteps, A[i], J_out ? J_out[i] : nullptr);
+    if (st != TDDFT_OK) return bcell(b, st, (int)i);
+    c->last_ms = b->last_ms;
+  }
+  return TDDFT_OK;
+}
+
+tddft_ctx* tddft_batch_cell(tddft_batch* b, int32_t cell) {
+  if (!b || cell < 0 || cell >= (int)b->cells.size()) return nullptr;
+  return b->cells[cell];
+}
+
+tddft_status tddft_batch_last_timing(tddft_batch* b, double* ms) {
+  if (!b || !ms) return TDDFT_EINVAL;
+  *ms = b->last_ms;
+  return TDDFT_OK;
+}
+
+tddft_status tddft_batch_report(tddft_batch* b, char* buf, size_t len) {
+  if (!b || !buf || len == 0) return TDDFT_EINVAL;
+  std::string r = "{\"groups\": [";
+  for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+    const auto& g = b->groups[gi];
+    char tmp[256];
+    std::snprintf(tmp, sizeof tmp, "%s{\"n\": %d, \"cells\": %zu, \"items\": %d, \"zs\": %d, \"workgroups\": %d, \"tuned_ms\": [",
+                  gi ? ", " : "", g.n, g.cells.size(), g.n_items, g.zs, g.wgs);
+    r += tmp;
+    for (size_t i = 0; i < g.cand_ms.size(); ++i) {
+      std::snprintf(tmp, sizeof tmp, "%s[%d, %d, %.4f]", i ? ", " : "", g.cand[i].first, g.cand[i].second,
+                    g.cand_ms[i]);
+      r += tmp;
+    }
+    r += "]}";
+  }
+  r += "], \"per_stage_cells\": [";
+  bool first = true;
+  for (const auto& lane : b->lanes)
+    for (int i : lane) {
+      r += (first ? "" : ", ") + std::to_string(i);
+      first = false;
+    }
+  r += "]}";
+  std::snprintf(buf, len, "%s", r.c_str());
+  return r.size() < len ? TDDFT_OK : TDDFT_EINVAL;
+}
+
+const char* tddft_batch_last_error(const tddft_batch* b) { return b ? b->err.c_str() : "null batch"; }
+
+void tddft_batch_free(tddft_batch* b) {
+  if (!b) return;
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  if (b->graph) (void)hipGraphExecDestroy(b->graph);
+  for (auto* c : b->cells) {
+    c->stream = b->stream;
+    tddft_free(c);
+  }
+  for (auto& g : b->groups) {
+    if (g.e0) (void)hipEventDestroy(g.e0);
+    if (g.e1) (void)hipEventDestroy(g.e1);
+  }
+  for (auto s : b->side) (void)hipStreamDestroy(s);
+  for (auto e : b->side_done) (void)hipEventDestroy(e);
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  if (b->ev0) (void)hipEventDestroy(b->ev0);
+  if (b->ev1) (void)hipEventDestroy(b->ev1);
+  for (void* p : b->allocs) (void)hipFree(p);
+  if (b->own_stream) (void)hipStreamDestroy(b->stream);
+  delete b;
 }
 
 }  // extern "C"

@@ -129,6 +129,11 @@ hipError_t launch_project(const ProjArgs<T>& a, hipStream_t s);
 template <typename T>
 hipError_t launch_fused(const FusedArgs<T>& a, hipStream_t s);
 bool fused_supported(const Geometry& g, int n_atoms, size_t elem);
+size_t fused_lds_bytes(const Geometry& g, int n_atoms, size_t elem);
+int fused_column_split(int n);
+template <typename T>
+hipError_t launch_fused_persistent(int n, int zs, bool periodic, const FusedArgs<T>* cells, const int2* items,
+                                   int n_items, int* queue, int wgs, size_t lds, hipStream_t s);
 
 hipError_t launch_step_params(const double* A, const int* counter, int use_counter,
                               const double* kpt, int n_k, const double* ent_x, int S, int gauge,

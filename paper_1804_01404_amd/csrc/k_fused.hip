@@ -1,18 +1,20 @@
 // Whole time step of one orbital with the orbital resident in LDS.
 //
-// For cells whose orbital fits in LDS (n1 n2 <= 512, n3 in {12, 16, 20},
+// For cubic cells whose orbital fits in LDS (n = 12, 16 or 20 per axis,
 // N * sizeof(complex) + tables <= 160 KB), one workgroup owns one orbital and
 // runs all four Horner stages u_{s-1} = w + (-i dt / s) h u_s, s = 4..1
 // (Program Summary: fourth-order truncated Taylor expansion; Sec. 4.1,
 // Eq. TDKS_solid for h), with
-//   * u_s in LDS, w and u_{s-1} in registers (thread = one (x, y) column);
+//   * u_s in LDS; w and u_{s-1} in registers. A thread owns one (x, y)
+//     column, or one half of it (ZS = 2: the two halves sit in different
+//     wavefronts, which halves the register arrays and doubles the waves);
 //   * the Kleinman-Bylander projections u_p = <beta_p^kappa|u_s> of every atom
 //     formed in the workgroup before each stage (one wavefront per atom,
 //     fixed-order shuffle reductions, FP64) and added back by a scatter over
 //     each atom's sphere into the LDS copy (atoms coloured so that spheres of
 //     one colour are disjoint: no atomics, a fixed summation order);
 //   * after the last stage: w_new written once, then the observables of
-//     w_new (norm, momentum, kinetic and local sums, FP64 accumulation) and
+//     w_new that the current needs (norm and momentum, FP64 accumulation) and
 //     the moment projections for the nonlocal current at t_{n+1}.
 // HBM traffic per orbital point and step: read w once, write w_new once.
 #include "internal.h"
@@ -25,74 +27,186 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-template <typename T, int N3, bool PERIODIC, int MAXT>
-__global__ __launch_bounds__(MAXT) void k_fused(FusedArgs<T> a) {
+// in-plane neighbour offsets of one column (periodic wrap) and its own offset
+struct Nbr {
+  int xp[4], xm[4], yp[4], ym[4];
+  int c;
+};
+
+template <typename T>
+struct Coef {
+  T cx[4], cy[4], cz[4], bx[4], by[4], bz[4];
+  T diag, ext, ez;
+};
+
+// A copy of the offsets that the compiler cannot see through: rebuilding the
+// addresses per stage keeps the unrolled column loop from holding every one
+// of them live across the stage loop.
+__device__ __forceinline__ Nbr opaque(const Nbr& n) {
+  Nbr r = n;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) asm volatile("" : "+v"(r.xp[m]), "+v"(r.xm[m]), "+v"(r.yp[m]), "+v"(r.ym[m]));
+  asm volatile("" : "+v"(r.c));
+  return r;
+}
+
+template <typename T, bool PERIODIC>
+__device__ __forceinline__ typename Vec2<T>::type lds_xy(const typename Vec2<T>::type* pl, int off, bool valid) {
+  typename Vec2<T>::type v = pl[off];
+  if (!PERIODIC && !valid) v.x = v.y = 0;
+  return v;
+}
+
+// h u_s (local part) and the Horner update for the planes Z0 .. Z0 + ZN - 1
+template <typename T, int N, int ZN, int Z0, bool PERIODIC>
+__device__ __forceinline__ void stencil_part(const typename Vec2<T>::type* u, const T* __restrict__ V,
+                                             const Coef<T>& cf, const Nbr& nb, const bool (&ok)[16],
+                                             const typename Vec2<T>::type (&w)[ZN],
+                                             typename Vec2<T>::type (&un)[ZN], T tau, bool length) {
   using T2 = typename Vec2<T>::type;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  const Geometry& g = a.g;
-  const int n1 = g.n1, n2 = g.n2;
-  const int plane = n1 * n2;
-  const int N = plane * N3;
+  constexpr int plane = N * N;
+#pragma unroll
+  for (int zz = 0; zz < ZN; ++zz) {
+    const int z = Z0 + zz;
+    const T2* pl = u + z * plane;
+    const T2 c = pl[nb.c];
+    T dg = cf.diag + V[z * plane + nb.c];
+    if (length) dg += cf.ext + cf.ez * ((T)z - (T)(0.5 * (N - 1)));
+    T hr = dg * c.x, hi = dg * c.y;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      T2 p = lds_xy<T, PERIODIC>(pl, nb.xp[m], ok[m]);
+      T2 n = lds_xy<T, PERIODIC>(pl, nb.xm[m], ok[4 + m]);
+      hr += cf.cx[m] * (p.x + n.x) + cf.bx[m] * (p.y - n.y);
+      hi += cf.cx[m] * (p.y + n.y) - cf.bx[m] * (p.x - n.x);
+      p = lds_xy<T, PERIODIC>(pl, nb.yp[m], ok[8 + m]);
+      n = lds_xy<T, PERIODIC>(pl, nb.ym[m], ok[12 + m]);
+      hr += cf.cy[m] * (p.x + n.x) + cf.by[m] * (p.y - n.y);
+      hi += cf.cy[m] * (p.y + n.y) - cf.by[m] * (p.x - n.x);
+      const int zp = z + m + 1, zm = z - m - 1;
+      T2 q, r;
+      q.x = q.y = r.x = r.y = 0;
+      if (PERIODIC || zp < N) q = u[(zp % N) * plane + nb.c];
+      if (PERIODIC || zm >= 0) r = u[((zm + N) % N) * plane + nb.c];
+      hr += cf.cz[m] * (q.x + r.x) + cf.bz[m] * (q.y - r.y);
+      hi += cf.cz[m] * (q.y + r.y) - cf.bz[m] * (q.x - r.x);
+    }
+    un[zz].x = w[zz].x + tau * hi;
+    un[zz].y = w[zz].y - tau * hr;
+  }
+}
+
+// norm and momentum sums of w_new for the planes Z0 .. Z0 + ZN - 1: the
+// differences in the stage precision, products and sums in FP64
+template <typename T, int N, int ZN, int Z0, bool PERIODIC>
+__device__ __forceinline__ void observe_part(const typename Vec2<T>::type* u, const double (&dh)[3][4],
+                                             const Nbr& nb, const bool (&ok)[16], double (&sv)[4]) {
+  using T2 = typename Vec2<T>::type;
+  constexpr int plane = N * N;
+#pragma unroll
+  for (int zz = 0; zz < ZN; ++zz) {
+    const int z = Z0 + zz;
+    const T2* pl = u + z * plane;
+    const T2 cv = pl[nb.c];
+    T dxr = 0, dxi = 0, dyr = 0, dyi = 0, dzr = 0, dzi = 0;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const T d0 = (T)dh[0][m], d1 = (T)dh[1][m], d2 = (T)dh[2][m];
+      T2 p = lds_xy<T, PERIODIC>(pl, nb.xp[m], ok[m]);
+      T2 n = lds_xy<T, PERIODIC>(pl, nb.xm[m], ok[4 + m]);
+      dxr += d0 * (p.x - n.x);
+      dxi += d0 * (p.y - n.y);
+      p = lds_xy<T, PERIODIC>(pl, nb.yp[m], ok[8 + m]);
+      n = lds_xy<T, PERIODIC>(pl, nb.ym[m], ok[12 + m]);
+      dyr += d1 * (p.x - n.x);
+      dyi += d1 * (p.y - n.y);
+      const int zp = z + m + 1, zm = z - m - 1;
+      T2 q, r;
+      q.x = q.y = r.x = r.y = 0;
+      if (PERIODIC || zp < N) q = u[(zp % N) * plane + nb.c];
+      if (PERIODIC || zm >= 0) r = u[((zm + N) % N) * plane + nb.c];
+      dzr += d2 * (q.x - r.x);
+      dzi += d2 * (q.y - r.y);
+    }
+    const double cr = (double)cv.x, ci = (double)cv.y;
+    sv[0] += cr * cr + ci * ci;
+    sv[1] += cr * (double)dxi - ci * (double)dxr;
+    sv[2] += cr * (double)dyi - ci * (double)dyr;
+    sv[3] += cr * (double)dzi - ci * (double)dzr;
+  }
+}
+
+template <typename T, int N, int ZS, bool PERIODIC>
+__device__ __forceinline__ void fused_body(const FusedArgs<T>& a, const int o, unsigned char* smem_raw) {
+  using T2 = typename Vec2<T>::type;
+  constexpr int plane = N * N;
+  constexpr int NP = plane * N;
+  constexpr int ZN = N / ZS;                      // planes per thread
+  constexpr int HALF = ((plane + 63) / 64) * 64;  // threads per column half (whole waves)
   const int n_atoms = a.nl.n_atoms;
   const int S = a.nl.n_ent;
   T2* u = reinterpret_cast<T2*>(smem_raw);
-  const size_t ubytes = ((size_t)N * sizeof(T2) + 15) & ~(size_t)15;
-  double2* eu = reinterpret_cast<double2*>(smem_raw + ubytes);            // [n_atoms][4]
+  constexpr size_t ubytes = ((size_t)NP * sizeof(T2) + 15) & ~(size_t)15;
+  double2* eu = reinterpret_cast<double2*>(smem_raw + ubytes);               // [n_atoms][4]
   double* red = reinterpret_cast<double*>(eu + (size_t)n_atoms * kMaxProj);  // [16][8]
+  double* ja = red + 16 * 8;                                                 // [n_atoms][4]
 
-  const int o = blockIdx.x;
-  const int k = o / g.n_orb;
+  const int k = o / a.g.n_orb;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6, nwaves = blockDim.x >> 6;
-  const int tx = tid % n1, ty = tid / n1;
-  const bool active = ty < n2;
-  const int col = active ? ty * n1 + tx : 0;
+  const int half = (ZS == 2 && tid >= HALF) ? 1 : 0;  // uniform per wavefront
+  const int ctid = tid - half * HALF;
+  const int tx = ctid % N, ty = ctid / N;
+  const bool active = ctid < plane;
 
-  // in-plane neighbour offsets (periodic wrap) and validity (isolated)
-  int oxp[4], oxm[4], oyp[4], oym[4];
-  bool vxp[4], vxm[4], vyp[4], vym[4];
+  Nbr nb;
+  bool ok[16];
 #pragma unroll
   for (int m = 1; m <= 4; ++m) {
     const int xp = tx + m, xm = tx - m, yp = ty + m, ym = ty - m;
-    vxp[m - 1] = PERIODIC || xp < n1;
-    vxm[m - 1] = PERIODIC || xm >= 0;
-    vyp[m - 1] = PERIODIC || yp < n2;
-    vym[m - 1] = PERIODIC || ym >= 0;
-    oxp[m - 1] = ty * n1 + (xp % n1);
-    oxm[m - 1] = ty * n1 + ((xm + n1) % n1);
-    oyp[m - 1] = (yp % n2) * n1 + tx;
-    oym[m - 1] = ((ym + n2) % n2) * n1 + tx;
+    ok[m - 1] = PERIODIC || xp < N;
+    ok[4 + m - 1] = PERIODIC || xm >= 0;
+    ok[8 + m - 1] = PERIODIC || yp < N;
+    ok[12 + m - 1] = PERIODIC || ym >= 0;
+    nb.xp[m - 1] = ty * N + (xp % N);
+    nb.xm[m - 1] = ty * N + ((xm + N) % N);
+    nb.yp[m - 1] = (yp % N) * N + tx;
+    nb.ym[m - 1] = ((ym + N) % N) * N + tx;
   }
+  nb.c = active ? ctid : 0;
 
-  T2* __restrict__ wg = a.w + (size_t)o * N;
-  T2 w[N3], un[N3];
+  T2* __restrict__ wg = a.w + (size_t)o * NP;
+  T2 w[ZN], un[ZN];
+  const int z0 = half * ZN;
 #pragma unroll
-  for (int z = 0; z < N3; ++z) {
+  for (int zz = 0; zz < ZN; ++zz) {
     T2 v;
-    v.x = 0;
-    v.y = 0;
-    if (active) v = wg[z * plane + col];
-    w[z] = v;
-    if (active) u[z * plane + col] = v;
+    v.x = v.y = 0;
+    if (active) v = wg[(z0 + zz) * plane + nb.c];
+    w[zz] = v;
+    if (active) u[(z0 + zz) * plane + nb.c] = v;
   }
 
-  const double kx = a.kappa[3 * k], ky = a.kappa[3 * k + 1], kz = a.kappa[3 * k + 2];
-  T cx[4], cy[4], cz[4], bx[4], by[4], bz[4];
+  Coef<T> cf;
+  {
+    const double kx = a.kappa[3 * k], ky = a.kappa[3 * k + 1], kz = a.kappa[3 * k + 2];
 #pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    cx[m] = (T)a.lap[0][m + 1];
-    cy[m] = (T)a.lap[1][m + 1];
-    cz[m] = (T)a.lap[2][m + 1];
-    bx[m] = (T)(kx * a.dh[0][m]);
-    by[m] = (T)(ky * a.dh[1][m]);
-    bz[m] = (T)(kz * a.dh[2][m]);
+    for (int m = 0; m < 4; ++m) {
+      cf.cx[m] = (T)a.lap[0][m + 1];
+      cf.cy[m] = (T)a.lap[1][m + 1];
+      cf.cz[m] = (T)a.lap[2][m + 1];
+      cf.bx[m] = (T)(kx * a.dh[0][m]);
+      cf.by[m] = (T)(ky * a.dh[1][m]);
+      cf.bz[m] = (T)(kz * a.dh[2][m]);
+    }
+    cf.diag = (T)(a.cdiag + 0.5 * (kx * kx + ky * ky + kz * kz));
+    cf.ext = cf.ez = 0;
+    if (a.efield) {
+      cf.ext = (T)(a.efield[0] * (tx - 0.5 * (N - 1)) * a.g.h1 + a.efield[1] * (ty - 0.5 * (N - 1)) * a.g.h2);
+      cf.ez = (T)(a.efield[2] * a.g.h3);
+    }
   }
-  const T diag = (T)(a.cdiag + 0.5 * (kx * kx + ky * ky + kz * kz));
-  T ext = 0, ez = 0;
-  if (a.efield) {
-    ext = (T)(a.efield[0] * (tx - 0.5 * (n1 - 1)) * g.h1 + a.efield[1] * (ty - 0.5 * (n2 - 1)) * g.h2);
-    ez = (T)(a.efield[2] * g.h3);
-  }
+  const bool length = a.efield != nullptr;
   const double2* __restrict__ phk = a.nl.phk + (size_t)k * S;
   __syncthreads();
 
@@ -132,61 +246,21 @@ __global__ __launch_bounds__(MAXT) void k_fused(FusedArgs<T> a) {
       }
       __syncthreads();
     }
-    // ---- h u_s and the Horner update, column by column. The LDS offsets are
-    // re-materialised per stage so that the compiler does not keep every
-    // address of the unrolled column loop live across the stage loop.
+    // ---- local part of h u_s and the Horner update
     const T tau = (T)(a.dt / s);
-    int sxp[4], sxm[4], syp[4], sym[4], scol = col;
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      sxp[m] = oxp[m];
-      sxm[m] = oxm[m];
-      syp[m] = oyp[m];
-      sym[m] = oym[m];
-      asm volatile("" : "+v"(sxp[m]), "+v"(sxm[m]), "+v"(syp[m]), "+v"(sym[m]));
-    }
-    asm volatile("" : "+v"(scol));
-    if (active) {
-#pragma unroll
-      for (int z = 0; z < N3; ++z) {
-        const T2* pl = u + z * plane;
-        const T2 c = pl[scol];
-        T dg = diag + a.V[z * plane + scol];
-        if (a.efield) dg += ext + ez * ((T)z - (T)(0.5 * (N3 - 1)));
-        T hr = dg * c.x, hi = dg * c.y;
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          T2 p = pl[sxp[m]], n = pl[sxm[m]];
-          if (!PERIODIC) {
-            if (!vxp[m]) p.x = p.y = 0;
-            if (!vxm[m]) n.x = n.y = 0;
-          }
-          hr += cx[m] * (p.x + n.x) + bx[m] * (p.y - n.y);
-          hi += cx[m] * (p.y + n.y) - bx[m] * (p.x - n.x);
-          p = pl[syp[m]];
-          n = pl[sym[m]];
-          if (!PERIODIC) {
-            if (!vyp[m]) p.x = p.y = 0;
-            if (!vym[m]) n.x = n.y = 0;
-          }
-          hr += cy[m] * (p.x + n.x) + by[m] * (p.y - n.y);
-          hi += cy[m] * (p.y + n.y) - by[m] * (p.x - n.x);
-          const int zp = z + m + 1, zm = z - m - 1;
-          T2 q, r;
-          q.x = q.y = r.x = r.y = 0;
-          if (PERIODIC || zp < N3) q = u[((zp) % N3) * plane + scol];
-          if (PERIODIC || zm >= 0) r = u[((zm + N3) % N3) * plane + scol];
-          hr += cz[m] * (q.x + r.x) + bz[m] * (q.y - r.y);
-          hi += cz[m] * (q.y + r.y) - bz[m] * (q.x - r.x);
-        }
-        un[z].x = w[z].x + tau * hi;
-        un[z].y = w[z].y - tau * hr;
+    {
+      const Nbr sb = opaque(nb);
+      if (active) {
+        if (ZS == 1 || half == 0)
+          stencil_part<T, N, ZN, 0, PERIODIC>(u, a.V, cf, sb, ok, w, un, tau, length);
+        else
+          stencil_part<T, N, ZN, (ZS == 2 ? ZN : 0), PERIODIC>(u, a.V, cf, sb, ok, w, un, tau, length);
       }
     }
     __syncthreads();
     if (active) {
 #pragma unroll
-      for (int z = 0; z < N3; ++z) u[z * plane + col] = un[z];
+      for (int zz = 0; zz < ZN; ++zz) u[(z0 + zz) * plane + nb.c] = un[zz];
     }
     __syncthreads();
     // ---- nonlocal part of the stage, scattered over each atom's sphere:
@@ -224,150 +298,145 @@ __global__ __launch_bounds__(MAXT) void k_fused(FusedArgs<T> a) {
     }
   }
 
-  // ---- w_new to HBM
-  if (active) {
+  // ---- w_new to HBM, observables for the current
+  double sv[4] = {0, 0, 0, 0};
+  {
+    const Nbr fb = opaque(nb);
+    if (active) {
 #pragma unroll
-    for (int z = 0; z < N3; ++z) wg[z * plane + col] = u[z * plane + col];
-  }
-
-  // ---- observables of w_new (FP64): norm, p_x, p_y, p_z, kin, vloc
-  double sv[6] = {0, 0, 0, 0, 0, 0};
-  if (active) {
-#pragma unroll
-    for (int z = 0; z < N3; ++z) {
-      const T2* pl = u + z * plane;
-      const T2 cv = pl[col];
-      const double cr = (double)cv.x, ci = (double)cv.y;
-      double lr = a.cdiag * cr, li = a.cdiag * ci;
-      double dxr = 0, dxi = 0, dyr = 0, dyi = 0, dzr = 0, dzi = 0;
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        T2 p = pl[oxp[m]], n = pl[oxm[m]];
-        if (!PERIODIC) {
-          if (!vxp[m]) p.x = p.y = 0;
-          if (!vxm[m]) n.x = n.y = 0;
-        }
-        lr += a.lap[0][m + 1] * ((double)p.x + (double)n.x);
-        li += a.lap[0][m + 1] * ((double)p.y + (double)n.y);
-        dxr += a.dh[0][m] * ((double)p.x - (double)n.x);
-        dxi += a.dh[0][m] * ((double)p.y - (double)n.y);
-        p = pl[oyp[m]];
-        n = pl[oym[m]];
-        if (!PERIODIC) {
-          if (!vyp[m]) p.x = p.y = 0;
-          if (!vym[m]) n.x = n.y = 0;
-        }
-        lr += a.lap[1][m + 1] * ((double)p.x + (double)n.x);
-        li += a.lap[1][m + 1] * ((double)p.y + (double)n.y);
-        dyr += a.dh[1][m] * ((double)p.x - (double)n.x);
-        dyi += a.dh[1][m] * ((double)p.y - (double)n.y);
-        const int zp = z + m + 1, zm = z - m - 1;
-        T2 q, r;
-        q.x = q.y = r.x = r.y = 0;
-        if (PERIODIC || zp < N3) q = u[((zp) % N3) * plane + col];
-        if (PERIODIC || zm >= 0) r = u[((zm + N3) % N3) * plane + col];
-        lr += a.lap[2][m + 1] * ((double)q.x + (double)r.x);
-        li += a.lap[2][m + 1] * ((double)q.y + (double)r.y);
-        dzr += a.dh[2][m] * ((double)q.x - (double)r.x);
-        dzi += a.dh[2][m] * ((double)q.y - (double)r.y);
-      }
-      const double nn = cr * cr + ci * ci;
-      sv[0] += nn;
-      sv[1] += cr * dxi - ci * dxr;
-      sv[2] += cr * dyi - ci * dyr;
-      sv[3] += cr * dzi - ci * dzr;
-      sv[4] += cr * lr + ci * li;
-      sv[5] += a.Vloc[z * plane + col] * nn;
+      for (int zz = 0; zz < ZN; ++zz) wg[(z0 + zz) * plane + fb.c] = u[(z0 + zz) * plane + fb.c];
+      // whole columns, by the threads of the first column half: the summation
+      // order is the same for either column split
+      if (half == 0) observe_part<T, N, N, 0, PERIODIC>(u, a.dh, fb, ok, sv);
     }
   }
 #pragma unroll
-  for (int i = 0; i < 6; ++i) sv[i] = wave_sum(sv[i]);
+  for (int i = 0; i < 4; ++i) sv[i] = wave_sum(sv[i]);
   if (lane == 0) {
 #pragma unroll
-    for (int i = 0; i < 6; ++i) red[wave * 8 + i] = sv[i];
+    for (int i = 0; i < 4; ++i) red[wave * 8 + i] = sv[i];
   }
   __syncthreads();
   if (tid < 6) {
     double acc = 0;
-    for (int wv = 0; wv < nwaves; ++wv) acc += red[wv * 8 + tid];
-    a.obs[(size_t)o * 8 + tid] = acc;
+    if (tid < 4)
+      for (int wv = 0; wv < nwaves; ++wv) acc += red[wv * 8 + tid];
+    a.obs[(size_t)o * 8 + tid] = acc;  // slots 4, 5 (kinetic, local) stay 0 here
   }
   __syncthreads();
 
   // ---- nonlocal current and energy at t_{n+1}: moments (1, x, y, z) of the
   // projections with the phase of A_{n+1}; one wavefront per atom
-  double jl[4] = {0, 0, 0, 0};  // lane 0 of each wave: J_x, J_y, J_z, E_NL
   if (n_atoms > 0) {
     for (int at = wave; at < n_atoms; at += nwaves) {
+      double jat[4] = {0, 0, 0, 0};
       const int e0 = a.nl.atom_start[at], e1 = a.nl.atom_start[at + 1];
-      double acc[kMaxProj][4][2];
+      double up[kMaxProj][2];
+      // pass m = 0: u_p; passes m = 1..3: v_p = <x_m beta_p^kappa | w>
+#pragma unroll 1
+      for (int m = 0; m < 4; ++m) {
+        double acc[kMaxProj][2];
 #pragma unroll
-      for (int p = 0; p < kMaxProj; ++p)
+        for (int p = 0; p < kMaxProj; ++p) acc[p][0] = acc[p][1] = 0.0;
+        for (int e = e0 + lane; e < e1; e += 64) {
+          const T2 v = u[a.nl.ent_idx[e]];
+          const double2 p1 = phk[e], p2 = a.phAJ[e];
+          const double pr = p1.x * p2.x - p1.y * p2.y, pim = p1.x * p2.y + p1.y * p2.x;
+          const double mom = (m == 0) ? 1.0 : a.ent_x[3 * (size_t)e + (m - 1)];
+          const double gr = mom * (pr * (double)v.x - pim * (double)v.y);
+          const double gi = mom * (pr * (double)v.y + pim * (double)v.x);
 #pragma unroll
-        for (int m = 0; m < 4; ++m) acc[p][m][0] = acc[p][m][1] = 0.0;
-      for (int e = e0 + lane; e < e1; e += 64) {
-        const T2 v = u[a.nl.ent_idx[e]];
-        const double2 p1 = phk[e], p2 = a.phAJ[e];
-        const double pr = p1.x * p2.x - p1.y * p2.y, pim = p1.x * p2.y + p1.y * p2.x;
-        const double gr = pr * (double)v.x - pim * (double)v.y;
-        const double gi = pr * (double)v.y + pim * (double)v.x;
-        const double mom[4] = {1.0, a.ent_x[3 * (size_t)e], a.ent_x[3 * (size_t)e + 1],
-                               a.ent_x[3 * (size_t)e + 2]};
+          for (int p = 0; p < kMaxProj; ++p) {
+            const double b = a.ent_beta[(size_t)e * kMaxProj + p];
+            acc[p][0] += b * gr;
+            acc[p][1] += b * gi;
+          }
+        }
 #pragma unroll
         for (int p = 0; p < kMaxProj; ++p) {
-          const double b = a.ent_beta[(size_t)e * kMaxProj + p];
-#pragma unroll
-          for (int m = 0; m < 4; ++m) {
-            acc[p][m][0] += b * mom[m] * gr;
-            acc[p][m][1] += b * mom[m] * gi;
+          const double E = a.nl.atom_E[at * kMaxProj + p];
+          const double r = wave_sum(acc[p][0]) * a.dV, i = wave_sum(acc[p][1]) * a.dV;
+          if (m == 0) {
+            up[p][0] = r;
+            up[p][1] = i;
+            jat[3] += E * (r * r + i * i);
+          } else {
+            jat[m - 1] += 2.0 * E * (r * up[p][1] - i * up[p][0]);
           }
         }
       }
+      if (lane == 0) {
 #pragma unroll
-      for (int p = 0; p < kMaxProj; ++p) {
-        double ur = wave_sum(acc[p][0][0]) * a.dV, ui = wave_sum(acc[p][0][1]) * a.dV;
-        const double E = a.nl.atom_E[at * kMaxProj + p];
-        jl[3] += E * (ur * ur + ui * ui);
-#pragma unroll
-        for (int m = 1; m < 4; ++m) {
-          const double vr = wave_sum(acc[p][m][0]) * a.dV, vi = wave_sum(acc[p][m][1]) * a.dV;
-          jl[m - 1] += 2.0 * E * (vr * ui - vi * ur);
-        }
+        for (int i = 0; i < 4; ++i) ja[at * 4 + i] = jat[i];
       }
     }
   }
-  if (lane == 0) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) red[wave * 8 + i] = jl[i];
-  }
   __syncthreads();
-  if (tid < 4) {
+  if (tid < 4) {  // atoms summed in index order, whatever wavefront formed them
     double acc = 0;
-    for (int wv = 0; wv < nwaves; ++wv) acc += red[wv * 8 + tid];
+    for (int at = 0; at < n_atoms; ++at) acc += ja[at * 4 + tid];
     a.jnl[(size_t)o * 4 + tid] = acc;
+  }
+}
+
+// one orbital per workgroup
+template <typename T, int N, int ZS, bool PERIODIC, int MAXT>
+__global__ __launch_bounds__(MAXT) void k_fused(FusedArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  fused_body<T, N, ZS, PERIODIC>(a, blockIdx.x, smem_raw);
+}
+
+// Persistent form for batches of cells with the same grid: a fixed grid of
+// workgroups pulls (cell, orbital) items from a device queue in the given
+// (largest-cell-first) order until the list is exhausted; every item is
+// computed exactly as in k_fused, so the result does not depend on which
+// workgroup takes it.
+template <typename T, int N, int ZS, bool PERIODIC, int MAXT>
+__global__ __launch_bounds__(MAXT) void k_fused_persistent(const FusedArgs<T>* __restrict__ cells,
+                                                           const int2* __restrict__ items, int n_items,
+                                                           int* queue) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int next;
+  for (;;) {
+    if (threadIdx.x == 0) next = atomicAdd(queue, 1);
+    __syncthreads();
+    const int it = __builtin_amdgcn_readfirstlane(next);
+    __syncthreads();
+    if (it >= n_items) break;
+    const int2 ci = items[it];
+    fused_body<T, N, ZS, PERIODIC>(cells[ci.x], ci.y, smem_raw);
+    __syncthreads();
   }
 }
 
 size_t fused_lds_bytes(const Geometry& g, int n_atoms, size_t elem) {
   const size_t N = (size_t)g.n1 * g.n2 * g.n3;
-  return ((N * elem + 15) & ~(size_t)15) + (size_t)n_atoms * kMaxProj * sizeof(double2) + 16 * 8 * sizeof(double);
+  return ((N * elem + 15) & ~(size_t)15) + (size_t)n_atoms * kMaxProj * sizeof(double2) + 16 * 8 * sizeof(double) +
+         (size_t)n_atoms * 4 * sizeof(double);
 }
 
 bool fused_supported(const Geometry& g, int n_atoms, size_t elem) {
-  const int n3 = g.n3;
-  if (n3 != 12 && n3 != 16 && n3 != 20) return false;
-  if (g.n1 * g.n2 > 512) return false;
+  const int n = g.n3;
+  if (n != 12 && n != 16 && n != 20) return false;
+  if (g.n1 != n || g.n2 != n) return false;
   return fused_lds_bytes(g, n_atoms, elem) <= 160 * 1024;
 }
 
-template <typename T, int N3, int MAXT>
-static void launch_n3(bool periodic, const FusedArgs<T>& a, size_t lds, hipStream_t s) {
-  const int threads = ((a.g.n1 * a.g.n2 + 63) / 64) * 64;
+template <int N, int ZS>
+constexpr int fused_threads() {
+  return ZS * (((N * N + 63) / 64) * 64);
+}
+
+template <typename T, int N, int ZS>
+static void launch_n(bool periodic, const FusedArgs<T>& a, size_t lds, hipStream_t s) {
+  constexpr int HALF = ((N * N + 63) / 64) * 64;
+  constexpr int threads = ZS * HALF;
+  constexpr int bound = threads <= 512 ? 512 : 1024;
   const dim3 grid((unsigned)((size_t)a.g.n_orb * a.g.n_k));
   if (periodic)
-    hipLaunchKernelGGL((k_fused<T, N3, true, MAXT>), grid, dim3(threads), lds, s, a);
+    hipLaunchKernelGGL((k_fused<T, N, ZS, true, bound>), grid, dim3(threads), lds, s, a);
   else
-    hipLaunchKernelGGL((k_fused<T, N3, false, MAXT>), grid, dim3(threads), lds, s, a);
+    hipLaunchKernelGGL((k_fused<T, N, ZS, false, bound>), grid, dim3(threads), lds, s, a);
 }
 
 template <typename T>
@@ -377,14 +446,59 @@ hipError_t launch_fused(const FusedArgs<T>& a, hipStream_t s) {
   const size_t lds = fused_lds_bytes(a.g, a.nl.n_atoms, sizeof(T2));
   const bool per = a.g.periodic != 0;
   switch (a.g.n3) {
-    case 12: launch_n3<T, 12, 512>(per, a, lds, s); break;
-    case 16: launch_n3<T, 16, 512>(per, a, lds, s); break;
-    default: launch_n3<T, 20, 512>(per, a, lds, s); break;
+    case 12: launch_n<T, 12, 2>(per, a, lds, s); break;
+    case 16: launch_n<T, 16, 2>(per, a, lds, s); break;
+    default: launch_n<T, 20, 1>(per, a, lds, s); break;
   }
   return hipGetLastError();
 }
 
+// Column split per grid size, fixed so that every path computes the same
+// bits: measured on MI355X, splitting the 12^3 and 16^3 columns between two
+// wavefronts is faster; at 20^3 the split spills registers and is slower.
+int fused_column_split(int n) { return n <= 16 ? 2 : 1; }
+
 template hipError_t launch_fused<double>(const FusedArgs<double>&, hipStream_t);
 template hipError_t launch_fused<float>(const FusedArgs<float>&, hipStream_t);
+
+template <typename T, int N, int ZS>
+static void launch_pers_n(bool periodic, const FusedArgs<T>* cells, const int2* items, int n_items,
+                          int* queue, int wgs, size_t lds, hipStream_t s) {
+  constexpr int threads = fused_threads<N, ZS>();
+  constexpr int bound = threads <= 512 ? 512 : 1024;
+  if (periodic)
+    hipLaunchKernelGGL((k_fused_persistent<T, N, ZS, true, bound>), dim3(wgs), dim3(threads), lds, s, cells,
+                       items, n_items, queue);
+  else
+    hipLaunchKernelGGL((k_fused_persistent<T, N, ZS, false, bound>), dim3(wgs), dim3(threads), lds, s, cells,
+                       items, n_items, queue);
+}
+
+template <typename T>
+hipError_t launch_fused_persistent(int n, int zs, bool periodic, const FusedArgs<T>* cells, const int2* items,
+                                   int n_items, int* queue, int wgs, size_t lds, hipStream_t s) {
+  if (wgs < 1 || n_items < 1) return hipErrorInvalidValue;
+  if (zs == 2) {
+    switch (n) {
+      case 12: launch_pers_n<T, 12, 2>(periodic, cells, items, n_items, queue, wgs, lds, s); break;
+      case 16: launch_pers_n<T, 16, 2>(periodic, cells, items, n_items, queue, wgs, lds, s); break;
+      case 20: launch_pers_n<T, 20, 2>(periodic, cells, items, n_items, queue, wgs, lds, s); break;
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    switch (n) {
+      case 12: launch_pers_n<T, 12, 1>(periodic, cells, items, n_items, queue, wgs, lds, s); break;
+      case 16: launch_pers_n<T, 16, 1>(periodic, cells, items, n_items, queue, wgs, lds, s); break;
+      case 20: launch_pers_n<T, 20, 1>(periodic, cells, items, n_items, queue, wgs, lds, s); break;
+      default: return hipErrorInvalidValue;
+    }
+  }
+  return hipGetLastError();
+}
+
+template hipError_t launch_fused_persistent<double>(int, int, bool, const FusedArgs<double>*, const int2*, int,
+                                                    int*, int, size_t, hipStream_t);
+template hipError_t launch_fused_persistent<float>(int, int, bool, const FusedArgs<float>*, const int2*, int,
+                                                   int*, int, size_t, hipStream_t);
 
 }  // namespace td

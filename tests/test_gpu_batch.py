@@ -1,0 +1,67 @@
+"""GPU checks of uneven batches: every cell of a batch equals its own solo
+run bit for bit (the persistent fused kernel computes each (cell, orbital)
+item exactly as the one-orbital-per-workgroup kernel; 24^3 cells take the
+per-stage kernels in both), the tuner's steps change nothing, and cells agree
+with the FP64 oracle."""
+import numpy as np
+import pytest
+
+import synth
+from gpu_helpers import announce, gpu_run, oracle_run, rel_l2, max_rel_series
+
+pytestmark = pytest.mark.gpu
+
+
+def _cells(precision):
+    cells = synth.batch_cells(cells=range(7), nsteps=7, max_orb=12, max_k=3,
+                              grids=(12, 16, 20, 24), precision=precision)
+    return cells
+
+
+@pytest.mark.parametrize("prec", ["c128", "mixed"])
+def test_batch_cells_equal_solo_runs(prec):
+    from paper_1804_01404_amd.binding import TDDFTBatch
+    cells = _cells(prec)
+    announce(f"batch of {len(cells)} cells, grids {[c.n[0] for c in cells]}, {prec}")
+    with TDDFTBatch(cells, precision=prec) as b:
+        Js = b.propagate([c.A for c in cells])
+        psis = [b.orbitals(i) for i in range(len(cells))]
+        rep = b.report()
+    announce(f"batch plan {rep}")
+    assert sum(g["cells"] for g in rep["groups"]) + len(rep["per_stage_cells"]) == len(cells)
+    for i, c in enumerate(cells):
+        solo = gpu_run(c, precision=prec)
+        assert np.array_equal(Js[i], solo["J"]), i
+        assert np.array_equal(psis[i], solo["psi"]), i
+
+
+def test_batch_cells_match_oracle():
+    from paper_1804_01404_amd.binding import TDDFTBatch
+    cells = _cells("c128")[:3]
+    announce("batch vs oracle")
+    with TDDFTBatch(cells, precision="c128") as b:
+        Js = b.propagate([c.A for c in cells])
+        psis = [b.orbitals(i) for i in range(len(cells))]
+    for i, c in enumerate(cells):
+        o = oracle_run(c)
+        assert rel_l2(psis[i], o["psi"]) < 1e-10, i
+        assert max_rel_series(Js[i], o["J"]) < 1e-8, i
+
+
+def test_batch_second_propagate_reuses_graph():
+    """Two propagate calls (tuning then graph replay) continue the same run."""
+    from paper_1804_01404_amd.binding import TDDFTBatch
+    cells = _cells("mixed")[:4]
+    for c in cells:
+        c.A = c.A  # 7 steps
+    announce("batch two calls")
+    with TDDFTBatch(cells, precision="mixed") as b:
+        J1 = b.propagate([c.A[:4] for c in cells])
+        J2 = b.propagate([c.A[3:] for c in cells])
+        psi_a = [b.orbitals(i) for i in range(len(cells))]
+    with TDDFTBatch(cells, precision="mixed") as b:
+        J = b.propagate([c.A for c in cells])
+        psi_b = [b.orbitals(i) for i in range(len(cells))]
+    for i in range(len(cells)):
+        assert np.array_equal(np.concatenate([J1[i], J2[i]]), J[i])
+        assert np.array_equal(psi_a[i], psi_b[i])
