@@ -152,6 +152,17 @@ tddft_status tddft_dipole(tddft_ctx *ctx, double d[3]);
  * axis 0..2; re-forms rho and the potential. EINVAL for periodic cells. */
 tddft_status tddft_kick(tddft_ctx *ctx, double F0, int32_t axis);
 
+/* Ground-state preparation (Sec. 2.1: the real-time run starts from the
+ * static Kohn-Sham solution), at A = 0. Each of n_iter iterations applies the
+ * imaginary-time Taylor step w <- sum_{m=0..4} (-tau h)^m / m! w with the
+ * potential frozen at the current density, orthonormalises the orbitals of
+ * every k-point (Gram-Schmidt in orbital order, as Cholesky-QR applied twice)
+ * and rebuilds the density and the Hartree + xc potential. tau > 0 with
+ * tau * lambda_max(h) <= 2.7, else EUNSTABLE (the damping polynomial must
+ * stay below one). energies (may be NULL) receives the total energy after
+ * each iteration. The final density becomes rho_0 of the dipole. */
+tddft_status tddft_ground_state(tddft_ctx *ctx, int32_t n_iter, double tau, double *energies);
+
 /* Mean device time per step of the last propagate, from HIP events (ms). */
 tddft_status tddft_last_timing(tddft_ctx *ctx, double *ms_per_step);
 

@@ -284,6 +284,32 @@ def taylor_step(W, dt, hop, order: int = 4):
     return out
 
 
+def imaginary_time_step(W, tau, hop, order: int = 4):
+    """sum_{m=0..order} (-tau h)^m / m! w: the truncated Taylor expansion of
+    exp(-tau h), which shrinks the high eigencomponents relative to the low
+    ones while tau * lambda_max stays inside the polynomial's decreasing range
+    (preparation of the initial state, Sec. 2.1)."""
+    term = W
+    out = W.copy()
+    for m in range(1, order + 1):
+        term = (-tau / m) * hop(term)
+        out = out + term
+    return out
+
+
+def gram_schmidt(W, grid: Grid):
+    """Orthonormalise the orbitals of one k-point in their index order (the
+    Gram-Schmidt step that is sequential over orbitals, Sec. 5), with
+    <a|b> = h^3 sum conj(a) b. W: [n_orb, n3, n2, n1]."""
+    Q = np.array(W, dtype=np.complex128, copy=True)
+    for i in range(Q.shape[0]):
+        v = Q[i]
+        for j in range(i):
+            v = v - grid.inner(Q[j], v) * Q[j]
+        Q[i] = v / np.sqrt(np.real(grid.inner(v, v)))
+    return Q
+
+
 # --------------------------------------------------------------------------
 # density, current, dipole (Eq. rho, Eq. macro_current, Sec. 3.1)
 
@@ -492,6 +518,27 @@ class TDKS:
         self.A_now = A1
         self.rho = density(self.psi, self.kw, self.grid)
         self._update_potential()
+
+    def ground_state(self, n_iter, tau):
+        """Prepare the initial state (Sec. 2.1) at A = 0: each iteration damps
+        every k-point's orbitals with the imaginary-time Taylor polynomial under
+        the potential of the current density, orthonormalises them by
+        Gram-Schmidt, and rebuilds the density and potential. Returns the energy
+        after each iteration; the final density becomes rho_0."""
+        energies = np.empty(n_iter)
+        zero = np.zeros(3)
+        for it in range(n_iter):
+            V = self.v_ks
+            for ik, k in enumerate(self.kpts):
+                hop = lambda X, k=k: apply_h(X, k, V, self.projs, self.grid)
+                W = imaginary_time_step(self.psi[ik], tau, hop)
+                self.psi[ik] = gram_schmidt(W, self.grid)
+            self.rho = density(self.psi, self.kw, self.grid)
+            self._update_potential()
+            energies[it] = self.energy(zero)
+        self.A_now = zero
+        self.rho0 = self.rho.copy()
+        return energies
 
     def propagate(self, A):
         """Step through the table A[0..nsteps]; returns I(t_{n+1}) per step."""

@@ -28,7 +28,7 @@ FLAG_ALLOW_UNSTABLE, FLAG_DEBUG_SYNC, FLAG_NO_GRAPH, FLAG_STREAMING, FLAG_NO_TUN
 
 EXPORTED = ["tddft_abi_version", "tddft_init", "tddft_set_potential", "tddft_propagate",
             "tddft_density_current", "tddft_get_orbitals", "tddft_set_orbitals", "tddft_energy",
-            "tddft_norms", "tddft_dipole", "tddft_kick", "tddft_last_timing", "tddft_time_kernel",
+            "tddft_norms", "tddft_dipole", "tddft_kick", "tddft_ground_state", "tddft_last_timing", "tddft_time_kernel",
             "tddft_last_error", "tddft_free", "tddft_batch_create", "tddft_batch_set_potential",
             "tddft_batch_propagate", "tddft_batch_cell", "tddft_batch_last_timing", "tddft_batch_report",
             "tddft_batch_last_error", "tddft_batch_free"]
@@ -89,6 +89,7 @@ def load_library(path: str = LIB_PATH):
     lib.tddft_norms.argtypes = [C.c_void_p, _dp]
     lib.tddft_dipole.argtypes = [C.c_void_p, _dp]
     lib.tddft_kick.argtypes = [C.c_void_p, C.c_double, C.c_int32]
+    lib.tddft_ground_state.argtypes = [C.c_void_p, C.c_int32, C.c_double, _dp]
     lib.tddft_last_timing.argtypes = [C.c_void_p, _dp]
     lib.tddft_time_kernel.argtypes = [C.c_void_p, C.c_int32, C.c_int32, _dp]
     lib.tddft_last_error.argtypes = [C.c_void_p]
@@ -256,6 +257,12 @@ class TDDFT:
         d = np.empty(3)
         self._check(self.lib.tddft_dipole(self.h, _ptr(d)))
         return d
+
+    def ground_state(self, n_iter: int, tau: float) -> np.ndarray:
+        """Imaginary-time preparation of the initial state; energy per iteration."""
+        E = np.empty(max(int(n_iter), 1))
+        self._check(self.lib.tddft_ground_state(self.h, int(n_iter), float(tau), _ptr(E)))
+        return E[: int(n_iter)]
 
     def kick(self, F0: float, axis: int):
         self._check(self.lib.tddft_kick(self.h, float(F0), int(axis)))

@@ -367,8 +367,10 @@ tddft_status enqueue_fused_tail(tddft_ctx* c) {
 }
 
 // one kernel per Horner stage, then observables, current, density, potential
+// the four Horner stages with per-stage projections, W <- sum_m (x h)^m / m! W
+// with x = -i dt (real time, Eq. 2) or x = -tau (imaginary time)
 template <typename T>
-tddft_status enqueue_streaming_update(tddft_ctx* c) {
+tddft_status enqueue_taylor_stages(tddft_ctx* c, double dt, double tau_imag) {
   StageArgs<T> a = stage_args<T>(c);
   a.V = vpot<T>(c);
   void* bufs_in[4] = {c->W, c->U0, c->U1, c->U0};
@@ -392,11 +394,19 @@ tddft_status enqueue_streaming_update(tddft_ctx* c) {
     a.in = as2<T>(bufs_in[i]);
     a.w = as2<T>(c->W);
     a.out = as2<T>(bufs_out[i]);
-    a.tau = c->cfg.dt / s;
+    a.tau = dt / s;  // u_{s-1} = w + (x / s) h u_s
+    a.tau_re = -tau_imag / s;
     const int mode = (s == 4) ? kFirst : (s == 1 ? kLast : kMid);
     LAUNCH(launch_stage<T>(mode, c->bc, a, c->stream), "stage");
   }
-  tddft_status st = enqueue_observe<T>(c, 1);
+  return TDDFT_OK;
+}
+
+template <typename T>
+tddft_status enqueue_streaming_update(tddft_ctx* c) {
+  tddft_status st = enqueue_taylor_stages<T>(c, c->cfg.dt, 0.0);
+  if (st != TDDFT_OK) return st;
+  st = enqueue_observe<T>(c, 1);
   if (st != TDDFT_OK) return st;
   return enqueue_density_potential<T>(c);
 }
@@ -564,6 +574,73 @@ tddft_status collect_propagate(tddft_ctx* c, int32_t nsteps, const double* A, do
   for (int i = 0; i < 3; ++i) c->A_last[i] = A[3 * (size_t)nsteps + i];
   if (flag) return fail(c, TDDFT_ENUMERIC, "NaN or Inf in the orbital norms or current");
   return TDDFT_OK;
+}
+
+// Cholesky S = L L^H of a Hermitian positive matrix, returns M = L^{-1}
+bool chol_inverse(const std::vector<double2>& S, int n, std::vector<double2>& M) {
+  std::vector<double> Lr(n * n, 0.0), Li(n * n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    double d = S[j * n + j].x;
+    for (int k = 0; k < j; ++k) d -= Lr[j * n + k] * Lr[j * n + k] + Li[j * n + k] * Li[j * n + k];
+    if (!(d > 0.0)) return false;
+    const double ljj = std::sqrt(d);
+    Lr[j * n + j] = ljj;
+    for (int i = j + 1; i < n; ++i) {
+      double ar = S[i * n + j].x, ai = S[i * n + j].y;
+      for (int k = 0; k < j; ++k) {  // - L[i][k] conj(L[j][k])
+        ar -= Lr[i * n + k] * Lr[j * n + k] + Li[i * n + k] * Li[j * n + k];
+        ai -= Li[i * n + k] * Lr[j * n + k] - Lr[i * n + k] * Li[j * n + k];
+      }
+      Lr[i * n + j] = ar / ljj;
+      Li[i * n + j] = ai / ljj;
+    }
+  }
+  // forward substitution: L M = I, M lower
+  M.assign(n * n, make_double2(0.0, 0.0));
+  for (int c = 0; c < n; ++c) {
+    for (int i = c; i < n; ++i) {
+      double br = (i == c) ? 1.0 : 0.0, bi = 0.0;
+      for (int k = c; k < i; ++k) {
+        const double2 m = M[k * n + c];
+        br -= Lr[i * n + k] * m.x - Li[i * n + k] * m.y;
+        bi -= Lr[i * n + k] * m.y + Li[i * n + k] * m.x;
+      }
+      M[i * n + c] = make_double2(br / Lr[i * n + i], bi / Lr[i * n + i]);
+    }
+  }
+  return true;
+}
+
+template <typename T>
+tddft_status orthonormalise(tddft_ctx* c) {
+  const int n = c->cfg.n_orb, nk = c->cfg.n_k, N = (int)c->N;
+  double2* dS = reinterpret_cast<double2*>(c->rho_part);  // n_k n_orb^2 complex fits: checked by caller
+  double2* dM = dS + (size_t)nk * n * n;
+  std::vector<double2> S((size_t)nk * n * n), M((size_t)nk * n * n), Mk;
+  for (int pass = 0; pass < 2; ++pass) {
+    LAUNCH(launch_gram<T>(as2<T>(c->W), n, nk, N, c->dV, dS, c->stream), "gram");
+    HIP_TRY(hipMemcpyAsync(S.data(), dS, S.size() * sizeof(double2), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (int k = 0; k < nk; ++k) {
+      std::vector<double2> Sk(S.begin() + (size_t)k * n * n, S.begin() + (size_t)(k + 1) * n * n);
+      if (!chol_inverse(Sk, n, Mk)) return fail(c, TDDFT_ENUMERIC, "orbitals became linearly dependent");
+      std::copy(Mk.begin(), Mk.end(), M.begin() + (size_t)k * n * n);
+    }
+    HIP_TRY(hipMemcpyAsync(dM, M.data(), M.size() * sizeof(double2), hipMemcpyHostToDevice, c->stream));
+    LAUNCH(launch_apply_lower<T>(as2<T>(c->W), dM, n, nk, N, as2<T>(c->U0), c->stream), "apply L^-1");
+    HIP_TRY(hipMemcpyAsync(c->W, c->U0, c->n_orb_tot * c->N * sizeof(typename Vec2<T>::type),
+                           hipMemcpyDeviceToDevice, c->stream));
+  }
+  return TDDFT_OK;
+}
+
+template <typename T>
+tddft_status ground_state_iteration(tddft_ctx* c, double tau) {
+  tddft_status st = enqueue_taylor_stages<T>(c, 0.0, tau);
+  if (st != TDDFT_OK) return st;
+  st = orthonormalise<T>(c);
+  if (st != TDDFT_OK) return st;
+  return enqueue_density_potential<T>(c);
 }
 
 }  // namespace
@@ -1111,6 +1188,37 @@ tddft_status tddft_time_kernel(tddft_ctx* c, int32_t which, int32_t reps, double
   float t = 0;
   HIP_TRY(hipEventElapsedTime(&t, c->ev0, c->ev1));
   *ms = t / reps;
+  return TDDFT_OK;
+}
+
+tddft_status tddft_ground_state(tddft_ctx* c, int32_t n_iter, double tau, double* energies) {
+  if (!c) return TDDFT_EINVAL;
+  if (c->poisoned) return fail(c, TDDFT_ESTATE, "context poisoned: " + c->err);
+  if (!c->potential_set) return fail(c, TDDFT_ESTATE, "ground_state before set_potential");
+  if (n_iter < 0 || !(tau > 0.0) || !std::isfinite(tau)) return fail(c, TDDFT_EINVAL, "bad ground-state arguments");
+  const double lam = spectral_bound(c, 0.0, -c->vabs, c->vabs);
+  if (tau * lam > 2.7) return fail(c, TDDFT_EUNSTABLE, "tau * lambda_max > 2.7: the imaginary-time step would grow");
+  const int n = c->cfg.n_orb;
+  if ((size_t)2 * c->cfg.n_k * n * n * 2 > (size_t)c->rho_nchunks * c->N)
+    return fail(c, TDDFT_EINVAL, "too many orbitals per k-point for the Gram workspace");
+  invalidate_graph(c);
+  for (int i = 0; i < 3; ++i) c->A_last[i] = 0.0;
+  double Ab[6] = {0, 0, 0, 0, 0, 0};
+  HIP_TRY(hipMemcpyAsync(c->Aobs, Ab, sizeof(Ab), hipMemcpyHostToDevice, c->stream));
+  for (int it = 0; it < n_iter; ++it) {
+    LAUNCH(launch_step_params(c->Aobs, c->counter, 0, c->kpt_d, c->cfg.n_k, c->ent_x, c->nl.n_ent,
+                              c->cfg.gauge, c->cfg.dt, c->kappa, c->kappaJ, c->efield, c->phA, c->phAJ,
+                              c->Alast, c->stream),
+           "step_params");
+    tddft_status st = c->mixed ? ground_state_iteration<float>(c, tau) : ground_state_iteration<double>(c, tau);
+    if (st != TDDFT_OK) return st;
+    if (energies) {
+      st = tddft_energy(c, &energies[it]);
+      if (st != TDDFT_OK) return st;
+    }
+  }
+  HIP_TRY(hipMemcpyAsync(c->rho0, c->rho, c->N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
   return TDDFT_OK;
 }
 

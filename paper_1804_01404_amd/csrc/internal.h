@@ -65,7 +65,8 @@ struct StageArgs {
   double lap[3][5];        // -1/2 c_m / h_mu^2
   double dh[3][4];         // d_m / h_mu
   double cdiag;            // sum_mu -1/2 c_0 / h_mu^2
-  double tau;              // dt / s
+  double tau;              // dt / s: u_{s-1} = w + (tau_re - i tau) h u_s
+  double tau_re;           // 0 in real time; -tau_imag / s for imaginary time
 };
 
 template <typename T>
@@ -170,6 +171,12 @@ template <typename T>
 hipError_t launch_kick(typename Vec2<T>::type* w, Geometry g, double F0, int axis, size_t n_orb_tot,
                        hipStream_t s);
 hipError_t launch_set_int(int* p, int v, hipStream_t s);
+template <typename T>
+hipError_t launch_gram(const typename Vec2<T>::type* w, int n_orb, int n_k, int N, double dV, double2* S,
+                       hipStream_t s);
+template <typename T>
+hipError_t launch_apply_lower(const typename Vec2<T>::type* w, const double2* M, int n_orb, int n_k, int N,
+                              typename Vec2<T>::type* out, hipStream_t s);
 hipError_t launch_real_part(const double2* src, double* dst, size_t n, hipStream_t s);
 hipError_t launch_fill(double* p, double v, size_t n, hipStream_t s);
 

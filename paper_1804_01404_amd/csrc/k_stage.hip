@@ -112,6 +112,7 @@ __global__ __launch_bounds__(1024) void k_stage(StageArgs<T> a) {
   }
   const double diag_d = a.cdiag + 0.5 * (kx * kx + ky * ky + kz * kz);
   const T tau = (T)a.tau;
+  const T tau_re = (T)a.tau_re;
   T ext = 0, ez = 0;
   if (a.efield) {
     const double xr = (gx - 0.5 * (n1 - 1)) * g.h1;
@@ -193,8 +194,8 @@ __global__ __launch_bounds__(1024) void k_stage(StageArgs<T> a) {
         }
       }
       T2 res;
-      res.x = wv.x + tau * hi;
-      res.y = wv.y - tau * hr;
+      res.x = wv.x + tau * hi + tau_re * hr;
+      res.y = wv.y - tau * hr + tau_re * hi;
       a.out[base + pz] = res;
     }
 #pragma unroll
