@@ -29,12 +29,14 @@ sys.path.insert(0, ROOT)
 METRIC = "orbital·gridpoint Taylor steps/s (FP64 vs mixed/batched), % HBM peak"
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP64_MFMA_PEAK_TFLOPS = 78.6   # MI355X dense FP64 matrix
+FP32_VALU_PEAK_TFLOPS = 157.3  # MI355X FP32 vector (256 CU x 2.4 GHz x 256 flop/clk, packed issue)
+FP64_VALU_PEAK_TFLOPS = 78.6   # MI355X FP64 vector
 
 
 def time_path(system, precision, steps, warmup):
     import torch
-    from paper_1804_01404_amd.binding import (KERNEL_DENSITY, KERNEL_OBSERVE, KERNEL_PROJECT,
-                                              KERNEL_STAGE, TDDFT)
+    from paper_1804_01404_amd.binding import (KERNEL_DENSITY, KERNEL_FUSED, KERNEL_OBSERVE,
+                                              KERNEL_PROJECT, KERNEL_STAGE, TDDFT, TDDFTError)
     A = system.A
     with TDDFT(system, precision=precision) as t:
         t.set_potential()
@@ -52,7 +54,43 @@ def time_path(system, precision, steps, warmup):
             "observe_ms": t.time_kernel(KERNEL_OBSERVE, 20),
             "density_ms": t.time_kernel(KERNEL_DENSITY, 20),
         }
+        try:
+            kern["fused_ms"] = t.time_kernel(KERNEL_FUSED, 20)
+        except TDDFTError:
+            kern["fused_ms"] = None   # this shape takes the per-stage kernels
     return (t1 - t0) / steps * 1e3, dev_ms, kern, J
+
+
+def step_flops_per_og(system):
+    """Algorithmic real flops of one time step per orbital x k-point x grid
+    point: 152 per Horner stage for the 25-point h (Laplacian and gradient,
+    kappa term, diagonal, Horner update), four stages, plus the projection and
+    add-back of the nonlocal term, 2 x 8 flops per projector and sphere point
+    and stage, spread over the grid."""
+    sphere = sum(p.beta.shape[0] * p.npts for p in system.projectors)
+    return 4 * 152 + 4 * 16 * sphere / system.n_grid
+
+
+def stored_traffic(kernel_source, kernel_name, workload):
+    """HBM bytes per launch from the committed profiler counters, if they were
+    taken on the current source of the kernel; else None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel_name}_{workload}_traffic.txt")
+    src = os.path.join(ROOT, "paper_1804_01404_amd", "csrc", kernel_source)
+    if not (os.path.exists(path) and os.path.exists(src)):
+        return None
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    fields = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    if fields.get("source_sha256") != digest:
+        return None
+    try:
+        return float(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(system, target_s=12.0):
@@ -126,11 +164,29 @@ def main():
     ms, dev_ms, kern, J = time_path(s, args.precision, args.steps, args.warmup)
     value = og / (ms * 1e-3)
     esz = 8 if args.precision == "mixed" else 16
-    # algorithmic bytes of one middle Horner stage: read u_s, read w, write u_{s-1}
-    stage_bytes = 3 * esz * og
-    achieved = stage_bytes / (kern["stage_ms"] * 1e-3) / 1e9
-    # issued MFMA work of one projection launch: one 16x16x4 FP64 MFMA per four
-    # sphere entries, per atom and group of eight orbitals
+    if kern["fused_ms"] is not None:
+        # dominant kernel: the LDS-resident whole-step update (four stages and the
+        # nonlocal term per orbital); the orbital is read and written once, so the
+        # plain arithmetic bounds it
+        flops = og * step_flops_per_og(s)
+        achieved = flops / (kern["fused_ms"] * 1e-3) / 1e12
+        peak = FP32_VALU_PEAK_TFLOPS if args.precision == "mixed" else FP64_VALU_PEAK_TFLOPS
+        roofline = {"bound": "alu", "kernel": "k_fused (whole step, LDS-resident)",
+                    "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                    "traffic": stored_traffic("k_fused.hip", "k_fused", "diamond20_k512"),
+                    "flops_per_launch": flops, "algorithmic_bytes_per_launch": 2 * esz * og,
+                    "ms_per_launch": kern["fused_ms"]}
+    else:
+        # dominant kernel: a middle Horner stage, read u_s, read w, write u_{s-1}
+        stage_bytes = 3 * esz * og
+        achieved = stage_bytes / (kern["stage_ms"] * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "kernel": "k_stage (middle Horner stage)",
+                    "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS,
+                    "traffic": stored_traffic("k_stage.hip", "k_stage", "diamond20_k512"),
+                    "bytes_per_launch": stage_bytes, "ms_per_launch": kern["stage_ms"]}
+    # issued MFMA work of one projection launch (per-stage path): one 16x16x4
+    # FP64 MFMA per four sphere entries, per atom and group of eight orbitals
     n_groups = (s.n_orb * s.n_k + 7) // 8
     mfma_flops = sum(n_groups * -(-p.npts // 4) * 2 * 16 * 16 * 4 for p in s.projectors)
     mfma_tflops = mfma_flops / (kern["project_ms"] * 1e-3) / 1e12
@@ -154,18 +210,9 @@ def main():
             "og_per_step": og,
             "precision": args.precision,
         },
-        "roofline": {
-            "bound": "hbm",
-            "kernel": "k_stage (middle Horner stage)",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
-            "bytes_per_launch": stage_bytes,
-            "ms_per_launch": kern["stage_ms"],
-        },
+        "roofline": roofline,
         "device_ms_per_step": dev_ms,
+        "flops_per_og_step": step_flops_per_og(s),
         "kernels_ms": kern,
         "mfma_projection": {"issued_tflops": mfma_tflops, "peak": FP64_MFMA_PEAK_TFLOPS,
                             "frac": mfma_tflops / FP64_MFMA_PEAK_TFLOPS},

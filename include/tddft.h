@@ -168,13 +168,16 @@ tddft_status tddft_last_timing(tddft_ctx *ctx, double *ms_per_step);
 
 /* Kernels of one step that tddft_time_kernel can time in isolation. */
 enum { TDDFT_KERNEL_STAGE = 0, TDDFT_KERNEL_PROJECT = 1, TDDFT_KERNEL_OBSERVE = 2,
-       TDDFT_KERNEL_DENSITY = 3 };
+       TDDFT_KERNEL_DENSITY = 3, TDDFT_KERNEL_FUSED = 4 };
 
 /* Launch one kernel of the step `reps` times back to back on the context's
  * stream and return the mean duration per launch from HIP events around the
  * launches (ms). TDDFT_KERNEL_STAGE is a middle Horner stage (reads u_s and w,
  * writes u_{s-1}); it and the projection use the two stage buffers, whose
- * contents are scratch between steps, so the state is unchanged. Requires
+ * contents are scratch between steps, so the state is unchanged.
+ * TDDFT_KERNEL_FUSED is the whole four-stage update of a context that takes the
+ * LDS-resident step (EINVAL otherwise); the orbitals are saved to the stage
+ * buffers before and restored after, so the state is unchanged too. Requires
  * set_potential; EINVAL for an unknown kernel or reps < 1. */
 tddft_status tddft_time_kernel(tddft_ctx *ctx, int32_t which, int32_t reps, double *ms_per_launch);
 

@@ -32,7 +32,7 @@ EXPORTED = ["tddft_abi_version", "tddft_init", "tddft_set_potential", "tddft_pro
             "tddft_last_error", "tddft_free", "tddft_batch_create", "tddft_batch_set_potential",
             "tddft_batch_propagate", "tddft_batch_cell", "tddft_batch_last_timing", "tddft_batch_report",
             "tddft_batch_last_error", "tddft_batch_free"]
-KERNEL_STAGE, KERNEL_PROJECT, KERNEL_OBSERVE, KERNEL_DENSITY = 0, 1, 2, 3
+KERNEL_STAGE, KERNEL_PROJECT, KERNEL_OBSERVE, KERNEL_DENSITY, KERNEL_FUSED = 0, 1, 2, 3, 4
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)

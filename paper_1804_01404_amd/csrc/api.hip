@@ -78,6 +78,7 @@ struct tddft_ctx {
 
   // per step
   double *kappa = nullptr, *kappaJ = nullptr, *efield = nullptr, *Alast = nullptr;
+  double* coef = nullptr;  // [n_k][kCoef] in the stage precision (fused step)
   double2 *phA = nullptr, *phAJ = nullptr;
   double* obs = nullptr;
   double *Atab = nullptr, *Jtab = nullptr;
@@ -321,12 +322,25 @@ tddft_status enqueue_observe(tddft_ctx* c, int bump) {
   return TDDFT_OK;
 }
 
+template <typename T>
+FusedArgs<T> fused_args(tddft_ctx* c);
+
+// stencil coefficients of the fused step from the kappa just set
+tddft_status enqueue_coef(tddft_ctx* c) {
+  if (!c->fused) return TDDFT_OK;
+  if (c->mixed)
+    LAUNCH(launch_fused_coef<float>(fused_args<float>(c), c->stream), "fused coefficients");
+  else
+    LAUNCH(launch_fused_coef<double>(fused_args<double>(c), c->stream), "fused coefficients");
+  return TDDFT_OK;
+}
+
 tddft_status enqueue_params(tddft_ctx* c) {
   LAUNCH(launch_step_params(c->Atab, c->counter, 1, c->kpt_d, c->cfg.n_k, c->ent_x, c->nl.n_ent,
                             c->cfg.gauge, c->cfg.dt, c->kappa, c->kappaJ, c->efield, c->phA, c->phAJ,
                             c->Alast, c->stream),
          "step_params");
-  return TDDFT_OK;
+  return enqueue_coef(c);
 }
 
 template <typename T>
@@ -353,6 +367,9 @@ FusedArgs<T> fused_args(tddft_ctx* c) {
   f.dV = c->dV;
   f.obs = c->obs;
   f.jnl = c->jnl;
+  f.coef = reinterpret_cast<T*>(c->coef);
+  for (int mu = 0; mu < 3; ++mu)
+    for (int m = 0; m < 4; ++m) f.lapc[mu][m] = (T)c->lap[mu][m + 1];
   return f;
 }
 
@@ -526,6 +543,8 @@ tddft_status launch_one(tddft_ctx* c, int which) {
     oa.cdiag = c->cdiag;
     oa.out = c->obs;
     LAUNCH(launch_observe<T>(c->bc, oa, c->stream), "observe");
+  } else if (which == TDDFT_KERNEL_FUSED) {
+    LAUNCH(launch_fused<T>(fused_args<T>(c), c->stream), "fused step");
   } else {
     LAUNCH(launch_rho_partial<T>(as2<T>(c->W), c->kw_d, c->cfg.n_orb, c->cfg.n_k, (int)c->N, c->rho_chunk,
                                  c->rho_part, c->stream),
@@ -787,6 +806,7 @@ tddft_status tddft_init(const tddft_config* cfg, const double* psi0, tddft_ctx**
   if ((st = dalloc_t(c, Mt, &c->fft)) || (st = dalloc_t(c, Mt, &c->Kfft))) return cleanup(st);
   if ((st = dalloc_t(c, 3 * (size_t)cfg->n_k, &c->kpt_d)) || (st = dalloc_t(c, (size_t)cfg->n_k, &c->kw_d)) ||
       (st = dalloc_t(c, 3 * (size_t)cfg->n_k, &c->kappa)) || (st = dalloc_t(c, 3 * (size_t)cfg->n_k, &c->kappaJ)) ||
+      (st = dalloc_t(c, (size_t)kCoef * cfg->n_k, &c->coef)) ||
       (st = dalloc_t(c, 3, &c->efield)) || (st = dalloc_t(c, 3, &c->Alast)) || (st = dalloc_t(c, 6, &c->Aobs)) ||
       (st = dalloc_t(c, 1, &c->counter)) || (st = dalloc_t(c, 1, &c->nanflag)) ||
       (st = dalloc_t(c, 8, &c->scalars)) || (st = dalloc_t(c, 8, &c->sums)) ||
@@ -1168,7 +1188,12 @@ tddft_status tddft_time_kernel(tddft_ctx* c, int32_t which, int32_t reps, double
   if (!c || !ms) return TDDFT_EINVAL;
   if (c->poisoned) return fail(c, TDDFT_ESTATE, "context poisoned: " + c->err);
   if (!c->potential_set) return fail(c, TDDFT_ESTATE, "time_kernel before set_potential");
-  if (reps < 1 || which < 0 || which > TDDFT_KERNEL_DENSITY) return fail(c, TDDFT_EINVAL, "bad kernel or reps");
+  if (reps < 1 || which < 0 || which > TDDFT_KERNEL_FUSED) return fail(c, TDDFT_EINVAL, "bad kernel or reps");
+  if (which == TDDFT_KERNEL_FUSED && !c->fused)
+    return fail(c, TDDFT_EINVAL, "this context takes the per-stage kernels, not the fused step");
+  const size_t wbytes = c->n_orb_tot * c->N * (c->mixed ? sizeof(float2) : sizeof(double2));
+  if (which == TDDFT_KERNEL_FUSED)
+    HIP_TRY(hipMemcpyAsync(c->U0, c->W, wbytes, hipMemcpyDeviceToDevice, c->stream));
   double Ab[6];
   for (int i = 0; i < 3; ++i) Ab[i] = Ab[3 + i] = c->A_last[i];
   HIP_TRY(hipMemcpyAsync(c->Aobs, Ab, sizeof(Ab), hipMemcpyHostToDevice, c->stream));
@@ -1176,7 +1201,9 @@ tddft_status tddft_time_kernel(tddft_ctx* c, int32_t which, int32_t reps, double
                             c->cfg.gauge, c->cfg.dt, c->kappa, c->kappaJ, c->efield, c->phA, c->phAJ,
                             c->Alast, c->stream),
          "step_params");
-  tddft_status st = c->mixed ? launch_one<float>(c, which) : launch_one<double>(c, which);  // warm-up
+  tddft_status st = enqueue_coef(c);
+  if (st != TDDFT_OK) return st;
+  st = c->mixed ? launch_one<float>(c, which) : launch_one<double>(c, which);  // warm-up
   if (st != TDDFT_OK) return st;
   HIP_TRY(hipEventRecord(c->ev0, c->stream));
   for (int r = 0; r < reps; ++r) {
@@ -1184,6 +1211,8 @@ tddft_status tddft_time_kernel(tddft_ctx* c, int32_t which, int32_t reps, double
     if (st != TDDFT_OK) return st;
   }
   HIP_TRY(hipEventRecord(c->ev1, c->stream));
+  if (which == TDDFT_KERNEL_FUSED)
+    HIP_TRY(hipMemcpyAsync(c->W, c->U0, wbytes, hipMemcpyDeviceToDevice, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   float t = 0;
   HIP_TRY(hipEventElapsedTime(&t, c->ev0, c->ev1));

@@ -17,6 +17,7 @@ constexpr int kHalf = 4;               // stencil half width (9 points per axis)
 constexpr int kMaxProj = 4;            // projectors per atom
 constexpr int kMoments = 4;            // beta, x beta, y beta, z beta
 constexpr int kCols = kMaxProj * kMoments;  // MFMA B-matrix columns (16)
+constexpr int kCoef = 16;  // per k-point: kappa_mu d_m / h_mu for x, y, z (3 x 4), diagonal, padding
 
 enum StageMode { kFirst = 0, kMid = 1, kLast = 2 };
 enum BcKind { kPeriodicPlane = 0, kPeriodicTile = 1, kIsolatedTile = 2 };
@@ -118,6 +119,8 @@ struct FusedArgs {
   double dt, dV;
   double* obs;             // [n_orb_tot][8]
   double* jnl;             // [n_orb_tot][4]
+  T* coef;                 // [n_k][kCoef] stencil coefficients of the step, stage precision
+  T lapc[3][4];            // off-centre Laplacian weights -1/2 c_m / h_mu^2, stage precision
 };
 
 // ---- launchers (defined in the .hip files) --------------------------------
@@ -129,6 +132,8 @@ template <typename T>
 hipError_t launch_project(const ProjArgs<T>& a, hipStream_t s);
 template <typename T>
 hipError_t launch_fused(const FusedArgs<T>& a, hipStream_t s);
+template <typename T>
+hipError_t launch_fused_coef(const FusedArgs<T>& a, hipStream_t s);
 bool fused_supported(const Geometry& g, int n_atoms, size_t elem);
 size_t fused_lds_bytes(const Geometry& g, int n_atoms, size_t elem);
 int fused_column_split(int n);

@@ -33,6 +33,11 @@ struct Nbr {
   int c;
 };
 
+struct FusedCoefIn {
+  double dh[3][4];
+  double cdiag;
+};
+
 template <typename T>
 struct Coef {
   T cx[4], cy[4], cz[4], bx[4], by[4], bz[4];
@@ -42,6 +47,15 @@ struct Coef {
 // A copy of the offsets that the compiler cannot see through: rebuilding the
 // addresses per stage keeps the unrolled column loop from holding every one
 // of them live across the stage loop.
+__device__ __forceinline__ float opaque_t(float v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+__device__ __forceinline__ double opaque_t(double v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
 __device__ __forceinline__ Nbr opaque(const Nbr& n) {
   Nbr r = n;
 #pragma unroll
@@ -61,17 +75,18 @@ __device__ __forceinline__ typename Vec2<T>::type lds_xy(const typename Vec2<T>:
 template <typename T, int N, int ZN, int Z0, bool PERIODIC>
 __device__ __forceinline__ void stencil_part(const typename Vec2<T>::type* u, const T* __restrict__ V,
                                              const Coef<T>& cf, const Nbr& nb, const bool (&ok)[16],
-                                             const typename Vec2<T>::type (&w)[ZN],
+                                             const typename Vec2<T>::type* __restrict__ wg,
                                              typename Vec2<T>::type (&un)[ZN], T tau, bool length) {
   using T2 = typename Vec2<T>::type;
   constexpr int plane = N * N;
+  const T ez = opaque_t(cf.ez);
 #pragma unroll
   for (int zz = 0; zz < ZN; ++zz) {
     const int z = Z0 + zz;
     const T2* pl = u + z * plane;
     const T2 c = pl[nb.c];
     T dg = cf.diag + V[z * plane + nb.c];
-    if (length) dg += cf.ext + cf.ez * ((T)z - (T)(0.5 * (N - 1)));
+    if (!PERIODIC && length) dg += cf.ext + ez * (T)z;
     T hr = dg * c.x, hi = dg * c.y;
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
@@ -91,8 +106,12 @@ __device__ __forceinline__ void stencil_part(const typename Vec2<T>::type* u, co
       hr += cf.cz[m] * (q.x + r.x) + cf.bz[m] * (q.y - r.y);
       hi += cf.cz[m] * (q.y + r.y) - cf.bz[m] * (q.x - r.x);
     }
-    un[zz].x = w[zz].x + tau * hi;
-    un[zz].y = w[zz].y - tau * hr;
+    // w is re-read (from cache) rather than held in registers for all stages
+    const T2 wv = wg[z * plane + nb.c];
+    un[zz].x = wv.x + tau * hi;
+    un[zz].y = wv.y - tau * hr;
+    // one plane at a time: bounds the loads in flight and so the registers
+    __builtin_amdgcn_sched_barrier(0);
   }
 }
 
@@ -176,37 +195,39 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, const int o, u
   nb.c = active ? ctid : 0;
 
   T2* __restrict__ wg = a.w + (size_t)o * NP;
-  T2 w[ZN], un[ZN];
+  T2 un[ZN];
   const int z0 = half * ZN;
 #pragma unroll
   for (int zz = 0; zz < ZN; ++zz) {
     T2 v;
     v.x = v.y = 0;
     if (active) v = wg[(z0 + zz) * plane + nb.c];
-    w[zz] = v;
     if (active) u[(z0 + zz) * plane + nb.c] = v;
   }
 
   Coef<T> cf;
   {
-    const double kx = a.kappa[3 * k], ky = a.kappa[3 * k + 1], kz = a.kappa[3 * k + 2];
+    // wave-uniform: the k-point table is read with scalar loads
+    const T* __restrict__ ck = a.coef + (size_t)k * kCoef;
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-      cf.cx[m] = (T)a.lap[0][m + 1];
-      cf.cy[m] = (T)a.lap[1][m + 1];
-      cf.cz[m] = (T)a.lap[2][m + 1];
-      cf.bx[m] = (T)(kx * a.dh[0][m]);
-      cf.by[m] = (T)(ky * a.dh[1][m]);
-      cf.bz[m] = (T)(kz * a.dh[2][m]);
+      cf.cx[m] = a.lapc[0][m];
+      cf.cy[m] = a.lapc[1][m];
+      cf.cz[m] = a.lapc[2][m];
+      cf.bx[m] = ck[m];
+      cf.by[m] = ck[4 + m];
+      cf.bz[m] = ck[8 + m];
     }
-    cf.diag = (T)(a.cdiag + 0.5 * (kx * kx + ky * ky + kz * kz));
+    cf.diag = ck[12];
     cf.ext = cf.ez = 0;
-    if (a.efield) {
-      cf.ext = (T)(a.efield[0] * (tx - 0.5 * (N - 1)) * a.g.h1 + a.efield[1] * (ty - 0.5 * (N - 1)) * a.g.h2);
+    if (!PERIODIC && a.efield) {
+      // E . r with r from the box centre; the z part is added per plane
+      cf.ext = (T)(a.efield[0] * (tx - 0.5 * (N - 1)) * a.g.h1 + a.efield[1] * (ty - 0.5 * (N - 1)) * a.g.h2 -
+                   a.efield[2] * a.g.h3 * 0.5 * (N - 1));
       cf.ez = (T)(a.efield[2] * a.g.h3);
     }
   }
-  const bool length = a.efield != nullptr;
+  const bool length = !PERIODIC && a.efield != nullptr;
   const double2* __restrict__ phk = a.nl.phk + (size_t)k * S;
   __syncthreads();
 
@@ -252,9 +273,9 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, const int o, u
       const Nbr sb = opaque(nb);
       if (active) {
         if (ZS == 1 || half == 0)
-          stencil_part<T, N, ZN, 0, PERIODIC>(u, a.V, cf, sb, ok, w, un, tau, length);
+          stencil_part<T, N, ZN, 0, PERIODIC>(u, a.V, cf, sb, ok, wg, un, tau, length);
         else
-          stencil_part<T, N, ZN, (ZS == 2 ? ZN : 0), PERIODIC>(u, a.V, cf, sb, ok, w, un, tau, length);
+          stencil_part<T, N, ZN, (ZS == 2 ? ZN : 0), PERIODIC>(u, a.V, cf, sb, ok, wg, un, tau, length);
       }
     }
     __syncthreads();
@@ -408,6 +429,38 @@ __global__ __launch_bounds__(MAXT) void k_fused_persistent(const FusedArgs<T>* _
     __syncthreads();
   }
 }
+
+// per k-point coefficients of the step in the stage precision (from kappa at
+// the step midpoint): kappa_mu d_m / h_mu and the diagonal
+// -1/2 sum_mu c_0 / h_mu^2 + |kappa|^2 / 2
+template <typename T>
+__global__ void k_fused_coef(const double* __restrict__ kappa, int n_k, FusedCoefIn in, T* __restrict__ coef) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_k) return;
+  const double kx = kappa[3 * k], ky = kappa[3 * k + 1], kz = kappa[3 * k + 2];
+  T* c = coef + (size_t)k * kCoef;
+  for (int m = 0; m < 4; ++m) {
+    c[m] = (T)(kx * in.dh[0][m]);
+    c[4 + m] = (T)(ky * in.dh[1][m]);
+    c[8 + m] = (T)(kz * in.dh[2][m]);
+  }
+  c[12] = (T)(in.cdiag + 0.5 * (kx * kx + ky * ky + kz * kz));
+  c[13] = c[14] = c[15] = (T)0;
+}
+
+template <typename T>
+hipError_t launch_fused_coef(const FusedArgs<T>& a, hipStream_t s) {
+  FusedCoefIn in;
+  for (int i = 0; i < 3; ++i)
+    for (int m = 0; m < 4; ++m) in.dh[i][m] = a.dh[i][m];
+  in.cdiag = a.cdiag;
+  const int nk = a.g.n_k;
+  hipLaunchKernelGGL((k_fused_coef<T>), dim3((unsigned)((nk + 63) / 64)), dim3(64), 0, s, a.kappa, nk, in, a.coef);
+  return hipGetLastError();
+}
+
+template hipError_t launch_fused_coef<double>(const FusedArgs<double>&, hipStream_t);
+template hipError_t launch_fused_coef<float>(const FusedArgs<float>&, hipStream_t);
 
 size_t fused_lds_bytes(const Geometry& g, int n_atoms, size_t elem) {
   const size_t N = (size_t)g.n1 * g.n2 * g.n3;
