@@ -299,7 +299,7 @@ def imaginary_time_step(W, tau, hop, order: int = 4):
 
 def gram_schmidt(W, grid: Grid):
     """Orthonormalise the orbitals of one k-point in their index order (the
-    Gram-Schmidt step that is sequential over orbitals, Sec. 5), with
+    Gram-Schmidt step that is sequential over orbitals, Sec. 3.2), with
     <a|b> = h^3 sum conj(a) b. W: [n_orb, n3, n2, n1]."""
     Q = np.array(W, dtype=np.complex128, copy=True)
     for i in range(Q.shape[0]):
