@@ -220,6 +220,103 @@ tddft_status tddft_batch_report(tddft_batch *b, char *buf, size_t len);
 const char *tddft_batch_last_error(const tddft_batch *b);
 void tddft_batch_free(tddft_batch *b);
 
+/* ---- Learned current surrogate -----------------------------------------
+ * A network that stands in for the microscopic cell of the multiscale
+ * coupling (Sec. 5, Eqs. Maxwell_ms and TDKS_ms): it maps the causal window
+ * of the last `window` macroscopic samples of the vector potential at one
+ * point to the current there. Form (the paper has none): x = A / a_scale;
+ * h1 = tanh(W1 x + b1) (window -> hidden); h2 = tanh(W2 h1 + b2);
+ * y = w3 . h2 + b3 + ws . x; I = j_scale y. Loss: mean of (y - target)^2.
+ * Training: Adam (Kingma and Ba 2015, Algorithm 1) on the device. FP32.
+ * Parameters, flat, host order: W1 [hidden][window], b1 [hidden],
+ * W2 [hidden][hidden], b2 [hidden], w3 [hidden], b3 [1], ws [window]. */
+typedef struct tddft_nn tddft_nn;
+
+typedef struct {
+  int32_t window;         /* input samples W, 1..4096                            */
+  int32_t hidden;         /* hidden width H, 1..1024                             */
+  double a_scale;         /* input scale: x = A / a_scale (nonzero)              */
+  double j_scale;         /* output scale: I = j_scale y (nonzero)               */
+  float lr, beta1, beta2, eps;  /* Adam hyper-parameters                        */
+} tddft_nn_config;
+
+/* Number of parameters for a window and hidden width. */
+int64_t tddft_nn_num_params(int32_t window, int32_t hidden);
+/* Create with initial parameters (host, n_params floats, copied). Adam's
+ * moments start at zero. EINVAL on bad sizes; ENOMEM/EDEVICE on HIP failure. */
+tddft_status tddft_nn_create(const tddft_nn_config *cfg, const float *params, tddft_nn **out);
+tddft_status tddft_nn_get_params(tddft_nn *nn, float *params);
+/* Replace the parameters and reset Adam's moments and step count. */
+tddft_status tddft_nn_set_params(tddft_nn *nn, const float *params);
+/* y [batch] = network(x [batch][window]) for already scaled inputs. */
+tddft_status tddft_nn_forward(tddft_nn *nn, int32_t batch, const float *x, float *y);
+/* Loss and its gradient (grad may be NULL) for a batch with scaled targets;
+ * the gradient is kept on the device for tddft_nn_adam_step. */
+tddft_status tddft_nn_loss_grad(tddft_nn *nn, int32_t batch, const float *x, const float *target, float *loss,
+                                float *grad);
+/* One Adam step with the gradient of the last tddft_nn_loss_grad. ESTATE if
+ * there is none. */
+tddft_status tddft_nn_adam_step(tddft_nn *nn);
+/* Train on trajectories: A and J are [n_traj][T] raw (unscaled) samples at
+ * the macroscopic times; every (trajectory, t) is one sample whose input is
+ * the window of A ending at t (zeros before the start) and whose target is
+ * J(t). Each epoch visits the samples in an order drawn from `seed` and the
+ * epoch number, in batches of `batch` (the last one may be smaller); one Adam
+ * step per batch. loss_per_epoch (may be NULL) gets each epoch's mean batch
+ * loss. */
+tddft_status tddft_nn_train(tddft_nn *nn, int32_t n_traj, int32_t T, const double *A, const double *J,
+                            int32_t epochs, int32_t batch, uint64_t seed, float *loss_per_epoch);
+const char *tddft_nn_last_error(const tddft_nn *nn);
+void tddft_nn_free(tddft_nn *nn);
+
+/* ---- Multiscale light propagation (Sec. 5) --------------------------------
+ * A(X, t) along one polarisation axis on a 1-D grid X_j = j dx obeys
+ * (1/c^2) d^2A/dt^2 - d^2A/dX^2 = (4 pi / c) I (Eq. Maxwell_ms), leapfrog in
+ * X and t with first-order Mur absorbing ends; an incident wave enters at the
+ * left end (the Mur condition acts on A - A_inc there). The points x0 ..
+ * x0 + n_mat - 1 hold the medium: each is a cell (Eq. TDKS_ms) advanced n_sub
+ * steps of dt / n_sub per macroscopic step, with A interpolated linearly; its
+ * current after the last of them is I there. The medium starts at rest
+ * (I = 0 at t = 0) and the field starts at zero. */
+typedef struct tddft_ms tddft_ms;
+
+typedef struct {
+  int32_t n_x;            /* macroscopic points, >= 4                            */
+  int32_t x0, n_mat;      /* medium: points x0 .. x0 + n_mat - 1, 1 <= x0,
+                             x0 + n_mat <= n_x - 1, n_mat >= 1                   */
+  double dx;              /* grid spacing (bohr)                                 */
+  double dt;              /* macroscopic time step; c dt / dx <= 1               */
+  int32_t n_sub;          /* cell steps per macroscopic step (>= 1); the cell
+                             configuration's dt must equal dt / n_sub           */
+  int32_t axis;           /* polarisation axis in the cell frame: 0, 1 or 2      */
+} tddft_ms_config;
+
+/* Every medium point starts from the same cell: configuration, orbitals
+ * (layout as tddft_init; normally the ground state), local potential and
+ * atoms as for tddft_set_potential. The cells are created when first needed
+ * (at once without a surrogate). */
+tddft_status tddft_ms_create(const tddft_ms_config *cfg, const tddft_config *cell, const double *psi0,
+                             const double *v_loc, int32_t n_atoms, const tddft_atom *atoms, tddft_ms **out);
+/* Couple through a trained network (borrowed; must outlive the run) instead
+ * of the cells. The cells remain the fallback: if |A| at a medium point
+ * exceeds a_max (the trained range), or if every `check_every` steps the
+ * sentinel points, which run full cells alongside, disagree with the network
+ * by more than tol (max |I_net - I_cell| over the interval, relative to the
+ * largest |I_cell| so far), every medium point switches to its cell, which
+ * first replays its A history from t = 0, and the run continues with cells.
+ * sentinels are medium indices (0 .. n_mat - 1). Must precede the first step. */
+tddft_status tddft_ms_attach_surrogate(tddft_ms *ms, tddft_nn *nn, double a_max, int32_t n_sentinel,
+                                       const int32_t *sentinels, int32_t check_every, double tol);
+/* Advance n_macro steps. inc [n_macro + 1][2]: incident A at X_0 and X_1 at
+ * t_n .. t_{n + n_macro} (NULL: none). A_out and I_out (may be NULL):
+ * [n_macro][n_x] after each step. */
+tddft_status tddft_ms_step(tddft_ms *ms, int32_t n_macro, const double *inc, double *A_out, double *I_out);
+/* mode: 0 cells, 1 network; fallbacks taken; the last sentinel error; steps done. */
+tddft_status tddft_ms_status(tddft_ms *ms, int32_t *mode, int32_t *fallbacks, double *last_check,
+                             int32_t *steps_done);
+const char *tddft_ms_last_error(const tddft_ms *ms);
+void tddft_ms_free(tddft_ms *ms);
+
 #ifdef __cplusplus
 }
 #endif

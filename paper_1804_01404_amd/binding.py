@@ -31,7 +31,11 @@ EXPORTED = ["tddft_abi_version", "tddft_init", "tddft_set_potential", "tddft_pro
             "tddft_norms", "tddft_dipole", "tddft_kick", "tddft_ground_state", "tddft_last_timing", "tddft_time_kernel",
             "tddft_last_error", "tddft_free", "tddft_batch_create", "tddft_batch_set_potential",
             "tddft_batch_propagate", "tddft_batch_cell", "tddft_batch_last_timing", "tddft_batch_report",
-            "tddft_batch_last_error", "tddft_batch_free"]
+            "tddft_batch_last_error", "tddft_batch_free", "tddft_nn_num_params", "tddft_nn_create",
+            "tddft_nn_get_params", "tddft_nn_set_params", "tddft_nn_forward", "tddft_nn_loss_grad",
+            "tddft_nn_adam_step", "tddft_nn_train", "tddft_nn_last_error", "tddft_nn_free",
+            "tddft_ms_create", "tddft_ms_attach_surrogate", "tddft_ms_step", "tddft_ms_status",
+            "tddft_ms_last_error", "tddft_ms_free"]
 KERNEL_STAGE, KERNEL_PROJECT, KERNEL_OBSERVE, KERNEL_DENSITY, KERNEL_FUSED = 0, 1, 2, 3, 4
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -52,6 +56,17 @@ class Config(C.Structure):
 class Atom(C.Structure):
     _fields_ = [("npts", C.c_int32), ("n_proj", C.c_int32), ("idx", _ip), ("x", _dp),
                 ("beta", _dp), ("e_kb", _dp)]
+
+
+class NNConfig(C.Structure):
+    _fields_ = [("window", C.c_int32), ("hidden", C.c_int32), ("a_scale", C.c_double),
+                ("j_scale", C.c_double), ("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float),
+                ("eps", C.c_float)]
+
+
+class MSConfig(C.Structure):
+    _fields_ = [("n_x", C.c_int32), ("x0", C.c_int32), ("n_mat", C.c_int32), ("dx", C.c_double),
+                ("dt", C.c_double), ("n_sub", C.c_int32), ("axis", C.c_int32)]
 
 
 class TDDFTError(RuntimeError):
@@ -113,6 +128,37 @@ def load_library(path: str = LIB_PATH):
     lib.tddft_batch_free.restype = None
     for name in ("tddft_batch_create", "tddft_batch_set_potential", "tddft_batch_propagate",
                  "tddft_batch_last_timing", "tddft_batch_report"):
+        getattr(lib, name).restype = C.c_int
+    # learned surrogate and multiscale
+    _fp = C.POINTER(C.c_float)
+    lib.tddft_nn_num_params.argtypes = [C.c_int32, C.c_int32]
+    lib.tddft_nn_num_params.restype = C.c_int64
+    lib.tddft_nn_create.argtypes = [C.POINTER(NNConfig), _fp, C.POINTER(C.c_void_p)]
+    lib.tddft_nn_get_params.argtypes = [C.c_void_p, _fp]
+    lib.tddft_nn_set_params.argtypes = [C.c_void_p, _fp]
+    lib.tddft_nn_forward.argtypes = [C.c_void_p, C.c_int32, _fp, _fp]
+    lib.tddft_nn_loss_grad.argtypes = [C.c_void_p, C.c_int32, _fp, _fp, _fp, _fp]
+    lib.tddft_nn_adam_step.argtypes = [C.c_void_p]
+    lib.tddft_nn_train.argtypes = [C.c_void_p, C.c_int32, C.c_int32, _dp, _dp, C.c_int32, C.c_int32,
+                                   C.c_uint64, _fp]
+    lib.tddft_nn_last_error.argtypes = [C.c_void_p]
+    lib.tddft_nn_last_error.restype = C.c_char_p
+    lib.tddft_nn_free.argtypes = [C.c_void_p]
+    lib.tddft_nn_free.restype = None
+    lib.tddft_ms_create.argtypes = [C.POINTER(MSConfig), C.POINTER(Config), _dp, _dp, C.c_int32,
+                                    C.POINTER(Atom), C.POINTER(C.c_void_p)]
+    lib.tddft_ms_attach_surrogate.argtypes = [C.c_void_p, C.c_void_p, C.c_double, C.c_int32,
+                                              C.POINTER(C.c_int32), C.c_int32, C.c_double]
+    lib.tddft_ms_step.argtypes = [C.c_void_p, C.c_int32, _dp, _dp, _dp]
+    lib.tddft_ms_status.argtypes = [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                    C.POINTER(C.c_double), C.POINTER(C.c_int32)]
+    lib.tddft_ms_last_error.argtypes = [C.c_void_p]
+    lib.tddft_ms_last_error.restype = C.c_char_p
+    lib.tddft_ms_free.argtypes = [C.c_void_p]
+    lib.tddft_ms_free.restype = None
+    for name in ("tddft_nn_create", "tddft_nn_get_params", "tddft_nn_set_params", "tddft_nn_forward",
+                 "tddft_nn_loss_grad", "tddft_nn_adam_step", "tddft_nn_train", "tddft_ms_create",
+                 "tddft_ms_attach_surrogate", "tddft_ms_step", "tddft_ms_status"):
         getattr(lib, name).restype = C.c_int
     if lib.tddft_abi_version() != ABI_VERSION:
         raise RuntimeError("libtddft.so ABI version mismatch")
@@ -436,6 +482,166 @@ class TDDFTBatch:
     def close(self):
         if getattr(self, "h", None):
             self.lib.tddft_batch_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+# ---------------------------------------------------------------------------
+# learned current surrogate and multiscale light propagation
+
+
+def nn_num_params(window: int, hidden: int) -> int:
+    return int(load_library().tddft_nn_num_params(int(window), int(hidden)))
+
+
+def _fptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+class Surrogate:
+    """The current surrogate (tddft_nn_* entry points): FP32 network on the
+    device, trained by the library's forward, backward and Adam kernels."""
+
+    def __init__(self, window, hidden, params, *, a_scale=1.0, j_scale=1.0, lr=1e-3, beta1=0.9,
+                 beta2=0.999, eps=1e-8):
+        self.lib = load_library()
+        self.window, self.hidden = int(window), int(hidden)
+        self.n_params = nn_num_params(window, hidden)
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.shape != (self.n_params,):
+            raise ValueError(f"expected {self.n_params} parameters, got {p.shape}")
+        cfg = NNConfig(window=self.window, hidden=self.hidden, a_scale=float(a_scale),
+                       j_scale=float(j_scale), lr=lr, beta1=beta1, beta2=beta2, eps=eps)
+        self.a_scale, self.j_scale = float(a_scale), float(j_scale)
+        h = C.c_void_p()
+        st = self.lib.tddft_nn_create(C.byref(cfg), _fptr(p), C.byref(h))
+        if st != OK:
+            raise TDDFTError(st, "tddft_nn_create failed")
+        self.h = h
+
+    def _check(self, st):
+        if st != OK:
+            msg = self.lib.tddft_nn_last_error(self.h)
+            raise TDDFTError(st, msg.decode() if msg else "")
+
+    def params(self) -> np.ndarray:
+        out = np.empty(self.n_params, dtype=np.float32)
+        self._check(self.lib.tddft_nn_get_params(self.h, _fptr(out)))
+        return out
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        self._check(self.lib.tddft_nn_set_params(self.h, _fptr(p)))
+
+    def forward(self, x) -> np.ndarray:
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        y = np.empty(x.shape[0], dtype=np.float32)
+        self._check(self.lib.tddft_nn_forward(self.h, x.shape[0], _fptr(x), _fptr(y)))
+        return y
+
+    def loss_grad(self, x, target):
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        t = np.ascontiguousarray(target, dtype=np.float32)
+        loss = np.zeros(1, dtype=np.float32)
+        g = np.empty(self.n_params, dtype=np.float32)
+        self._check(self.lib.tddft_nn_loss_grad(self.h, x.shape[0], _fptr(x), _fptr(t), _fptr(loss), _fptr(g)))
+        return float(loss[0]), g
+
+    def adam_step(self):
+        self._check(self.lib.tddft_nn_adam_step(self.h))
+
+    def train(self, A, J, *, epochs, batch, seed=0):
+        A = np.ascontiguousarray(A, dtype=np.float64)
+        J = np.ascontiguousarray(J, dtype=np.float64)
+        assert A.shape == J.shape and A.ndim == 2
+        losses = np.zeros(max(int(epochs), 1), dtype=np.float32)
+        self._check(self.lib.tddft_nn_train(self.h, A.shape[0], A.shape[1], _ptr(A), _ptr(J), int(epochs),
+                                            int(batch), int(seed), _fptr(losses)))
+        return losses[: int(epochs)]
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.tddft_nn_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+class Multiscale:
+    """Coupled 1-D Maxwell + cells (tddft_ms_* entry points). ``cell`` is a
+    System whose dt is the cell step (dt / n_sub); ``psi0`` its orbitals."""
+
+    def __init__(self, cell, psi0, *, n_x, x0, n_mat, dx, dt, n_sub, axis=2, precision="mixed", flags=0):
+        self.lib = load_library()
+        self.n_x = int(n_x)
+        cfg = MSConfig(n_x=int(n_x), x0=int(x0), n_mat=int(n_mat), dx=float(dx), dt=float(dt),
+                       n_sub=int(n_sub), axis=int(axis))
+        ccfg, keep = _config_for(cell, precision, flags)
+        psi = np.ascontiguousarray(psi0, dtype=np.complex128)
+        v = np.ascontiguousarray(cell.v_loc, dtype=np.float64)
+        atoms, kp = _atoms_for(cell.projectors)
+        h = C.c_void_p()
+        st = self.lib.tddft_ms_create(C.byref(cfg), C.byref(ccfg), _ptr(psi.view(np.float64)), _ptr(v),
+                                      len(cell.projectors), atoms if cell.projectors else None, C.byref(h))
+        if st != OK:
+            raise TDDFTError(st, "tddft_ms_create failed")
+        self.h = h
+
+    def _check(self, st):
+        if st != OK:
+            msg = self.lib.tddft_ms_last_error(self.h)
+            raise TDDFTError(st, msg.decode() if msg else "")
+
+    def attach_surrogate(self, nn, *, a_max, sentinels=(), check_every=50, tol=1e-3):
+        sen = np.ascontiguousarray(sentinels, dtype=np.int32)
+        self._nn = nn
+        self._check(self.lib.tddft_ms_attach_surrogate(self.h, nn.h, float(a_max), sen.shape[0],
+                                                       _ptr(sen, C.c_int32) if sen.shape[0] else None,
+                                                       int(check_every), float(tol)))
+
+    def step(self, n_macro, inc=None):
+        A = np.zeros((int(n_macro), self.n_x))
+        I = np.zeros((int(n_macro), self.n_x))
+        incp = None
+        if inc is not None:
+            inc = np.ascontiguousarray(inc, dtype=np.float64)
+            assert inc.shape == (int(n_macro) + 1, 2)
+            incp = _ptr(inc)
+        self._check(self.lib.tddft_ms_step(self.h, int(n_macro), incp, _ptr(A), _ptr(I)))
+        return A, I
+
+    def status(self) -> dict:
+        mode, fb, steps = C.c_int32(), C.c_int32(), C.c_int32()
+        last = C.c_double()
+        self._check(self.lib.tddft_ms_status(self.h, C.byref(mode), C.byref(fb), C.byref(last),
+                                             C.byref(steps)))
+        return {"mode": "network" if mode.value == 1 else "cells", "fallbacks": fb.value,
+                "last_check": last.value, "steps": steps.value}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.tddft_ms_free(self.h)
             self.h = None
 
     def __del__(self):

@@ -185,4 +185,30 @@ hipError_t launch_apply_lower(const typename Vec2<T>::type* w, const double2* M,
 hipError_t launch_real_part(const double2* src, double* dst, size_t n, hipStream_t s);
 hipError_t launch_fill(double* p, double v, size_t n, hipStream_t s);
 
+// ---- multiscale Maxwell (k_maxwell.hip) -----------------------------------
+hipError_t launch_fdtd_step(const double* A_now, const double* A_prev, const double* I, double* A_new, int n,
+                            double S2, double src, double q, const double inc[4], hipStream_t s);
+hipError_t launch_ring_push(const double* A, int x0, int n_mat, float* ring, int W, int slot, double inv_scale,
+                            hipStream_t s);
+hipError_t launch_ring_windows(const float* ring, int n_mat, int W, int head, float* X, hipStream_t s);
+hipError_t launch_scatter_current(const float* y, int x0, int n_mat, int n, double j_scale, double* I,
+                                  hipStream_t s);
+hipError_t launch_ms_gate(const double* A, int x0, int n_mat, double a_max, int* flag, hipStream_t s);
+
+// ---- current surrogate (k_nn.hip) ------------------------------------------
+struct NNShape {
+  int W, H;
+};
+struct NNWork {  // per-batch activations and gradients, FP32
+  float *h1, *h2, *y, *dy, *dz2, *dz1, *loss;
+};
+hipError_t nn_forward(const NNShape& sh, const float* theta, const float* X, int B, NNWork& wk, hipStream_t s);
+hipError_t nn_backward(const NNShape& sh, const float* theta, const float* X, const float* target, int B,
+                       NNWork& wk, float* grad, hipStream_t s);
+hipError_t nn_adam(float* theta, float* m, float* v, const float* g, long n, float lr, float b1, float b2,
+                   float eps, float c1, float c2, hipStream_t s);
+hipError_t nn_gather(const float* seqA, const float* seqJ, int T, int W, const int* idx, int B, float* X,
+                     float* target, hipStream_t s);
+hipError_t nn_accumulate(const float* src, float* dst, hipStream_t s);
+
 }  // namespace td

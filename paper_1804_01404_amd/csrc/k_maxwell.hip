@@ -1,0 +1,105 @@
+// 1-D wave equation for the vector potential of a normally incident,
+// linearly polarised pulse (Sec. 5, Eq. Maxwell_ms):
+//   (1/c^2) d^2A/dt^2 - d^2A/dX^2 = (4 pi / c) I(X, t),
+// leapfrog in X and t with first-order Mur absorbing ends; the left end lets
+// a prescribed incident wave in (the condition acts on A - A_inc). FP64.
+#include "internal.h"
+
+namespace td {
+
+// interior update at point j
+__device__ __forceinline__ double leap(const double* __restrict__ A_now, const double* __restrict__ A_prev,
+                                       const double* __restrict__ I, int j, double S2, double src) {
+  return 2.0 * A_now[j] - A_prev[j] + S2 * (A_now[j + 1] - 2.0 * A_now[j] + A_now[j - 1]) + src * I[j];
+}
+
+// One macroscopic step for all points. inc = (A_inc(X_0, t_n), A_inc(X_1, t_n),
+// A_inc(X_0, t_{n+1}), A_inc(X_1, t_{n+1})). The end points recompute their
+// inner neighbour's new value, so one launch suffices.
+__global__ void k_fdtd_step(const double* __restrict__ A_now, const double* __restrict__ A_prev,
+                            const double* __restrict__ I, double* __restrict__ A_new, int n, double S2,
+                            double src, double q, double4 inc) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  if (j > 0 && j < n - 1) {
+    A_new[j] = leap(A_now, A_prev, I, j, S2, src);
+  } else if (j == 0) {
+    const double a1 = leap(A_now, A_prev, I, 1, S2, src);
+    A_new[0] = inc.z + (A_now[1] - inc.y) + q * ((a1 - inc.w) - (A_now[0] - inc.x));
+  } else {
+    const double an = leap(A_now, A_prev, I, n - 2, S2, src);
+    A_new[n - 1] = A_now[n - 2] + q * (an - A_now[n - 1]);
+  }
+}
+
+// Append A(X_{x0+m}, t_n) / a_scale to each material point's window ring
+// (FP32, [n_mat][W]) at slot `slot`.
+__global__ void k_ring_push(const double* __restrict__ A, int x0, int n_mat, float* __restrict__ ring, int W,
+                            int slot, double inv_scale) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= n_mat) return;
+  ring[(size_t)m * W + slot] = (float)(A[x0 + m] * inv_scale);
+}
+
+// Causal windows from the rings: X[m][w] = ring[m][(head + 1 + w) mod W],
+// oldest first, where `head` is the slot written last.
+__global__ void k_ring_windows(const float* __restrict__ ring, int n_mat, int W, int head, float* __restrict__ X) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_mat * W) return;
+  const int m = t / W, w = t - m * W;
+  int s = head + 1 + w;
+  if (s >= W) s -= W;
+  X[t] = ring[(size_t)m * W + s];
+}
+
+// I(X_{x0+m}) = j_scale * y[m]; zero outside the material
+__global__ void k_scatter_current(const float* __restrict__ y, int x0, int n_mat, int n, double j_scale,
+                                  double* __restrict__ I) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const int m = j - x0;
+  I[j] = (m >= 0 && m < n_mat) ? j_scale * (double)y[m] : 0.0;
+}
+
+// amplitude gate of the surrogate: flag = 1 if |A| exceeds a_max at a medium
+// point (every writer stores the same value)
+__global__ void k_ms_gate(const double* __restrict__ A, int x0, int n_mat, double a_max, int* __restrict__ flag) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= n_mat) return;
+  if (!(fabs(A[x0 + m]) <= a_max)) flag[0] = 1;
+}
+
+hipError_t launch_ms_gate(const double* A, int x0, int n_mat, double a_max, int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_ms_gate, dim3((unsigned)((n_mat + 255) / 256)), dim3(256), 0, s, A, x0, n_mat, a_max, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_fdtd_step(const double* A_now, const double* A_prev, const double* I, double* A_new, int n,
+                            double S2, double src, double q, const double inc[4], hipStream_t s) {
+  const double4 iv = make_double4(inc[0], inc[1], inc[2], inc[3]);
+  hipLaunchKernelGGL(k_fdtd_step, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, A_now, A_prev, I, A_new, n,
+                     S2, src, q, iv);
+  return hipGetLastError();
+}
+
+hipError_t launch_ring_push(const double* A, int x0, int n_mat, float* ring, int W, int slot, double inv_scale,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_ring_push, dim3((unsigned)((n_mat + 255) / 256)), dim3(256), 0, s, A, x0, n_mat, ring, W,
+                     slot, inv_scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_ring_windows(const float* ring, int n_mat, int W, int head, float* X, hipStream_t s) {
+  const int n = n_mat * W;
+  hipLaunchKernelGGL(k_ring_windows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, ring, n_mat, W, head, X);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_current(const float* y, int x0, int n_mat, int n, double j_scale, double* I,
+                                  hipStream_t s) {
+  hipLaunchKernelGGL(k_scatter_current, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, y, x0, n_mat, n,
+                     j_scale, I);
+  return hipGetLastError();
+}
+
+}  // namespace td

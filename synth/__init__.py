@@ -30,5 +30,7 @@ from .configs import (  # noqa: F401
     single_cell_config,
     batch_cells,
     multiscale_cell,
+    surrogate_init,
+    random_pulse_tables,
     CONFIG_NAMES,
 )

@@ -136,3 +136,38 @@ def multiscale_cell(*, nk=4, n=16, n_orb=16, dt=0.08, nsteps=0, with_orbitals=Tr
         kpts=kpts, kw=kw, atoms=diamond_positions(L), rng=rng, n_proj=4, dt=dt,
         nsteps=nsteps, A=np.zeros((nsteps + 1, 3)), precision=precision,
         with_orbitals=with_orbitals, seed_index=4)
+
+
+def surrogate_init(window: int, hidden: int, seed: int) -> np.ndarray:
+    """Seeded initial parameters of the current surrogate, float32, in the
+    library's flat layout W1 [H][W], b1 [H], W2 [H][H], b2 [H], w3 [H], b3,
+    ws [W]: Glorot-uniform dense weights, zero biases, zero skip weights."""
+    rng = rng_for(7, seed)
+    W, H = int(window), int(hidden)
+
+    def glorot(fan_out, fan_in):
+        lim = np.sqrt(6.0 / (fan_in + fan_out))
+        return rng.uniform(-lim, lim, size=(fan_out, fan_in))
+    parts = [glorot(H, W), np.zeros(H), glorot(H, H), np.zeros(H), glorot(1, H)[0], np.zeros(1), np.zeros(W)]
+    return np.concatenate([np.ravel(p) for p in parts]).astype(np.float32)
+
+
+def random_pulse_tables(n_traj: int, n_macro: int, dt_macro: float, seed: int, *,
+                        e0_range=(1e-4, 1e-2), ev_range=(0.5, 3.0), t_range=(40.0, 200.0)):
+    """Seeded training fields for the surrogate: per trajectory a cos^2
+    pulse (log-uniform peak field, uniform photon energy in eV, duration in
+    a.u., carrier-envelope phase) sampled at the macroscopic times
+    t_0 .. t_{n_macro - 1}; returns A [n_traj][n_macro] along one axis and
+    the pulse parameters."""
+    rng = rng_for(8, seed)
+    out = np.empty((n_traj, n_macro))
+    params = []
+    for i in range(n_traj):
+        E0 = float(np.exp(rng.uniform(np.log(e0_range[0]), np.log(e0_range[1]))))
+        omega = float(rng.uniform(*ev_range)) * EV
+        T = float(rng.uniform(*t_range))
+        cep = float(rng.uniform(0.0, 1.0))
+        tab = cos2_pulse_table(n_macro - 1, dt_macro, E0, omega, T, cep, [1.0, 0.0, 0.0])
+        out[i] = tab[:, 0]
+        params.append((E0, omega, T, cep))
+    return out, params

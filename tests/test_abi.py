@@ -42,6 +42,44 @@ def test_struct_layout_matches_header(tmp_path):
                    binding.Config.stream.offset, binding.Atom.beta.offset]
 
 
+def test_surrogate_and_multiscale_struct_layouts(tmp_path):
+    from paper_1804_01404_amd import binding
+    src = tmp_path / "sz2.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "tddft.h"\n'
+                   'int main(){printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(tddft_nn_config),'
+                   ' offsetof(tddft_nn_config, j_scale), offsetof(tddft_nn_config, eps),'
+                   ' sizeof(tddft_ms_config), offsetof(tddft_ms_config, dx), offsetof(tddft_ms_config, axis));'
+                   'return 0;}\n')
+    exe = tmp_path / "sz2"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
+    assert got == [C.sizeof(binding.NNConfig), binding.NNConfig.j_scale.offset, binding.NNConfig.eps.offset,
+                   C.sizeof(binding.MSConfig), binding.MSConfig.dx.offset, binding.MSConfig.axis.offset]
+
+
+def test_surrogate_and_multiscale_reject_bad_arguments_without_device():
+    from paper_1804_01404_amd import binding
+    lib = binding.load_library()
+    assert lib.tddft_nn_num_params(7, 5) == 5 * 7 + 5 + 25 + 5 + 5 + 1 + 7
+    h = C.c_void_p()
+    cfg = binding.NNConfig(window=0, hidden=4, a_scale=1.0, j_scale=1.0, lr=1e-3, beta1=0.9, beta2=0.999,
+                           eps=1e-8)
+    p = np.zeros(10, dtype=np.float32)
+    assert lib.tddft_nn_create(C.byref(cfg), p.ctypes.data_as(C.POINTER(C.c_float)), C.byref(h)) == binding.EINVAL
+    assert not h.value
+    ccfg, keep = _cfg(dt=0.02)
+    for bad in (dict(n_x=3), dict(x0=0), dict(n_mat=40), dict(dt=1.0), dict(n_sub=3), dict(axis=3)):
+        kw = dict(n_x=40, x0=5, n_mat=10, dx=50.0, dt=0.08, n_sub=4, axis=2)
+        kw.update(bad)
+        mcfg = binding.MSConfig(**kw)
+        psi = np.zeros(2 * 16 ** 3 * 2)
+        v = np.zeros(16 ** 3)
+        st = lib.tddft_ms_create(C.byref(mcfg), C.byref(ccfg), psi.ctypes.data_as(C.POINTER(C.c_double)),
+                                 v.ctypes.data_as(C.POINTER(C.c_double)), 0, None, C.byref(h))
+        assert st == binding.EINVAL, bad
+        assert not h.value
+
+
 def _cfg(**kw):
     from paper_1804_01404_amd import binding
     cfg = binding.Config()
