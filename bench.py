@@ -126,6 +126,74 @@ def cpu_baseline(system, target_s=12.0):
                       f"{el:.1f} s, NumPy FP64 with one BLAS thread"}
 
 
+def bench_batch(steps=30, warmup=8):
+    """The uneven-batch path on 64 seeded cells (grids 12..32, up to 32
+    orbitals and 8 k-points each: the 64-cell workload with the orbital and
+    k-point ranges cut so that the host can generate the initial orbitals in
+    seconds), mixed and complex128."""
+    import torch
+    import synth
+    from paper_1804_01404_amd.binding import TDDFTBatch
+    cells = synth.batch_cells(64, nsteps=warmup + steps, max_orb=32, max_k=8)
+    og = sum(c.og for c in cells)
+    out = {"workload": "batch-64cells: 64 periodic cells, grids {12,16,20,24,32}^3 at h 0.55, "
+                       "8-32 orbitals, 1-8 k-points, 2-16 atoms, own cos^2 pulse each, dt 0.02",
+           "og_per_step": og}
+    for prec in ("mixed", "c128"):
+        with TDDFTBatch(cells, precision=prec) as b:
+            b.propagate([c.A[: warmup + 1] for c in cells])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            b.propagate([c.A[warmup: warmup + steps + 1] for c in cells])
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            out[prec] = {"value": og * steps / el, "ms_per_step": el / steps * 1e3,
+                         "device_ms_per_step": b.last_timing_ms()}
+    out["speedup_mixed_over_c128"] = out["mixed"]["value"] / out["c128"]["value"]
+    return out
+
+
+def bench_multiscale():
+    """Learned multiscale coupling: a 16-point slab of 12^3 diamond-like cells
+    (8 orbitals, 2^3 k-points, ground state) under a 1.55 eV pulse, run with a
+    cell at every point (complex128 and mixed) and through the trained
+    surrogate with two sentinel cells; the network is trained here by the
+    library's kernels on 48 batch-path trajectories."""
+    import numpy as np
+    import synth
+    from paper_1804_01404_amd import pipeline
+    n_sub, dt, T = 4, 0.32, 300
+    cell = synth.multiscale_cell(nk=2, n=12, n_orb=8, dt=dt / n_sub)
+    psi, _ = pipeline.ground_state(cell, n_iter=3000, tau=0.06)
+    A_tr = synth.random_field_tables(48, T, dt, 1, a_max=12.0)
+    J_tr, t_gen = pipeline.trajectories(cell, psi, A_tr, n_sub=n_sub, axis=0)
+    a_scale, j_scale = float(np.abs(A_tr).max()), float(np.abs(J_tr).max())
+    t0 = time.perf_counter()
+    nn, losses = pipeline.train(A_tr, J_tr, synth.surrogate_init(T, 16, 1), window=T, hidden=16,
+                                a_scale=a_scale, j_scale=j_scale, epochs=150, batch=256, seed=1, lr=2e-3)
+    t_train = time.perf_counter() - t0
+    dx, n_mat, n_vac = 147.6, 16, 12
+    n_x = n_mat + 2 * n_vac
+    inc = synth.incident_table(T, dt, dx, delay=0.0, E0=3e-3, omega=1.55 / 27.211386245988, T=100.0)
+    kw = dict(n_x=n_x, x0=n_vac, n_mat=n_mat, dx=dx, dt=dt, n_sub=n_sub, axis=0)
+    A64, _, t64, _ = pipeline.run_slab(cell, psi, inc, precision="c128", **kw)
+    A32, _, t32, _ = pipeline.run_slab(cell, psi, inc, precision="mixed", **kw)
+    with nn:
+        An, _, tn, st = pipeline.run_slab(cell, psi, inc, precision="mixed", nn=nn, a_max=a_scale,
+                                          sentinels=[0, n_mat // 2], check_every=50, tol=0.1, **kw)
+    ref = np.max(np.abs(A64))
+    og_run = cell.og * n_mat * T * n_sub
+    return {"workload": f"slab of {n_mat} cells (12^3, 8 orbitals, 8 k-points) + {2 * n_vac} vacuum "
+                        f"points, dX 147.6, dt 0.32 = 4 cell steps, {T} steps, 1.55 eV pulse E0 3e-3",
+            "cells_c128_s": t64, "cells_mixed_s": t32, "surrogate_s": tn,
+            "cells_c128_og_steps_per_s": og_run / t64, "cells_mixed_og_steps_per_s": og_run / t32,
+            "speedup_surrogate_over_c128_cells": t64 / tn, "speedup_mixed_over_c128_cells": t64 / t32,
+            "field_error_mixed_cells": float(np.max(np.abs(A32 - A64)) / ref),
+            "field_error_surrogate": float(np.max(np.abs(An - A64)) / ref),
+            "surrogate_status": st, "train_s": t_train, "trajectories_s": t_gen,
+            "loss_first_last": [float(losses[0]), float(losses[-1])]}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -134,6 +202,8 @@ def main():
     ap.add_argument("--precision", default="mixed", choices=["mixed", "c128"])
     ap.add_argument("--no-twin", action="store_true", help="skip the complex128 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the uneven-batch line")
+    ap.add_argument("--no-multiscale", action="store_true", help="skip the learned multiscale line")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="also run a plain device copy of this many MB (a known-size "
                          "reference for the HBM byte counters of a profiler run)")
@@ -224,6 +294,10 @@ def main():
         out["twin"] = {"precision": other, "value": og / (ms2 * 1e-3), "ms_per_step": ms2,
                        "kernels_ms": kern2,
                        "stage_GBs": 3 * (16 if other == "c128" else 8) * og / (kern2["stage_ms"] * 1e-3) / 1e9}
+    if not args.no_batch:
+        out["batched"] = bench_batch()
+    if not args.no_multiscale:
+        out["multiscale"] = bench_multiscale()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(s)
     print(json.dumps(out), flush=True)

@@ -158,9 +158,11 @@ tddft_status tddft_kick(tddft_ctx *ctx, double F0, int32_t axis);
  * potential frozen at the current density, orthonormalises the orbitals of
  * every k-point (Gram-Schmidt in orbital order, as Cholesky-QR applied twice)
  * and rebuilds the density and the Hartree + xc potential. tau > 0 with
- * tau * lambda_max(h) <= 2.7, else EUNSTABLE (the damping polynomial must
- * stay below one). energies (may be NULL) receives the total energy after
- * each iteration. The final density becomes rho_0 of the dipole. */
+ * tau * lambda_max(h) <= 1.59, else EUNSTABLE (the damping polynomial
+ * P4(-x) must decrease over the whole spectrum, so that every mode is damped
+ * more than every lower one). energies (may be NULL) receives the total
+ * energy after each iteration. The final density becomes rho_0 of the
+ * dipole. */
 tddft_status tddft_ground_state(tddft_ctx *ctx, int32_t n_iter, double tau, double *energies);
 
 /* Mean device time per step of the last propagate, from HIP events (ms). */
@@ -302,7 +304,7 @@ tddft_status tddft_ms_create(const tddft_ms_config *cfg, const tddft_config *cel
  * exceeds a_max (the trained range), or if every `check_every` steps the
  * sentinel points, which run full cells alongside, disagree with the network
  * by more than tol (max |I_net - I_cell| over the interval, relative to the
- * largest |I_cell| so far), every medium point switches to its cell, which
+ * network's output scale |j_scale|), every medium point switches to its cell, which
  * first replays its A history from t = 0, and the run continues with cells.
  * sentinels are medium indices (0 .. n_mat - 1). Must precede the first step. */
 tddft_status tddft_ms_attach_surrogate(tddft_ms *ms, tddft_nn *nn, double a_max, int32_t n_sentinel,

@@ -71,33 +71,6 @@ def em_energy(A_now, A_prev, dx, dt):
     return (np.sum(E * E) + np.sum(B * B)) * dx / (8.0 * math.pi)
 
 
-def cos2_pulse_potential(tau, E0, omega, T):
-    """A(tau) = -c int_0^tau E for E(t) = E0 sin^2(pi t/T) sin(omega t) on
-    0 < t < T (Eq. pulse of Sec. 3.1 with a sine carrier), constant after T,
-    zero before 0; closed form of the integral."""
-    p = math.pi / T
-    tau = np.clip(np.asarray(tau, dtype=np.float64), 0.0, T)
-
-    def prim(t):
-        out = -0.5 * np.cos(omega * t) / omega
-        out = out + 0.25 * np.cos((omega + 2 * p) * t) / (omega + 2 * p)
-        wm = omega - 2 * p
-        if abs(wm) > 1e-12:
-            out = out + 0.25 * np.cos(wm * t) / wm
-        return out
-    return -C_LIGHT * E0 * (prim(tau) - prim(0.0))
-
-
-def incident_table(n_macro, dt, dx, delay, E0, omega, T):
-    """Incident A at X_0 = 0 and X_1 = dX for t_0 .. t_{n_macro}: the pulse
-    travels towards +X and reaches X = 0 at t = delay."""
-    t = np.arange(n_macro + 1) * dt
-    out = np.empty((n_macro + 1, 2))
-    out[:, 0] = cos2_pulse_potential(t - delay, E0, omega, T)
-    out[:, 1] = cos2_pulse_potential(t - delay - dx / C_LIGHT, E0, omega, T)
-    return out
-
-
 class Multiscale:
     """Coupled Maxwell + microscopic cells (Sec. 5). ``cells`` are objects with
     ``propagate(A_table) -> J`` (the oracle's TDKS); the material occupies the

@@ -79,6 +79,7 @@ struct tddft_ctx {
   // per step
   double *kappa = nullptr, *kappaJ = nullptr, *efield = nullptr, *Alast = nullptr;
   double* coef = nullptr;  // [n_k][kCoef] in the stage precision (fused step)
+  double2* gram = nullptr;  // [2][n_k][n_orb][n_orb] overlap and its inverse factor (ground state)
   double2 *phA = nullptr, *phAJ = nullptr;
   double* obs = nullptr;
   double *Atab = nullptr, *Jtab = nullptr;
@@ -633,7 +634,7 @@ bool chol_inverse(const std::vector<double2>& S, int n, std::vector<double2>& M)
 template <typename T>
 tddft_status orthonormalise(tddft_ctx* c) {
   const int n = c->cfg.n_orb, nk = c->cfg.n_k, N = (int)c->N;
-  double2* dS = reinterpret_cast<double2*>(c->rho_part);  // n_k n_orb^2 complex fits: checked by caller
+  double2* dS = c->gram;
   double2* dM = dS + (size_t)nk * n * n;
   std::vector<double2> S((size_t)nk * n * n), M((size_t)nk * n * n), Mk;
   for (int pass = 0; pass < 2; ++pass) {
@@ -1226,10 +1227,16 @@ tddft_status tddft_ground_state(tddft_ctx* c, int32_t n_iter, double tau, double
   if (!c->potential_set) return fail(c, TDDFT_ESTATE, "ground_state before set_potential");
   if (n_iter < 0 || !(tau > 0.0) || !std::isfinite(tau)) return fail(c, TDDFT_EINVAL, "bad ground-state arguments");
   const double lam = spectral_bound(c, 0.0, -c->vabs, c->vabs);
-  if (tau * lam > 2.7) return fail(c, TDDFT_EUNSTABLE, "tau * lambda_max > 2.7: the imaginary-time step would grow");
+  // P4(-x) = 1 - x + x^2/2 - x^3/6 + x^4/24 decreases monotonically only up to
+  // x = 1.596 (where P4'(-x) = 0); beyond it high modes are damped less than
+  // lower ones and the iteration can settle on the wrong subspace
+  if (tau * lam > 1.59)
+    return fail(c, TDDFT_EUNSTABLE, "tau * lambda_max > 1.59: the damping polynomial is not monotone there");
   const int n = c->cfg.n_orb;
-  if ((size_t)2 * c->cfg.n_k * n * n * 2 > (size_t)c->rho_nchunks * c->N)
-    return fail(c, TDDFT_EINVAL, "too many orbitals per k-point for the Gram workspace");
+  if (!c->gram) {
+    tddft_status st = dalloc_t(c, (size_t)2 * c->cfg.n_k * n * n, &c->gram);
+    if (st != TDDFT_OK) return st;
+  }
   invalidate_graph(c);
   for (int i = 0; i < 3; ++i) c->A_last[i] = 0.0;
   double Ab[6] = {0, 0, 0, 0, 0, 0};

@@ -280,7 +280,7 @@ struct tddft_ms {
   std::vector<double> hist;  // cells mode: medium A at t_0 .. t_steps, [steps + 1][n_mat]
   // surrogate mode
   tddft_nn* nn = nullptr;
-  double a_max = 0, tol = 0, imax_sent = 0;
+  double a_max = 0, tol = 0;
   std::vector<int> sentinels;
   int check_every = 0, checked_to = 0;
   float *ring = nullptr, *Xw = nullptr;
@@ -445,10 +445,11 @@ tddft_status ms_check(tddft_ms* ms, bool* trip) {
   for (int s = s0; s < s1; ++s)
     for (int c = 0; c < nc; ++c) {
       const double ic = Ic[(size_t)(s - s0) * nc + c];
-      ms->imax_sent = std::max(ms->imax_sent, std::fabs(ic));
       err = std::max(err, std::fabs(In[(size_t)(s + 1) * nm + ms->sentinels[c]] - ic));
     }
-  ms->last_check = err / std::max(ms->imax_sent, 1e-300);
+  // relative to the network's output scale: early in a run the cells' current
+  // is near zero and a ratio to it would flag rounding-size differences
+  ms->last_check = err / std::fabs(ms->nn->cfg.j_scale);
   ms->checked_to = s1;
   if (!(ms->last_check <= ms->tol)) *trip = true;
   return TDDFT_OK;

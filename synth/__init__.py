@@ -32,5 +32,8 @@ from .configs import (  # noqa: F401
     multiscale_cell,
     surrogate_init,
     random_pulse_tables,
+    random_field_tables,
+    cos2_pulse_potential,
+    incident_table,
     CONFIG_NAMES,
 )

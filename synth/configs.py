@@ -20,6 +20,8 @@ batch add their cell number).
 """
 from __future__ import annotations
 
+import math
+
 import numpy as np
 
 from .systems import (C_AU, System, build_system, cos2_pulse_table, diamond_positions,
@@ -171,3 +173,68 @@ def random_pulse_tables(n_traj: int, n_macro: int, dt_macro: float, seed: int, *
         out[i] = tab[:, 0]
         params.append((E0, omega, T, cep))
     return out, params
+
+
+def random_field_tables(n_traj: int, n_macro: int, dt_macro: float, seed: int, *, a_max=10.0,
+                        ev_range=(0.3, 4.0)):
+    """Seeded, varied training fields for the surrogate, A [n_traj][n_macro]
+    along one axis at the macroscopic times: in turn a cos^2 pulse of random
+    duration (10..150 a.u.), photon energy, phase and peak; a smoothed step
+    (an impulsive kick) at a random time; and a superposition of 12 random
+    short pulses (a broadband field). Peaks of |A| are log-uniform in
+    [a_max / 100, a_max]; every field is zero at t_0."""
+    rng = rng_for(9, seed)
+    t = np.arange(n_macro) * dt_macro
+    out = np.zeros((n_traj, n_macro))
+    for i in range(n_traj):
+        kind = i % 3
+        if kind == 0:
+            T = float(rng.uniform(10.0, 150.0))
+            om = float(rng.uniform(*ev_range)) * EV
+            t0 = float(rng.uniform(0.0, 0.3)) * t[-1]
+            env = np.where((t > t0) & (t < t0 + T), np.sin(np.pi * (t - t0) / T) ** 2, 0.0)
+            a = env * np.sin(om * (t - t0) + 2 * np.pi * rng.uniform())
+        elif kind == 1:
+            t0 = float(rng.uniform(0.05, 0.6)) * t[-1]
+            w = float(rng.uniform(0.5, 3.0))
+            a = 0.5 * (1.0 + np.tanh((t - t0) / w))
+            a -= a[0]
+        else:
+            a = np.zeros(n_macro)
+            for _ in range(12):
+                T = float(rng.uniform(5.0, 40.0))
+                om = float(rng.uniform(*ev_range)) * EV
+                t0 = float(rng.uniform(0.0, 0.9)) * t[-1]
+                env = np.where((t > t0) & (t < t0 + T), np.sin(np.pi * (t - t0) / T) ** 2, 0.0)
+                a += rng.normal() * env * np.sin(om * (t - t0) + 2 * np.pi * rng.uniform())
+        peak = float(np.exp(rng.uniform(np.log(a_max / 100.0), np.log(a_max))))
+        m = np.max(np.abs(a))
+        out[i] = a * (peak / m) if m > 0 else a
+    return out
+
+
+def cos2_pulse_potential(tau, E0, omega, T):
+    """A(tau) = -c int_0^tau E for E(t) = E0 sin^2(pi t/T) sin(omega t) on
+    0 < t < T (Eq. pulse of Sec. 3.1 with a sine carrier), constant after T,
+    zero before 0; closed form of the integral."""
+    p = math.pi / T
+    tau = np.clip(np.asarray(tau, dtype=np.float64), 0.0, T)
+
+    def prim(t):
+        out = -0.5 * np.cos(omega * t) / omega
+        out = out + 0.25 * np.cos((omega + 2 * p) * t) / (omega + 2 * p)
+        wm = omega - 2 * p
+        if abs(wm) > 1e-12:
+            out = out + 0.25 * np.cos(wm * t) / wm
+        return out
+    return -C_AU * E0 * (prim(tau) - prim(0.0))
+
+
+def incident_table(n_macro, dt, dx, delay, E0, omega, T):
+    """Incident A at X_0 = 0 and X_1 = dX for t_0 .. t_{n_macro}: the pulse
+    travels towards +X and reaches X = 0 at t = delay."""
+    t = np.arange(n_macro + 1) * dt
+    out = np.empty((n_macro + 1, 2))
+    out[:, 0] = cos2_pulse_potential(t - delay, E0, omega, T)
+    out[:, 1] = cos2_pulse_potential(t - delay - dx / C_AU, E0, omega, T)
+    return out

@@ -42,7 +42,7 @@ def _small_cell(boundary="periodic"):
 @pytest.mark.parametrize("boundary", ["periodic", "isolated"])
 def test_ground_state_iterations_match_oracle(boundary):
     s = _small_cell(boundary)
-    tau, n_iter = 0.03, 6
+    tau, n_iter = 0.025, 6
     E, psi, rho = _gpu_ground_state(s, n_iter, tau, "c128")
     o = tdks.TDKS.from_system(s)
     Eo = o.ground_state(n_iter, tau)
@@ -53,7 +53,7 @@ def test_ground_state_iterations_match_oracle(boundary):
 
 def test_ground_state_diamond16_matches_oracle():
     s = synth.single_cell_config(0, nsteps=1)
-    tau, n_iter = 0.04, 4
+    tau, n_iter = 0.035, 4
     E, psi, rho = _gpu_ground_state(s, n_iter, tau, "c128")
     o = tdks.TDKS.from_system(s)
     Eo = o.ground_state(n_iter, tau)
@@ -86,7 +86,7 @@ def test_converged_ground_state_is_stationary():
     announce("ground state then field-free run")
     with TDDFT(s, precision="c128") as t:
         t.set_potential()
-        E = t.ground_state(800, 0.03)
+        E = t.ground_state(1500, 0.02)
         rho0, _ = t.density_current()
         J = t.propagate(np.zeros((41, 3)))
         rho1, _ = t.density_current()

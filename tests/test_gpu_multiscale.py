@@ -17,6 +17,8 @@ import math
 import numpy as np
 import pytest
 
+import synth
+
 from oracle import maxwell, surrogate, tdks
 from oracle_helpers import tiny_periodic
 from synth.systems import build_system, rng_for
@@ -57,7 +59,7 @@ def test_free_electron_slab_matches_oracle():
     dt = 0.6 * dx / C
     s = _free_electron_system(dt / n_sub)
     steps = 30
-    inc = maxwell.incident_table(steps, dt, dx, delay=0.0, E0=5e-3, omega=0.2, T=12.0)
+    inc = synth.incident_table(steps, dt, dx, delay=0.0, E0=5e-3, omega=0.2, T=12.0)
     announce("multiscale free-electron slab vs oracle")
     A, I, st = _gpu_ms(s, n_x, x0, n_mat, dx, dt, n_sub, 2, steps, inc)
     Ao, Io = _oracle_ms(s, n_x, x0, n_mat, dx, dt, n_sub, 2, steps, inc)
@@ -76,7 +78,7 @@ def test_pseudopotential_cells_match_oracle():
                       dt=dt / n_sub, real=False, seed=5502)
     s.precision = "c128"
     steps = 10
-    inc = maxwell.incident_table(steps, dt, dx, delay=0.0, E0=2e-2, omega=0.6, T=4.0)
+    inc = synth.incident_table(steps, dt, dx, delay=0.0, E0=2e-2, omega=0.6, T=4.0)
     announce("multiscale pseudopotential cells vs oracle")
     A, I, _ = _gpu_ms(s, n_x, x0, n_mat, dx, dt, n_sub, 0, steps, inc)
     Ao, Io = _oracle_ms(s, n_x, x0, n_mat, dx, dt, n_sub, 0, steps, inc)
@@ -139,7 +141,7 @@ def test_amplitude_gate_fallback_reproduces_cells_run():
     dt = 0.6 * dx / C
     s = _free_electron_system(dt / n_sub)
     steps = 20
-    inc = maxwell.incident_table(steps, dt, dx, delay=0.0, E0=5e-3, omega=0.2, T=12.0)
+    inc = synth.incident_table(steps, dt, dx, delay=0.0, E0=5e-3, omega=0.2, T=12.0)
     A_ref, I_ref, _ = _gpu_ms(s, n_x, x0, n_mat, dx, dt, n_sub, 2, steps, inc)
     nn, _ = _net(6605)
     announce("multiscale amplitude-gate fallback")
@@ -159,7 +161,7 @@ def test_sentinel_check_trips_on_an_untrained_network():
     dt = 0.6 * dx / C
     s = _free_electron_system(dt / n_sub)
     steps = 24
-    inc = maxwell.incident_table(steps, dt, dx, delay=0.0, E0=5e-3, omega=0.2, T=12.0)
+    inc = synth.incident_table(steps, dt, dx, delay=0.0, E0=5e-3, omega=0.2, T=12.0)
     nn, _ = _net(6606, a_scale=1e-2, j_scale=1e-6)
     announce("multiscale sentinel fallback")
     with nn, Multiscale(s, s.psi0, n_x=n_x, x0=x0, n_mat=n_mat, dx=dx, dt=dt, n_sub=n_sub, axis=2,
