@@ -95,17 +95,23 @@ def stored_traffic(kernel_source, kernel_name, workload):
 
 def cpu_baseline(system, target_s=12.0):
     """The oracle as it stands, on a bounded sample: the same cell, grid,
-    orbitals and projectors with a subset of the k-points, one BLAS thread."""
+    orbitals and projectors with a subset of the k-points, one BLAS thread.
+    The same sample then runs on the GPU (complex128 and mixed) and the
+    errors against the oracle's steps are reported beside the timing."""
+    import copy
     import numpy as np
     from threadpoolctl import threadpool_limits
     from oracle import tdks
+    from paper_1804_01404_amd.binding import TDDFT
     s = system
     nk = 2
+
+    def make(nk):
+        return tdks.TDKS(s.n, s.cell, s.boundary, s.kpts[:nk], np.full(nk, 1.0 / nk), s.psi0[:nk], s.dt,
+                         s.v_loc, s.projectors, hartree=s.hartree, xc=s.xc, gauge=s.gauge)
     with threadpool_limits(limits=1):
         while True:
-            kw = np.full(nk, 1.0 / nk)
-            o = tdks.TDKS(s.n, s.cell, s.boundary, s.kpts[:nk], kw, s.psi0[:nk], s.dt, s.v_loc,
-                          s.projectors, hartree=s.hartree, xc=s.xc, gauge=s.gauge)
+            o = make(nk)
             t0 = time.perf_counter()
             o.step(s.A[0], s.A[1])
             o.current()
@@ -114,16 +120,82 @@ def cpu_baseline(system, target_s=12.0):
                 break
             nk = min(s.n_k, max(nk + 1, int(nk * target_s / (3 * one))))
         steps = max(1, min(5, int(target_s / max(one, 1e-3))))
+        o = make(nk)
+        J_o = np.empty((steps, 3))
         t0 = time.perf_counter()
         for n in range(steps):
             o.step(s.A[n], s.A[n + 1])
-            o.current()
+            J_o[n] = o.current()
         el = time.perf_counter() - t0
     og = s.n_orb * nk * s.n_grid
+    sub = copy.copy(s)
+    sub.kpts = s.kpts[:nk]
+    sub.kw = np.full(nk, 1.0 / nk)
+    sub.psi0 = s.psi0[:nk]
+    parity = {}
+    for prec in ("c128", "mixed"):
+        with TDDFT(sub, precision=prec) as t:
+            t.set_potential()
+            J = t.propagate(s.A[:steps + 1])
+            rho, _ = t.density_current()
+        parity[prec] = {"density_l2_error": float(np.linalg.norm(rho - o.rho) / np.linalg.norm(o.rho)),
+                        "current_error": float(np.max(np.abs(J - J_o)) / np.max(np.abs(J_o)))}
     return {"value": og * steps / el, "unit": "og-steps/s", "cores": 1, "kind": "oracle",
             "sample": f"{nk} of {s.n_k} k-points x {s.n_orb} orbitals x {s.n_grid} points, "
                       f"{steps} full steps (Taylor + density + current + Hartree + LDA), "
-                      f"{el:.1f} s, NumPy FP64 with one BLAS thread"}
+                      f"{el:.1f} s, NumPy FP64 with one BLAS thread",
+            "gpu_vs_oracle_on_sample": parity}
+
+
+def accuracy_report():
+    """Errors of the mixed path against the complex128 path over 1000 steps
+    (the complex128 path is pinned to the oracle by the parity tests and by
+    the cpu_baseline leg), and the field-free energy drift per 1000 steps
+    from the ground state, both precisions."""
+    import numpy as np
+    import synth
+    from paper_1804_01404_amd.binding import TDDFT
+
+    def run(s, prec, psi=None, every=0):
+        with TDDFT(s, precision=prec) as t:
+            t.set_potential()
+            if psi is not None:
+                t.set_orbitals(psi)
+            Es = [t.energy()]
+            J = None
+            if every:
+                for i in range(0, s.A.shape[0] - 1, every):
+                    t.propagate(s.A[i:i + every + 1])
+                    Es.append(t.energy())
+            else:
+                J = t.propagate(s.A)
+            rho, _ = t.density_current()
+            d = t.dipole()
+        return J, rho, d, np.array(Es)
+    out = {}
+    s = synth.single_cell_config(1, nk=2, nsteps=1000)
+    J64, r64, _, _ = run(s, "c128")
+    J32, r32, _, _ = run(s, "mixed")
+    out["periodic_20^3_k8_1000_steps"] = {
+        "current_error": float(np.max(np.max(np.abs(J32 - J64), axis=0) / np.max(np.abs(J64), axis=0))),
+        "density_l2_error": float(np.linalg.norm(r32 - r64) / np.linalg.norm(r64))}
+    c = synth.single_cell_config(2, n=40, n_orb=32, n_fcc=1, nsteps=1000)
+    _, _, d64, _ = run(c, "c128")
+    _, _, d32, _ = run(c, "mixed")
+    out["isolated_40^3_32orb_1000_steps"] = {
+        "dipole_error": float(np.max(np.abs(d32 - d64)) / np.max(np.abs(d64)))}
+    g = synth.single_cell_config(0, nsteps=1000, kick=0.0)
+    with TDDFT(g, precision="c128") as t:
+        t.set_potential()
+        t.ground_state(600, 0.035)
+        psi = t.orbitals()
+    drift = {}
+    for prec in ("c128", "mixed"):
+        _, _, _, E = run(g, prec, psi=psi, every=100)
+        tt = np.arange(E.shape[0]) * 100
+        drift[prec] = float(np.polyfit(tt, E, 1)[0] * 1000 / abs(E[0]))
+    out["energy_drift_per_1000_steps_16^3_ground_state"] = drift
+    return out
 
 
 def bench_batch(steps=30, warmup=8):
@@ -204,6 +276,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the uneven-batch line")
     ap.add_argument("--no-multiscale", action="store_true", help="skip the learned multiscale line")
+    ap.add_argument("--no-accuracy", action="store_true", help="skip the 1000-step accuracy report")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="also run a plain device copy of this many MB (a known-size "
                          "reference for the HBM byte counters of a profiler run)")
@@ -294,6 +367,8 @@ def main():
         out["twin"] = {"precision": other, "value": og / (ms2 * 1e-3), "ms_per_step": ms2,
                        "kernels_ms": kern2,
                        "stage_GBs": 3 * (16 if other == "c128" else 8) * og / (kern2["stage_ms"] * 1e-3) / 1e9}
+    if not args.no_accuracy:
+        out["accuracy"] = accuracy_report()
     if not args.no_batch:
         out["batched"] = bench_batch()
     if not args.no_multiscale:

@@ -297,3 +297,29 @@ def test_full_size_diamond20_k512_sampled(flags):
             assert rel_l2(g["psi"][ik], ref) < tol, ik
         rho_host = tdks.density(g["psi"], s.kw, grid)
         assert rel_l2(g["rho"], rho_host) < (1e-13 if prec == "c128" else 1e-7)
+
+
+def test_mixed_path_after_1000_steps():
+    """The mixed path against the complex128 path (itself pinned to the
+    oracle above) over 1000 steps: current series and cluster dipole within
+    1e-5 of their maxima, density within 1e-5 relative L2."""
+    from paper_1804_01404_amd.binding import TDDFT
+
+    def run(s, prec):
+        with TDDFT(s, precision=prec) as t:
+            t.set_potential()
+            J = t.propagate(s.A)
+            rho, _ = t.density_current()
+            d = t.dipole()
+        return J, rho, d
+    s = synth.single_cell_config(1, nk=2, nsteps=1000)
+    announce("mixed vs c128, 20^3 x 8 k, 1000 steps")
+    J64, r64, _ = run(s, "c128")
+    J32, r32, _ = run(s, "mixed")
+    assert max_rel_series(J32, J64) < 1e-5
+    assert rel_l2(r32, r64) < 1e-5
+    c = synth.single_cell_config(2, n=40, n_orb=32, n_fcc=1, nsteps=1000)
+    announce("mixed vs c128, isolated 40^3 cluster, 1000 steps")
+    _, _, d64 = run(c, "c128")
+    _, _, d32 = run(c, "mixed")
+    assert np.max(np.abs(d32 - d64)) < 1e-5 * np.max(np.abs(d64))
