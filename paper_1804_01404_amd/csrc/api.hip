@@ -69,6 +69,8 @@ struct tddft_ctx {
   double* ent_beta = nullptr;  // [S][4]
   int n_colors = 0;
   int *color_start = nullptr, *color_atoms = nullptr;
+  std::vector<int> color_ent_start;  // host: entries of colour c are color_ents[start[c] .. start[c+1])
+  int* color_ents = nullptr;         // [S] entry ids grouped by colour
   bool fused = false;          // whole step per orbital in LDS
   double2* Eu = nullptr;
   double* jnl = nullptr;
@@ -416,6 +418,11 @@ tddft_status enqueue_taylor_stages(tddft_ctx* c, double dt, double tau_imag) {
     a.tau_re = -tau_imag / s;
     const int mode = (s == 4) ? kFirst : (s == 1 ? kLast : kMid);
     LAUNCH(launch_stage<T>(mode, c->bc, a, c->stream), "stage");
+    // the nonlocal term of the stage, added over each colour's sphere entries
+    for (int cl = 0; cl < c->n_colors && c->nl.n_atoms > 0; ++cl) {
+      const int e0 = c->color_ent_start[cl], ne = c->color_ent_start[cl + 1] - e0;
+      LAUNCH(launch_nl_addback<T>(a, c->color_ents + e0, ne, (int)c->n_orb_tot, c->stream), "nonlocal add-back");
+    }
   }
   return TDDFT_OK;
 }
@@ -520,6 +527,10 @@ tddft_status launch_one(tddft_ctx* c, int which) {
     a.out = as2<T>(c->U1);
     a.tau = c->cfg.dt / 2;
     LAUNCH(launch_stage<T>(kMid, c->bc, a, c->stream), "stage");
+    for (int cl = 0; cl < c->n_colors && c->nl.n_atoms > 0; ++cl) {
+      const int e0 = c->color_ent_start[cl], ne = c->color_ent_start[cl + 1] - e0;
+      LAUNCH(launch_nl_addback<T>(a, c->color_ents + e0, ne, (int)c->n_orb_tot, c->stream), "nonlocal add-back");
+    }
   } else if (which == TDDFT_KERNEL_PROJECT) {
     if (c->nl.n_atoms == 0) return TDDFT_OK;
     ProjArgs<T> pa{};
@@ -922,6 +933,12 @@ tddft_status tddft_set_potential(tddft_ctx* c, const double* v_loc, int32_t n_at
       if (color[a] == cl) color_atoms.push_back(a);
     color_start[cl + 1] = (int)color_atoms.size();
   }
+  std::vector<int> color_ent_start(n_colors + 1, 0), color_ents;
+  for (int cl = 0; cl < n_colors; ++cl) {
+    for (int i = color_start[cl]; i < color_start[cl + 1]; ++i)
+      for (int e = atom_start[color_atoms[i]]; e < atom_start[color_atoms[i] + 1]; ++e) color_ents.push_back(e);
+    color_ent_start[cl + 1] = (int)color_ents.size();
+  }
   c->max_overlap = max_overlap;
   // exp(i k . x_e)
   std::vector<double2> phk((size_t)c->cfg.n_k * std::max(S, 1));
@@ -956,6 +973,7 @@ tddft_status tddft_set_potential(tddft_ctx* c, const double* v_loc, int32_t n_at
       (st = dalloc_t(c, (size_t)nA * kMaxProj, &d_atom_E)) || (st = dalloc_t(c, (size_t)Sx * 3, &d_ent_x)) ||
       (st = dalloc_t(c, (size_t)Sx * kMaxProj, &d_ent_beta)) ||
       (st = dalloc_t(c, (size_t)n_colors + 1, &c->color_start)) || (st = dalloc_t(c, (size_t)nA, &c->color_atoms)) ||
+      (st = dalloc_t(c, (size_t)Sx, &c->color_ents)) ||
       (st = dalloc_t(c, phk.size(), &d_phk)) || (st = dalloc_t(c, Sx, &d_phA)) ||
       (st = dalloc_t(c, Sx, &d_phAJ)) ||
       (st = dalloc_t(c, c->n_orb_tot * nA * kMaxProj, &d_Eu)) || (st = dalloc_t(c, c->n_orb_tot * 4, &d_jnl)))
@@ -978,6 +996,8 @@ tddft_status tddft_set_potential(tddft_ctx* c, const double* v_loc, int32_t n_at
   HIP_TRY(up(d_ent_beta, ent_beta.data(), ent_beta.size() * sizeof(double)));
   HIP_TRY(up(c->color_start, color_start.data(), color_start.size() * sizeof(int)));
   HIP_TRY(up(c->color_atoms, color_atoms.data(), color_atoms.size() * sizeof(int)));
+  HIP_TRY(up(c->color_ents, color_ents.data(), color_ents.size() * sizeof(int)));
+  c->color_ent_start = color_ent_start;
   c->n_colors = n_colors;
   HIP_TRY(up(d_phk, phk.data(), (size_t)c->cfg.n_k * S * sizeof(double2)));
   HIP_TRY(up(c->Vloc, v_loc, N * sizeof(double)));

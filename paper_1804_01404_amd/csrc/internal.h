@@ -127,6 +127,8 @@ struct FusedArgs {
 template <typename T>
 hipError_t launch_stage(int mode, int bc, const StageArgs<T>& a, hipStream_t s);
 template <typename T>
+hipError_t launch_nl_addback(const StageArgs<T>& a, const int* ents, int n_ents, int n_orb_tot, hipStream_t s);
+template <typename T>
 hipError_t launch_observe(int bc, const ObserveArgs<T>& a, hipStream_t s);
 template <typename T>
 hipError_t launch_project(const ProjArgs<T>& a, hipStream_t s);

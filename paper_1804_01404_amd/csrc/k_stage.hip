@@ -121,23 +121,29 @@ __global__ __launch_bounds__(1024) void k_stage(StageArgs<T> a) {
     ez = (T)(a.efield[2] * g.h3);
   }
   const T zc = (T)(0.5 * (n3 - 1));
-  const bool has_nl = (a.Eu != nullptr);
-  const int S = a.nl.n_ent;
-  const int n_atoms = a.nl.n_atoms;
 
   T2 q[9];
 #pragma unroll
   for (int i = 0; i < 8; ++i) q[i] = load_col(i - 4);
   T2 nxt = load_col(4);
+  // w and V of the next plane are fetched one plane ahead, like u
+  T2 w_nxt = z2;
+  T v_nxt = 0;
+  if (active) {
+    if (MODE != kFirst) w_nxt = a.w[base + col];
+    v_nxt = a.V[col];
+  }
 
   for (int z = 0; z < n3; ++z) {
     q[8] = nxt;
     if (z + 1 < n3) nxt = load_col(z + 5);
     const size_t pz = (size_t)z * plane + col;
-    T2 wv = q[4];
-    if (MODE != kFirst && active) wv = a.w[base + pz];
-    T vv = 0;
-    if (active) vv = a.V[pz];
+    T2 wv = (MODE == kFirst) ? q[4] : w_nxt;
+    const T vv = v_nxt;
+    if (active && z + 1 < n3) {
+      if (MODE != kFirst) w_nxt = a.w[base + pz + plane];
+      v_nxt = a.V[pz + plane];
+    }
 
     T2* buf = lds + (z & 1) * lsz;
     if (active) {
@@ -171,28 +177,6 @@ __global__ __launch_bounds__(1024) void k_stage(StageArgs<T> a) {
         hr += cz[m] * (p.x + n.x) + bz[m] * (p.y - n.y);
         hi += cz[m] * (p.y + n.y) - bz[m] * (p.x - n.x);
       }
-      if (has_nl) {
-        const int e0 = a.nl.pt_ptr[pz], e1 = a.nl.pt_ptr[pz + 1];
-        for (int t = e0; t < e1; ++t) {
-          const int e = a.nl.pt_ent[t];
-          const int at = a.nl.ent_atom[e];
-          const double2 p1 = a.nl.phk[(size_t)k * S + e];
-          const double2 p2 = a.phA[e];
-          const double pr = p1.x * p2.x - p1.y * p2.y;
-          const double pim = p1.x * p2.y + p1.y * p2.x;
-          const double2* eu = a.Eu + ((size_t)o * n_atoms + at) * kMaxProj;
-          const double* B = a.nl.ent_B + (size_t)e * kCols;
-          double sr = 0.0, si = 0.0;
-#pragma unroll
-          for (int pp = 0; pp < kMaxProj; ++pp) {
-            const double b = B[pp * kMoments];
-            sr += b * eu[pp].x;
-            si += b * eu[pp].y;
-          }
-          hr += (T)(pr * sr + pim * si);
-          hi += (T)(pr * si - pim * sr);
-        }
-      }
       T2 res;
       res.x = wv.x + tau * hi + tau_re * hr;
       res.y = wv.y - tau * hr + tau_re * hi;
@@ -202,6 +186,62 @@ __global__ __launch_bounds__(1024) void k_stage(StageArgs<T> a) {
     for (int i = 0; i < 8; ++i) q[i] = q[i + 1];
   }
 }
+
+// Nonlocal term of a stage, added to u_{s-1} after the local part:
+//   u_{s-1}(x_e) += (x / s) sum_p beta_p(x_e) exp(-i kappa . x_e) E_p u_p
+// for the sphere entries of one colour (atoms whose spheres share no grid
+// point, so the entries of one launch touch distinct points); colours run in
+// a fixed order. Eu holds E_p u_p (h^3 included) from the projection of u_s.
+// One thread per (entry, k-point), looping over the k-point's orbitals.
+template <typename T>
+__global__ void k_nl_addback(StageArgs<T> a, const int* __restrict__ ents, int n_ents) {
+  using T2 = typename Vec2<T>::type;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = blockIdx.y;
+  if (t >= n_ents) return;
+  const int e = ents[t];
+  const int S = a.nl.n_ent;
+  const int n_orb = a.g.n_orb;
+  const size_t N = (size_t)a.g.n1 * a.g.n2 * a.g.n3;
+  const int at = a.nl.ent_atom[e];
+  const double2 p1 = a.nl.phk[(size_t)k * S + e];
+  const double2 p2 = a.phA[e];
+  const double pr = p1.x * p2.x - p1.y * p2.y;
+  const double pim = p1.x * p2.y + p1.y * p2.x;
+  const double* B = a.nl.ent_B + (size_t)e * kCols;
+  double b[kMaxProj];
+#pragma unroll
+  for (int p = 0; p < kMaxProj; ++p) b[p] = B[p * kMoments];
+  const int idx = a.nl.ent_idx[e];
+  // the entry's table values serve every orbital of this k-point
+  for (int j = 0; j < n_orb; ++j) {
+    const size_t o = (size_t)k * n_orb + j;
+    const double2* eu = a.Eu + (o * a.nl.n_atoms + at) * kMaxProj;
+    double sr = 0.0, si = 0.0;
+#pragma unroll
+    for (int p = 0; p < kMaxProj; ++p) {
+      sr += b[p] * eu[p].x;
+      si += b[p] * eu[p].y;
+    }
+    const double hr = pr * sr + pim * si, hi = pr * si - pim * sr;
+    T2* dst = a.out + o * N + idx;
+    T2 v = *dst;
+    v.x += (T)(a.tau * hi + a.tau_re * hr);
+    v.y += (T)(-a.tau * hr + a.tau_re * hi);
+    *dst = v;
+  }
+}
+
+template <typename T>
+hipError_t launch_nl_addback(const StageArgs<T>& a, const int* ents, int n_ents, int n_orb_tot, hipStream_t s) {
+  if (n_ents <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((n_ents + 255) / 256), (unsigned)(n_orb_tot / a.g.n_orb));
+  hipLaunchKernelGGL((k_nl_addback<T>), grid, dim3(256), 0, s, a, ents, n_ents);
+  return hipGetLastError();
+}
+
+template hipError_t launch_nl_addback<double>(const StageArgs<double>&, const int*, int, int, hipStream_t);
+template hipError_t launch_nl_addback<float>(const StageArgs<float>&, const int*, int, int, hipStream_t);
 
 // Per-orbital sums used by the current and the energy, all in FP64:
 // norm = sum |w|^2, p_mu = sum Im(conj(w) d_mu w), kin = sum Re(conj(w)(-1/2 Lap w)),
@@ -276,8 +316,13 @@ __global__ __launch_bounds__(1024) void k_observe(ObserveArgs<T> a) {
   double2 q[9];
 #pragma unroll
   for (int i = 0; i < 8; ++i) q[i] = load_col(i - 4);
+  double2 nxt = load_col(4);  // the column one plane ahead, and V_loc
+  double vl_nxt = active ? a.Vloc[col] : 0.0;
   for (int z = 0; z < n3; ++z) {
-    q[8] = load_col(z + 4);
+    q[8] = nxt;
+    if (z + 1 < n3) nxt = load_col(z + 5);
+    const double vl = vl_nxt;
+    if (active && z + 1 < n3) vl_nxt = a.Vloc[(size_t)(z + 1) * plane + col];
     double2* buf = lds + (z & 1) * lsz;
     if (active) {
       buf[lc] = q[4];
@@ -319,7 +364,7 @@ __global__ __launch_bounds__(1024) void k_observe(ObserveArgs<T> a) {
       s_py += u.x * dyi - u.y * dyr;
       s_pz += u.x * dzi - u.y * dzr;
       s_kin += u.x * lr + u.y * li;
-      s_v += a.Vloc[(size_t)z * plane + col] * nn;
+      s_v += vl * nn;
     }
 #pragma unroll
     for (int i = 0; i < 8; ++i) q[i] = q[i + 1];
