@@ -462,7 +462,7 @@ class TDKS:
     then read ``rho``, ``current()``, ``energy()``, ``psi``."""
 
     def __init__(self, n, cell, boundary, kpts, kw, psi0, dt, v_loc, projectors,
-                 hartree=True, xc=True, gauge="velocity"):
+                 hartree=True, xc=True, gauge="velocity", predictor_corrector=False):
         self.grid = Grid(n, cell, boundary)
         self.kpts = np.asarray(kpts, dtype=np.float64)
         self.kw = np.asarray(kw, dtype=np.float64)
@@ -473,6 +473,7 @@ class TDKS:
         self.use_hartree = bool(hartree)
         self.use_xc = bool(xc)
         self.gauge = gauge
+        self.predictor_corrector = bool(predictor_corrector)
         self._hker = coulomb_kernel_isolated(self.grid) if (hartree and not self.grid.periodic) else None
         self.A_now = np.zeros(3)            # A at the current time (for the current)
         self.rho = density(self.psi, self.kw, self.grid)
@@ -480,9 +481,10 @@ class TDKS:
         self._update_potential()
 
     @classmethod
-    def from_system(cls, s, psi0=None):
+    def from_system(cls, s, psi0=None, predictor_corrector=False):
         return cls(s.n, s.cell, s.boundary, s.kpts, s.kw, s.psi0 if psi0 is None else psi0, s.dt,
-                   s.v_loc, s.projectors, hartree=s.hartree, xc=s.xc, gauge=s.gauge)
+                   s.v_loc, s.projectors, hartree=s.hartree, xc=s.xc, gauge=s.gauge,
+                   predictor_corrector=predictor_corrector)
 
     # potentials ----------------------------------------------------------
     def _update_potential(self):
@@ -501,20 +503,36 @@ class TDKS:
         return E[0] * rx + E[1] * ry + E[2] * rz
 
     # one step (Program Summary: truncated Taylor; V frozen over the step) --
-    def step(self, A0, A1):
-        A0 = np.asarray(A0, dtype=np.float64)
-        A1 = np.asarray(A1, dtype=np.float64)
-        V = self.v_ks
+    def _taylor_all(self, psi, V, A0, A1):
+        """The Taylor step of every k-point from psi under the potential V."""
         if self.gauge == "length":
             E = -(A1 - A0) / (C_LIGHT * self.dt)
             V = V + self._external(E)
             shift = np.zeros(3)
         else:
             shift = 0.5 * (A0 + A1) / C_LIGHT
+        out = np.empty_like(psi)
         for ik, k in enumerate(self.kpts):
             kappa = k + shift
-            hop = lambda X: apply_h(X, kappa, V, self.projs, self.grid)
-            self.psi[ik] = taylor_step(self.psi[ik], self.dt, hop)
+            hop = lambda X, kappa=kappa: apply_h(X, kappa, V, self.projs, self.grid)
+            out[ik] = taylor_step(psi[ik], self.dt, hop)
+        return out
+
+    def step(self, A0, A1):
+        """One step. Plain: the potential is frozen at rho(t_n). With the
+        predictor-corrector (Program Summary: "when necessary"), a predicted
+        step gives rho and V at t_{n+1}, and the step is redone from t_n under
+        the mean of V(t_n) and the predicted V(t_{n+1})."""
+        A0 = np.asarray(A0, dtype=np.float64)
+        A1 = np.asarray(A1, dtype=np.float64)
+        V = self.v_ks
+        if self.predictor_corrector:
+            pred = self._taylor_all(self.psi, V, A0, A1)
+            V_n = V
+            self.rho = density(pred, self.kw, self.grid)
+            self._update_potential()
+            V = 0.5 * (V_n + self.v_ks)
+        self.psi = self._taylor_all(self.psi, V, A0, A1)
         self.A_now = A1
         self.rho = density(self.psi, self.kw, self.grid)
         self._update_potential()

@@ -123,13 +123,13 @@ def test_current_is_energy_derivative():
     assert np.max(np.abs(I + grad / o.grid.volume)) < 1e-7 * np.max(np.abs(I))
 
 
-def _energy_work_gap(dt, hx):
+def _energy_work_gap(dt, hx, pc=False):
     T = 2.0
     n = int(round(T / dt))
     A = synth.cos2_pulse_table(n, dt, 0.05, 0.5, T, 0.1, [1, 0.3, -0.2])
     s = tiny_periodic(kpts=[[0.1, 0.2, -0.1], [-0.3, 0.0, 0.2]], n_orb=3, dt=dt, nsteps=n, A=A,
                       hartree=hx, xc=hx, n=8, L=5.2)
-    o = tdks.TDKS.from_system(s)
+    o = tdks.TDKS.from_system(s, predictor_corrector=pc)
     E0 = o.energy(A[0])
     Is = [o.current(A[0])]
     for m in range(n):
@@ -153,6 +153,30 @@ def test_energy_work_theorem_selfconsistent_first_order():
     ratio = abs(d1 - w1) / abs(d2 - w2)
     assert 1.6 < ratio < 2.5                          # potential frozen over the step
     assert abs(w1 - w2) < 1e-2 * abs(w2)
+
+
+def test_energy_work_theorem_predictor_corrector_second_order():
+    """With the potential taken at the step midpoint (predictor-corrector),
+    the self-consistent energy-work gap falls with the square of dt."""
+    d1, w1 = _energy_work_gap(0.04, True, pc=True)
+    d2, w2 = _energy_work_gap(0.02, True, pc=True)
+    ratio = abs(d1 - w1) / abs(d2 - w2)
+    assert ratio > 3.3
+    e1, v1 = _energy_work_gap(0.04, True)
+    assert abs(d1 - w1) < 0.5 * abs(e1 - v1)     # better than the frozen potential
+
+
+def test_predictor_corrector_is_exact_without_self_consistency():
+    """Without Hartree and xc the potential does not depend on rho, so the
+    corrector repeats the plain step exactly."""
+    s = tiny_periodic(kpts=[[0.1, 0.0, 0.2]], n_orb=2, nsteps=4, dt=0.03, hartree=False, xc=False,
+                      A=synth.kick_table(4, [0.4, 0, 0]), n=8, L=5.2)
+    a = tdks.TDKS.from_system(s)
+    b = tdks.TDKS.from_system(s, predictor_corrector=True)
+    Ja = a.propagate(s.A)
+    Jb = b.propagate(s.A)
+    assert np.max(np.abs(a.psi - b.psi)) < 1e-14
+    assert np.max(np.abs(Ja - Jb)) < 1e-15
 
 
 def test_density_bookkeeping():
