@@ -66,6 +66,13 @@ enum { TDDFT_XC_NONE = 0, TDDFT_XC_PZ81 = 1 };
 #define TDDFT_FLAG_NO_GRAPH 0x4u       /* launch kernels directly, no hipGraph    */
 #define TDDFT_FLAG_STREAMING 0x8u      /* one kernel per Horner stage even when the
                                           orbital fits in LDS (the fused step) */
+#define TDDFT_FLAG_PREDICTOR_CORRECTOR 0x20u /* Program Summary ("a predictor-corrector
+                                          step when necessary"): each step is first
+                                          predicted under V(t_n); the density of the
+                                          prediction gives V(t_{n+1}), and the step is
+                                          redone from t_n under (V(t_n) + V(t_{n+1})) / 2.
+                                          Twice the work per step; one more copy of
+                                          the orbitals in device memory */
 
 typedef struct {
   uint32_t abi_version;   /* TDDFT_ABI_VERSION                                  */
@@ -203,7 +210,8 @@ typedef struct tddft_batch tddft_batch;
 
 /* n_cells configurations and initial orbitals (layout as in tddft_init).
  * All cells use cfgs[0].precision, cfgs[0].stream (NULL: a stream owned by
- * the batch) and cfgs[0].flags. Errors as tddft_init; on failure *out = NULL. */
+ * the batch) and cfgs[0].flags (TDDFT_FLAG_PREDICTOR_CORRECTOR: EINVAL, single
+ * contexts only). Errors as tddft_init; on failure *out = NULL. */
 tddft_status tddft_batch_create(int32_t n_cells, const tddft_config *cfgs, const double *const *psi0,
                                 tddft_batch **out);
 /* As tddft_set_potential for one cell (0 <= cell < n_cells). */

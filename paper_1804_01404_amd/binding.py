@@ -25,6 +25,7 @@ C128, MIXED = 0, 1
 VELOCITY, LENGTH = 0, 1
 XC_NONE, XC_PZ81 = 0, 1
 FLAG_ALLOW_UNSTABLE, FLAG_DEBUG_SYNC, FLAG_NO_GRAPH, FLAG_STREAMING, FLAG_NO_TUNE = 1, 2, 4, 8, 16
+FLAG_PREDICTOR_CORRECTOR = 32
 
 EXPORTED = ["tddft_abi_version", "tddft_init", "tddft_set_potential", "tddft_propagate",
             "tddft_density_current", "tddft_get_orbitals", "tddft_set_orbitals", "tddft_energy",

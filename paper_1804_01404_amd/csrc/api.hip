@@ -82,6 +82,8 @@ struct tddft_ctx {
   double *kappa = nullptr, *kappaJ = nullptr, *efield = nullptr, *Alast = nullptr;
   double* coef = nullptr;  // [n_k][kCoef] in the stage precision (fused step)
   double2* gram = nullptr;  // [2][n_k][n_orb][n_orb] overlap and its inverse factor (ground state)
+  void* Wsave = nullptr;    // predictor-corrector: the orbitals at t_n
+  double* Vsave = nullptr;  // predictor-corrector: V(t_n)
   double2 *phA = nullptr, *phAJ = nullptr;
   double* obs = nullptr;
   double *Atab = nullptr, *Jtab = nullptr;
@@ -440,6 +442,23 @@ template <typename T>
 tddft_status enqueue_step(tddft_ctx* c) {
   tddft_status st = enqueue_params(c);
   if (st != TDDFT_OK) return st;
+  if (c->cfg.flags & TDDFT_FLAG_PREDICTOR_CORRECTOR) {
+    // predictor: the step under V(t_n), then rho and V at t_{n+1}; the
+    // corrector below restarts from the saved orbitals under the mean potential
+    const size_t wbytes = c->n_orb_tot * c->N * sizeof(typename Vec2<T>::type);
+    LAUNCH(launch_copy8(c->W, c->Wsave, wbytes, c->stream), "save orbitals");
+    LAUNCH(launch_copy8(c->Vd, c->Vsave, c->N * sizeof(double), c->stream), "save potential");
+    if (c->fused) {
+      LAUNCH(launch_fused<T>(fused_args<T>(c), c->stream), "fused step (predictor)");
+    } else {
+      st = enqueue_taylor_stages<T>(c, c->cfg.dt, 0.0);
+      if (st != TDDFT_OK) return st;
+    }
+    st = enqueue_density_potential<T>(c);
+    if (st != TDDFT_OK) return st;
+    LAUNCH(launch_mid_potential(c->Vsave, c->Vd, c->Vf, c->N, c->stream), "mid potential");
+    LAUNCH(launch_copy8(c->Wsave, c->W, wbytes, c->stream), "restore orbitals");
+  }
   if (c->fused) {
     LAUNCH(launch_fused<T>(fused_args<T>(c), c->stream), "fused step");
     return enqueue_fused_tail<T>(c);
@@ -806,6 +825,8 @@ tddft_status tddft_init(const tddft_config* cfg, const double* psi0, tddft_ctx**
   if ((st = dalloc(c, 2 * total * esz, &u01)) != TDDFT_OK) return cleanup(st);
   c->U0 = u01;
   c->U1 = static_cast<char*>(u01) + total * esz;
+  if ((cfg->flags & TDDFT_FLAG_PREDICTOR_CORRECTOR) && (st = dalloc(c, total * esz, &c->Wsave)) != TDDFT_OK)
+    return cleanup(st);
   const size_t N = c->N;
   if ((st = dalloc_t(c, N, &c->Vd)) || (st = dalloc_t(c, N, &c->Vf)) || (st = dalloc_t(c, N, &c->Vloc)) ||
       (st = dalloc_t(c, N, &c->vh)) || (st = dalloc_t(c, N, &c->exc)) || (st = dalloc_t(c, N, &c->rho)) ||
@@ -819,6 +840,7 @@ tddft_status tddft_init(const tddft_config* cfg, const double* psi0, tddft_ctx**
   if ((st = dalloc_t(c, 3 * (size_t)cfg->n_k, &c->kpt_d)) || (st = dalloc_t(c, (size_t)cfg->n_k, &c->kw_d)) ||
       (st = dalloc_t(c, 3 * (size_t)cfg->n_k, &c->kappa)) || (st = dalloc_t(c, 3 * (size_t)cfg->n_k, &c->kappaJ)) ||
       (st = dalloc_t(c, (size_t)kCoef * cfg->n_k, &c->coef)) ||
+      (st = dalloc_t(c, (cfg->flags & TDDFT_FLAG_PREDICTOR_CORRECTOR) ? N : 1, &c->Vsave)) ||
       (st = dalloc_t(c, 3, &c->efield)) || (st = dalloc_t(c, 3, &c->Alast)) || (st = dalloc_t(c, 6, &c->Aobs)) ||
       (st = dalloc_t(c, 1, &c->counter)) || (st = dalloc_t(c, 1, &c->nanflag)) ||
       (st = dalloc_t(c, 8, &c->scalars)) || (st = dalloc_t(c, 8, &c->sums)) ||
@@ -1565,6 +1587,7 @@ tddft_status tddft_batch_create(int32_t n_cells, const tddft_config* cfgs, const
   if (!out) return TDDFT_EINVAL;
   *out = nullptr;
   if (n_cells < 1 || !cfgs || !psi0) return TDDFT_EINVAL;
+  if (cfgs[0].flags & TDDFT_FLAG_PREDICTOR_CORRECTOR) return TDDFT_EINVAL;  // single contexts only
   auto* b = new tddft_batch();
   b->mixed = cfgs[0].precision == TDDFT_MIXED;
   b->flags = cfgs[0].flags;

@@ -186,6 +186,8 @@ hipError_t launch_apply_lower(const typename Vec2<T>::type* w, const double2* M,
                               typename Vec2<T>::type* out, hipStream_t s);
 hipError_t launch_real_part(const double2* src, double* dst, size_t n, hipStream_t s);
 hipError_t launch_fill(double* p, double v, size_t n, hipStream_t s);
+hipError_t launch_copy8(const void* src, void* dst, size_t bytes, hipStream_t s);
+hipError_t launch_mid_potential(const double* Vn, double* Vd, float* Vf, size_t n, hipStream_t s);
 
 // ---- multiscale Maxwell (k_maxwell.hip) -----------------------------------
 hipError_t launch_fdtd_step(const double* A_now, const double* A_prev, const double* I, double* A_new, int n,

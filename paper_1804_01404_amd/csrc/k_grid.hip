@@ -602,6 +602,33 @@ hipError_t launch_fill(double* p, double v, size_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
+// dst = src, 8 bytes per thread (both 8-byte aligned, bytes a multiple of 8)
+__global__ void k_copy8(const double* __restrict__ src, double* __restrict__ dst, size_t n8) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n8) dst[i] = src[i];
+}
+hipError_t launch_copy8(const void* src, void* dst, size_t bytes, hipStream_t s) {
+  const size_t n8 = bytes / 8;
+  if (n8 == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy8, dim3((unsigned)((n8 + 255) / 256)), dim3(256), 0, s,
+                     static_cast<const double*>(src), static_cast<double*>(dst), n8);
+  return hipGetLastError();
+}
+
+// predictor-corrector: V = (V_n + V_pred) / 2 in FP64 and its stage-precision copy
+__global__ void k_mid_potential(const double* __restrict__ Vn, double* __restrict__ Vd, float* __restrict__ Vf,
+                                size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double v = 0.5 * (Vn[i] + Vd[i]);
+  Vd[i] = v;
+  Vf[i] = (float)v;
+}
+hipError_t launch_mid_potential(const double* Vn, double* Vd, float* Vf, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_mid_potential, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, Vn, Vd, Vf, n);
+  return hipGetLastError();
+}
+
 __global__ void k_set_int(int* p, int v) { *p = v; }
 hipError_t launch_set_int(int* p, int v, hipStream_t s) {
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, p, v);

@@ -323,3 +323,26 @@ def test_mixed_path_after_1000_steps():
     _, _, d64 = run(c, "c128")
     _, _, d32 = run(c, "mixed")
     assert np.max(np.abs(d32 - d64)) < 1e-5 * np.max(np.abs(d64))
+
+
+@pytest.mark.parametrize("flags", PATHS)
+def test_predictor_corrector_matches_oracle(flags):
+    """The predictor-corrector step (potential at the step midpoint) against
+    the oracle's, complex128, on a periodic cell with k-points and on the
+    isolated cluster in the length gauge."""
+    from paper_1804_01404_amd.binding import FLAG_PREDICTOR_CORRECTOR
+    s = synth.single_cell_config(1, n=16, nk=2, n_orb=4, nsteps=12, precision="c128")
+    announce(f"predictor-corrector periodic flags={flags}")
+    g = gpu_run(s, precision="c128", flags=flags | FLAG_PREDICTOR_CORRECTOR)
+    o = tdks.TDKS.from_system(s, predictor_corrector=True)
+    Jo = o.propagate(s.A)
+    assert rel_l2(g["psi"], o.psi) < 1e-10
+    assert rel_l2(g["rho"], o.rho) < 1e-10
+    assert max_rel_series(g["J"], Jo) < 1e-8
+    c = synth.single_cell_config(2, n=20, n_orb=6, n_fcc=1, nsteps=10, precision="c128")
+    announce("predictor-corrector isolated length gauge")
+    g = gpu_run(c, precision="c128", flags=FLAG_PREDICTOR_CORRECTOR)
+    o = tdks.TDKS.from_system(c, predictor_corrector=True)
+    o.propagate(c.A)
+    assert rel_l2(g["psi"], o.psi) < 1e-10
+    assert np.max(np.abs(g["dipole"] - o.dipole())) < 1e-9 * np.max(np.abs(o.dipole()))
