@@ -172,6 +172,19 @@ tddft_status tddft_kick(tddft_ctx *ctx, double F0, int32_t axis);
  * dipole. */
 tddft_status tddft_ground_state(tddft_ctx *ctx, int32_t n_iter, double tau, double *energies);
 
+/* Keep a copy of the current orbitals (normally the ground state, before any
+ * field) as the reference for tddft_excited_electrons. At most 64 orbitals
+ * per k-point (EINVAL otherwise). */
+tddft_status tddft_set_reference(tddft_ctx *ctx);
+
+/* Number density of excited electron-hole pairs (Sec. 4.2, Fig. Si_pulse):
+ * the occupied weight that has left the span of the reference orbitals of the
+ * same k-point, n_ex = (1/Omega) sum_k w_k 2 [n_orb - sum_{m,n}
+ * |<ref_mk|w_nk>|^2] (bohr^-3). The paper names the quantity without a
+ * formula; this projection is exact once the field has returned to its
+ * starting value. ESTATE before tddft_set_reference. */
+tddft_status tddft_excited_electrons(tddft_ctx *ctx, double *n_ex);
+
 /* Mean device time per step of the last propagate, from HIP events (ms). */
 tddft_status tddft_last_timing(tddft_ctx *ctx, double *ms_per_step);
 

@@ -343,6 +343,21 @@ def current(psi, kpts, kw, A, projs, grid: Grid, gauge: str = "velocity"):
     return -total / grid.volume
 
 
+def excited_electrons(psi_ref, psi, kw, grid: Grid):
+    """Number density of excited electron-hole pairs (Sec. 4.2, Fig. Si_pulse):
+    the occupied weight that has left the space of the reference (ground-state)
+    orbitals of the same k-point,
+        n_ex = (1/Omega) sum_k w_k 2 [n_orb - sum_{m,n} |<ref_mk|psi_nk>|^2].
+    The paper names the quantity without a formula; this projection reading
+    is exact once the applied field has returned to its starting value."""
+    n_orb = psi.shape[1]
+    total = 0.0
+    for ik in range(psi.shape[0]):
+        O = np.array([[grid.inner(psi_ref[ik, m], psi[ik, n]) for n in range(n_orb)] for m in range(n_orb)])
+        total += kw[ik] * 2.0 * (n_orb - float(np.sum(np.abs(O) ** 2)))
+    return total / grid.volume
+
+
 def dipole(rho, rho0, grid: Grid):
     """d_mu = -int r_mu (rho - rho_0) dr, r from the box centre (Sec. 3.1)."""
     x, y, z = grid.coords()

@@ -29,7 +29,8 @@ FLAG_PREDICTOR_CORRECTOR = 32
 
 EXPORTED = ["tddft_abi_version", "tddft_init", "tddft_set_potential", "tddft_propagate",
             "tddft_density_current", "tddft_get_orbitals", "tddft_set_orbitals", "tddft_energy",
-            "tddft_norms", "tddft_dipole", "tddft_kick", "tddft_ground_state", "tddft_last_timing", "tddft_time_kernel",
+            "tddft_norms", "tddft_dipole", "tddft_kick", "tddft_ground_state", "tddft_set_reference",
+            "tddft_excited_electrons", "tddft_last_timing", "tddft_time_kernel",
             "tddft_last_error", "tddft_free", "tddft_batch_create", "tddft_batch_set_potential",
             "tddft_batch_propagate", "tddft_batch_cell", "tddft_batch_last_timing", "tddft_batch_report",
             "tddft_batch_last_error", "tddft_batch_free", "tddft_nn_num_params", "tddft_nn_create",
@@ -106,6 +107,8 @@ def load_library(path: str = LIB_PATH):
     lib.tddft_dipole.argtypes = [C.c_void_p, _dp]
     lib.tddft_kick.argtypes = [C.c_void_p, C.c_double, C.c_int32]
     lib.tddft_ground_state.argtypes = [C.c_void_p, C.c_int32, C.c_double, _dp]
+    lib.tddft_set_reference.argtypes = [C.c_void_p]
+    lib.tddft_excited_electrons.argtypes = [C.c_void_p, _dp]
     lib.tddft_last_timing.argtypes = [C.c_void_p, _dp]
     lib.tddft_time_kernel.argtypes = [C.c_void_p, C.c_int32, C.c_int32, _dp]
     lib.tddft_last_error.argtypes = [C.c_void_p]
@@ -310,6 +313,16 @@ class TDDFT:
         E = np.empty(max(int(n_iter), 1))
         self._check(self.lib.tddft_ground_state(self.h, int(n_iter), float(tau), _ptr(E)))
         return E[: int(n_iter)]
+
+    def set_reference(self):
+        """Keep the current orbitals as the reference of excited_electrons."""
+        self._check(self.lib.tddft_set_reference(self.h))
+
+    def excited_electrons(self) -> float:
+        """Number density of excited electron-hole pairs (bohr^-3)."""
+        v = C.c_double()
+        self._check(self.lib.tddft_excited_electrons(self.h, C.byref(v)))
+        return v.value
 
     def kick(self, F0: float, axis: int):
         self._check(self.lib.tddft_kick(self.h, float(F0), int(axis)))

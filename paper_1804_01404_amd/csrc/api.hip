@@ -83,6 +83,8 @@ struct tddft_ctx {
   double* coef = nullptr;  // [n_k][kCoef] in the stage precision (fused step)
   double2* gram = nullptr;  // [2][n_k][n_orb][n_orb] overlap and its inverse factor (ground state)
   void* Wsave = nullptr;    // predictor-corrector: the orbitals at t_n
+  void* Wref = nullptr;     // reference (ground-state) orbitals for the excited-pair count
+  double* Sk = nullptr;     // [n_k] occupied weight kept in the reference space
   double* Vsave = nullptr;  // predictor-corrector: V(t_n)
   double2 *phA = nullptr, *phAJ = nullptr;
   double* obs = nullptr;
@@ -1297,6 +1299,41 @@ tddft_status tddft_ground_state(tddft_ctx* c, int32_t n_iter, double tau, double
   }
   HIP_TRY(hipMemcpyAsync(c->rho0, c->rho, c->N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
+  return TDDFT_OK;
+}
+
+tddft_status tddft_set_reference(tddft_ctx* c) {
+  if (!c) return TDDFT_EINVAL;
+  if (c->poisoned) return fail(c, TDDFT_ESTATE, "context poisoned: " + c->err);
+  if (c->cfg.n_orb > 64) return fail(c, TDDFT_EINVAL, "the excited-pair count supports at most 64 orbitals");
+  const size_t wbytes = c->n_orb_tot * c->N * (c->mixed ? sizeof(float2) : sizeof(double2));
+  tddft_status st;
+  if (!c->Wref && (st = dalloc(c, wbytes, &c->Wref)) != TDDFT_OK) return st;
+  if (!c->Sk && (st = dalloc_t(c, (size_t)c->cfg.n_k, &c->Sk)) != TDDFT_OK) return st;
+  LAUNCH(launch_copy8(c->W, c->Wref, wbytes, c->stream), "copy reference");
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return TDDFT_OK;
+}
+
+tddft_status tddft_excited_electrons(tddft_ctx* c, double* n_ex) {
+  if (!c || !n_ex) return c ? fail(c, TDDFT_EINVAL, "null n_ex") : TDDFT_EINVAL;
+  if (c->poisoned) return fail(c, TDDFT_ESTATE, "context poisoned: " + c->err);
+  if (!c->Wref) return fail(c, TDDFT_ESTATE, "excited_electrons before set_reference");
+  const int nk = c->cfg.n_k, n = c->cfg.n_orb;
+  if (c->mixed)
+    LAUNCH(launch_overlap_weight<float>(as2<float>(c->Wref), as2<float>(c->W), n, nk, (int)c->N, c->dV, c->Sk,
+                                        c->stream),
+           "overlap weight");
+  else
+    LAUNCH(launch_overlap_weight<double>(as2<double>(c->Wref), as2<double>(c->W), n, nk, (int)c->N, c->dV, c->Sk,
+                                         c->stream),
+           "overlap weight");
+  std::vector<double> S(nk);
+  HIP_TRY(hipMemcpyAsync(S.data(), c->Sk, nk * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  double total = 0.0;
+  for (int k = 0; k < nk; ++k) total += c->kw[k] * 2.0 * ((double)n - S[k]);
+  *n_ex = total / c->volume;
   return TDDFT_OK;
 }
 

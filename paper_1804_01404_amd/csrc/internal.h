@@ -182,6 +182,9 @@ template <typename T>
 hipError_t launch_gram(const typename Vec2<T>::type* w, int n_orb, int n_k, int N, double dV, double2* S,
                        hipStream_t s);
 template <typename T>
+hipError_t launch_overlap_weight(const typename Vec2<T>::type* ref, const typename Vec2<T>::type* w, int n_orb,
+                                 int n_k, int N, double dV, double* Sk, hipStream_t s);
+template <typename T>
 hipError_t launch_apply_lower(const typename Vec2<T>::type* w, const double2* M, int n_orb, int n_k, int N,
                               typename Vec2<T>::type* out, hipStream_t s);
 hipError_t launch_real_part(const double2* src, double* dst, size_t n, hipStream_t s);

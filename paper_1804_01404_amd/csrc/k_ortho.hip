@@ -72,6 +72,84 @@ __global__ void k_apply_lower(const typename Vec2<T>::type* w, const double2* M,
   }
 }
 
+// Occupied weight kept in the reference space, per k-point:
+//   S_k = sum_{m,n} |h^3 sum_r conj(ref_m(r)) w_n(r)|^2   (n_orb <= 64).
+// One workgroup per k-point; the grid is walked in tiles of 16 points staged
+// in LDS in FP64; thread t owns the orbital pairs t, t + 256, ... and the
+// pair sums are combined by a fixed tree.
+constexpr int kOvTile = 16;
+constexpr int kOvMaxOrb = 64;
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_overlap_weight(const typename Vec2<T>::type* __restrict__ ref,
+                                                        const typename Vec2<T>::type* __restrict__ w, int n_orb,
+                                                        int N, double dV, double* __restrict__ Sk) {
+  __shared__ double2 tr[kOvMaxOrb][kOvTile + 1];
+  __shared__ double2 tw[kOvMaxOrb][kOvTile + 1];
+  __shared__ double red[256];
+  constexpr int kPairs = kOvMaxOrb * kOvMaxOrb / 256;
+  const int k = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int npair = n_orb * n_orb;
+  double ar[kPairs], ai[kPairs];
+#pragma unroll
+  for (int j = 0; j < kPairs; ++j) ar[j] = ai[j] = 0.0;
+  const size_t base = (size_t)k * n_orb * N;
+  for (int p0 = 0; p0 < N; p0 += kOvTile) {
+    for (int t = tid; t < n_orb * kOvTile; t += 256) {
+      const int m = t / kOvTile, q = t - m * kOvTile;
+      const int p = p0 + q;
+      double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
+      if (p < N) {
+        const auto va = ref[base + (size_t)m * N + p];
+        const auto vb = w[base + (size_t)m * N + p];
+        a = make_double2((double)va.x, (double)va.y);
+        b = make_double2((double)vb.x, (double)vb.y);
+      }
+      tr[m][q] = a;
+      tw[m][q] = b;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kPairs; ++j) {
+      const int pr = tid + 256 * j;
+      if (pr < npair) {
+        const int m = pr / n_orb, n = pr - m * n_orb;
+#pragma unroll
+        for (int q = 0; q < kOvTile; ++q) {
+          const double2 a = tr[m][q], b = tw[n][q];
+          ar[j] += a.x * b.x + a.y * b.y;  // conj(a) b
+          ai[j] += a.x * b.y - a.y * b.x;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int j = 0; j < kPairs; ++j) s += dV * dV * (ar[j] * ar[j] + ai[j] * ai[j]);
+  red[tid] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (tid < h) red[tid] += red[tid + h];
+    __syncthreads();
+  }
+  if (tid == 0) Sk[k] = red[0];
+}
+
+template <typename T>
+hipError_t launch_overlap_weight(const typename Vec2<T>::type* ref, const typename Vec2<T>::type* w, int n_orb,
+                                 int n_k, int N, double dV, double* Sk, hipStream_t s) {
+  if (n_orb > kOvMaxOrb) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_overlap_weight<T>), dim3((unsigned)n_k), dim3(256), 0, s, ref, w, n_orb, N, dV, Sk);
+  return hipGetLastError();
+}
+
+template hipError_t launch_overlap_weight<double>(const double2*, const double2*, int, int, int, double, double*,
+                                                  hipStream_t);
+template hipError_t launch_overlap_weight<float>(const float2*, const float2*, int, int, int, double, double*,
+                                                 hipStream_t);
+
 template <typename T>
 hipError_t launch_gram(const typename Vec2<T>::type* w, int n_orb, int n_k, int N, double dV, double2* S,
                        hipStream_t s) {

@@ -346,3 +346,26 @@ def test_predictor_corrector_matches_oracle(flags):
     o.propagate(c.A)
     assert rel_l2(g["psi"], o.psi) < 1e-10
     assert np.max(np.abs(g["dipole"] - o.dipole())) < 1e-9 * np.max(np.abs(o.dipole()))
+
+
+@pytest.mark.parametrize("prec", ["c128", "mixed"])
+def test_excited_electrons_match_oracle(prec):
+    """Excited electron-hole pairs against the oracle's projection after a
+    kick; zero right after the reference is taken."""
+    from paper_1804_01404_amd.binding import TDDFT
+    s = synth.single_cell_config(1, n=16, nk=2, n_orb=4, nsteps=20, kick=5e-3)
+    announce(f"excited electrons {prec}")
+    with TDDFT(s, precision=prec) as t:
+        t.set_potential()
+        t.set_reference()
+        n0 = t.excited_electrons()
+        t.propagate(s.A)
+        n1 = t.excited_electrons()
+    o = tdks.TDKS.from_system(s)
+    o.propagate(s.A)
+    ref = tdks.excited_electrons(s.psi0, o.psi, s.kw, o.grid)
+    full = 2 * s.n_orb / o.grid.volume          # every electron excited
+    # complex128: rounding only; mixed: FP32 orbitals are orthonormal to ~1e-7
+    floor = 1e-13 * full if prec == "c128" else 1e-6 * full
+    assert abs(n0) < floor
+    assert abs(n1 - ref) < (1e-10 if prec == "c128" else 1e-4) * abs(ref) + floor

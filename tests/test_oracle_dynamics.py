@@ -204,3 +204,49 @@ def test_linear_regime_superposition():
         lin = np.max(np.abs(J["1"] - J["0"]))
         assert res[-1] < 1e-2 * lin
     assert 3.0 < res[0] / res[1] < 5.0               # residual is quadratic in the field
+
+
+def test_excited_electrons_pins():
+    """Zero against itself; invariant under a unitary mixing of the occupied
+    orbitals of one k-point; one orbital rotated fully out of the reference
+    space counts exactly 2 w_k / Omega; quadratic in a weak kick."""
+    s = tiny_periodic(kpts=[[0.1, 0.0, 0.2], [0.0, -0.2, 0.1]], n_orb=3, nsteps=30, dt=0.03, n=8, L=5.2,
+                      real=False)
+    g = tdks.Grid(s.n, s.cell, s.boundary)
+    ref = s.psi0
+    assert abs(tdks.excited_electrons(ref, ref, s.kw, g)) < 1e-13
+    rng = np.random.default_rng(7)
+    M = rng.normal(size=(3, 3)) + 1j * rng.normal(size=(3, 3))
+    U, _ = np.linalg.qr(M)
+    mixed = ref.copy()
+    mixed[1] = np.einsum("mn,nzyx->mzyx", U, ref[1])
+    assert abs(tdks.excited_electrons(ref, mixed, s.kw, g)) < 1e-13
+    # replace orbital 2 of k-point 0 by a normalised vector orthogonal to all references
+    v = rng.normal(size=g.shape) + 1j * rng.normal(size=g.shape)
+    for m in range(3):
+        v = v - g.inner(ref[0, m], v) * ref[0, m]
+    v = v / np.sqrt(np.real(g.inner(v, v)))
+    out = ref.copy()
+    out[0, 2] = v
+    assert abs(tdks.excited_electrons(ref, out, s.kw, g) - 2 * s.kw[0] / g.volume) < 1e-13
+    # weak kicks from exact eigenstates (no Hartree or xc, dense H per
+    # k-point): nothing is excited without the kick, and n_ex grows as the
+    # square of the kick
+    from test_oracle_operators import _kron_hamiltonian
+    s0 = tiny_periodic(kpts=[[0.1, 0.0, 0.2], [0.0, -0.2, 0.1]], n_orb=3, nsteps=30, dt=0.03, n=8, L=5.2,
+                       hartree=False, xc=False)
+    g0 = tdks.Grid(s0.n, s0.cell, s0.boundary)
+    projs = [tdks.Projector(p.idx, p.x, p.beta, p.e_kb) for p in s0.projectors]
+    eig = np.empty_like(s0.psi0)
+    for ik, k in enumerate(s0.kpts):
+        _, U = np.linalg.eigh(_kron_hamiltonian(g0, k, s0.v_loc, projs))
+        for m in range(3):
+            eig[ik, m] = (U[:, m] / np.sqrt(g0.dV)).reshape(g0.shape)
+    vals = []
+    for a0 in (0.0, 0.05, 0.1):
+        o = tdks.TDKS.from_system(s0, psi0=eig)
+        o.propagate(synth.kick_table(30, [a0, 0, 0]))
+        vals.append(tdks.excited_electrons(eig, o.psi, s0.kw, o.grid))
+    # without the kick only the Taylor step's tiny norm loss shows
+    assert abs(vals[0]) < 1e-3 * vals[1]
+    assert abs((vals[2] - vals[0]) / (vals[1] - vals[0]) - 4.0) < 0.01
