@@ -81,6 +81,7 @@ struct tddft_ctx {
   // per step
   double *kappa = nullptr, *kappaJ = nullptr, *efield = nullptr, *Alast = nullptr;
   double* coef = nullptr;  // [n_k][kCoef] in the stage precision (fused step)
+  double2* phkA = nullptr;  // [n_k][S] combined projector phases of the step (fused step)
   double2* gram = nullptr;  // [2][n_k][n_orb][n_orb] overlap and its inverse factor (ground state)
   void* Wsave = nullptr;    // predictor-corrector: the orbitals at t_n
   void* Wref = nullptr;     // reference (ground-state) orbitals for the excited-pair count
@@ -375,6 +376,7 @@ FusedArgs<T> fused_args(tddft_ctx* c) {
   f.obs = c->obs;
   f.jnl = c->jnl;
   f.coef = reinterpret_cast<T*>(c->coef);
+  f.phkA = c->phkA;
   for (int mu = 0; mu < 3; ++mu)
     for (int m = 0; m < 4; ++m) f.lapc[mu][m] = (T)c->lap[mu][m + 1];
   return f;
@@ -1039,6 +1041,7 @@ tddft_status tddft_set_potential(tddft_ctx* c, const double* v_loc, int32_t n_at
   c->ent_beta = d_ent_beta;
   c->fused = !(c->cfg.flags & TDDFT_FLAG_STREAMING) &&
              fused_supported(c->g, n_atoms, c->mixed ? sizeof(float2) : sizeof(double2));
+  if (c->fused && (st = dalloc_t(c, (size_t)c->cfg.n_k * Sx, &c->phkA)) != TDDFT_OK) return st;
   c->phA = d_phA;
   c->phAJ = d_phAJ;
   c->Eu = d_Eu;

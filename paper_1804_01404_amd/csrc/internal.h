@@ -120,6 +120,7 @@ struct FusedArgs {
   double* obs;             // [n_orb_tot][8]
   double* jnl;             // [n_orb_tot][4]
   T* coef;                 // [n_k][kCoef] stencil coefficients of the step, stage precision
+  double2* phkA;           // [n_k][S] exp(i kappa . x_e) at the step midpoint (set with coef)
   T lapc[3][4];            // off-centre Laplacian weights -1/2 c_m / h_mu^2, stage precision
 };
 

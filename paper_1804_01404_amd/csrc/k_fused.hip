@@ -229,6 +229,7 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, const int o, u
   }
   const bool length = !PERIODIC && a.efield != nullptr;
   const double2* __restrict__ phk = a.nl.phk + (size_t)k * S;
+  const double2* __restrict__ phkA = a.phkA + (size_t)k * S;  // exp(i kappa . x_e) of this step
   __syncthreads();
 
 #pragma unroll 1
@@ -240,8 +241,8 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, const int o, u
         double acc[2 * kMaxProj] = {0, 0, 0, 0, 0, 0, 0, 0};
         for (int e = e0 + lane; e < e1; e += 64) {
           const T2 v = u[a.nl.ent_idx[e]];
-          const double2 p1 = phk[e], p2 = a.phA[e];
-          const double pr = p1.x * p2.x - p1.y * p2.y, pim = p1.x * p2.y + p1.y * p2.x;
+          const double2 ph = phkA[e];
+          const double pr = ph.x, pim = ph.y;
           const double gr = pr * (double)v.x - pim * (double)v.y;
           const double gi = pr * (double)v.y + pim * (double)v.x;
 #pragma unroll
@@ -298,8 +299,8 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, const int o, u
           for (int p = 0; p < kMaxProj; ++p) E4[p] = eu[at * kMaxProj + p];
           for (int e = e0 + lane; e < e1; e += 64) {
             const int idx = a.nl.ent_idx[e];
-            const double2 p1 = phk[e], p2 = a.phA[e];
-            const double pr = p1.x * p2.x - p1.y * p2.y, pim = p1.x * p2.y + p1.y * p2.x;
+            const double2 ph = phkA[e];
+            const double pr = ph.x, pim = ph.y;
             double sr = 0.0, si = 0.0;
 #pragma unroll
             for (int p = 0; p < kMaxProj; ++p) {
@@ -448,6 +449,17 @@ __global__ void k_fused_coef(const double* __restrict__ kappa, int n_k, FusedCoe
   c[13] = c[14] = c[15] = (T)0;
 }
 
+// exp(i kappa . x_e) = exp(i k . x_e) exp(i A . x_e / c) for every k-point and
+// sphere entry, once per step (each workgroup then reads one factor per entry)
+__global__ void k_fused_phase(const double2* __restrict__ phk, const double2* __restrict__ phA, int S, int n_k,
+                              double2* __restrict__ out) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (size_t)n_k * S) return;
+  const int e = (int)(t % S);
+  const double2 p1 = phk[t], p2 = phA[e];
+  out[t] = make_double2(p1.x * p2.x - p1.y * p2.y, p1.x * p2.y + p1.y * p2.x);
+}
+
 template <typename T>
 hipError_t launch_fused_coef(const FusedArgs<T>& a, hipStream_t s) {
   FusedCoefIn in;
@@ -456,6 +468,10 @@ hipError_t launch_fused_coef(const FusedArgs<T>& a, hipStream_t s) {
   in.cdiag = a.cdiag;
   const int nk = a.g.n_k;
   hipLaunchKernelGGL((k_fused_coef<T>), dim3((unsigned)((nk + 63) / 64)), dim3(64), 0, s, a.kappa, nk, in, a.coef);
+  const size_t tot = (size_t)nk * a.nl.n_ent;
+  if (tot > 0)
+    hipLaunchKernelGGL(k_fused_phase, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, a.nl.phk, a.phA,
+                       a.nl.n_ent, nk, a.phkA);
   return hipGetLastError();
 }
 
