@@ -435,22 +435,18 @@ PZ_GAMMA, PZ_BETA1, PZ_BETA2 = -0.1423, 1.0529, 0.3334
 PZ_A, PZ_B, PZ_C, PZ_D = 0.0311, -0.048, 0.0020, -0.0116
 
 
-def lda_pz81(rho):
-    """Perdew-Zunger 1981 LDA, spin-unpolarised: returns (v_xc, eps_xc).
+def pz81_correlation(rho):
+    """Perdew-Zunger 1981 correlation, spin-unpolarised: returns (v_c, eps_c).
 
-    eps_x = -(3/4)(3 rho/pi)^(1/3); correlation: r_s >= 1 Pade form in sqrt(r_s),
-    r_s < 1 high-density logarithmic form; v_c = eps_c - (r_s/3) d eps_c/d r_s.
-    Densities below 1e-30 give zero."""
+    r_s >= 1: Pade form in sqrt(r_s); r_s < 1: high-density logarithmic form;
+    v_c = eps_c - (r_s/3) d eps_c/d r_s. Densities below 1e-30 give zero."""
     rho = np.asarray(rho, dtype=np.float64)
     v = np.zeros_like(rho)
     e = np.zeros_like(rho)
     m = rho >= 1e-30
-    r = rho[m]
-    rs = (3.0 / (4.0 * np.pi * r)) ** (1.0 / 3.0)
-    vx = -(3.0 * r / np.pi) ** (1.0 / 3.0)
-    ex = 0.75 * vx
-    ec = np.empty_like(r)
-    vc = np.empty_like(r)
+    rs = (3.0 / (4.0 * np.pi * rho[m])) ** (1.0 / 3.0)
+    ec = np.empty_like(rs)
+    vc = np.empty_like(rs)
     hi = rs >= 1.0
     s = np.sqrt(rs[hi])
     den = 1.0 + PZ_BETA1 * s + PZ_BETA2 * rs[hi]
@@ -460,8 +456,22 @@ def lda_pz81(rho):
     l = np.log(rs[lo])
     ec[lo] = PZ_A * l + PZ_B + PZ_C * rs[lo] * l + PZ_D * rs[lo]
     vc[lo] = PZ_A * l + (PZ_B - PZ_A / 3.0) + 2.0 / 3.0 * PZ_C * rs[lo] * l + (2.0 * PZ_D - PZ_C) / 3.0 * rs[lo]
-    v[m] = vx + vc
-    e[m] = ex + ec
+    v[m] = vc
+    e[m] = ec
+    return v, e
+
+
+def lda_pz81(rho):
+    """Perdew-Zunger 1981 LDA, spin-unpolarised: returns (v_xc, eps_xc).
+
+    Exchange eps_x = -(3/4)(3 rho/pi)^(1/3), v_x = (4/3) eps_x, plus the
+    correlation above. Densities below 1e-30 give zero."""
+    rho = np.asarray(rho, dtype=np.float64)
+    v, e = pz81_correlation(rho)
+    m = rho >= 1e-30
+    vx = -(3.0 * rho[m] / np.pi) ** (1.0 / 3.0)
+    v[m] = vx + v[m]
+    e[m] = 0.75 * vx + e[m]
     return v, e
 
 
@@ -486,14 +496,19 @@ class TDKS:
         self.v_loc = np.asarray(v_loc, dtype=np.float64)
         self.projs = [Projector(p.idx, p.x, p.beta, p.e_kb) for p in projectors]
         self.use_hartree = bool(hartree)
-        self.use_xc = bool(xc)
+        # xc: False / None (none), True or "lda" (PZ81), "tb09" or "bj" (Sec. 4.1)
+        self.xc_kind = ("lda" if xc is True else xc) if xc else None
+        if self.xc_kind not in (None, "lda", "tb09", "bj"):
+            raise ValueError(f"unknown xc {xc!r}")
+        self.use_xc = self.xc_kind is not None
+        self.mgga_c = None
         self.gauge = gauge
         self.predictor_corrector = bool(predictor_corrector)
         self._hker = coulomb_kernel_isolated(self.grid) if (hartree and not self.grid.periodic) else None
         self.A_now = np.zeros(3)            # A at the current time (for the current)
         self.rho = density(self.psi, self.kw, self.grid)
         self.rho0 = self.rho.copy()
-        self._update_potential()
+        self._update_potential(self.psi, self.A_now)
 
     @classmethod
     def from_system(cls, s, psi0=None, predictor_corrector=False):
@@ -502,15 +517,22 @@ class TDKS:
                    predictor_corrector=predictor_corrector)
 
     # potentials ----------------------------------------------------------
-    def _update_potential(self):
+    def _update_potential(self, psi, A):
+        """V_KS from self.rho; the BJ / TB09 exchange also needs the orbitals
+        psi (their kinetic energy density) and the vector potential A at
+        their time."""
         g = self.grid
         self.v_h = np.zeros(g.shape)
         self.v_xc = np.zeros(g.shape)
         self.e_xc = np.zeros(g.shape)
         if self.use_hartree:
             self.v_h = hartree_periodic(self.rho, g) if g.periodic else hartree_isolated(self.rho, g, self._hker)
-        if self.use_xc:
+        if self.xc_kind == "lda":
             self.v_xc, self.e_xc = lda_pz81(self.rho)
+        elif self.xc_kind is not None:
+            from . import mgga
+            self.v_xc, self.e_xc, self.mgga_c = mgga.mgga_potential(psi, self.kpts, self.kw, A, self.rho, g,
+                                                                   self.xc_kind, self.gauge)
         self.v_ks = self.v_loc + self.v_h + self.v_xc
 
     def _external(self, E):
@@ -545,12 +567,12 @@ class TDKS:
             pred = self._taylor_all(self.psi, V, A0, A1)
             V_n = V
             self.rho = density(pred, self.kw, self.grid)
-            self._update_potential()
+            self._update_potential(pred, A1)
             V = 0.5 * (V_n + self.v_ks)
         self.psi = self._taylor_all(self.psi, V, A0, A1)
         self.A_now = A1
         self.rho = density(self.psi, self.kw, self.grid)
-        self._update_potential()
+        self._update_potential(self.psi, self.A_now)
 
     def ground_state(self, n_iter, tau):
         """Prepare the initial state (Sec. 2.1) at A = 0: each iteration damps
@@ -567,7 +589,7 @@ class TDKS:
                 W = imaginary_time_step(self.psi[ik], tau, hop)
                 self.psi[ik] = gram_schmidt(W, self.grid)
             self.rho = density(self.psi, self.kw, self.grid)
-            self._update_potential()
+            self._update_potential(self.psi, zero)
             energies[it] = self.energy(zero)
         self.A_now = zero
         self.rho0 = self.rho.copy()
