@@ -59,7 +59,19 @@ typedef enum {
 enum { TDDFT_PERIODIC = 0, TDDFT_ISOLATED = 1 };
 enum { TDDFT_C128 = 0, TDDFT_MIXED = 1 };        /* precision of the orbital stream */
 enum { TDDFT_VELOCITY = 0, TDDFT_LENGTH = 1 };   /* gauge of the applied field     */
-enum { TDDFT_XC_NONE = 0, TDDFT_XC_PZ81 = 1 };
+/* Exchange-correlation potential (Sec. 3.1: adiabatic LDA; Sec. 4.1: the
+ * Becke-Johnson potential and the Tran-Blaha variant as alternatives).
+ * TDDFT_XC_TB09 and TDDFT_XC_BJ use the exchange potential
+ *   v_x = c v_BR + (3c - 2)(1/pi) sqrt(5/12) sqrt(2 t_s / rho_s)
+ * with the Becke-Roussel hole potential v_BR (gamma = 1), rho_s = rho/2 and
+ * t_s = tau/2, tau = sum_k w_k sum_n |(grad_h + i kappa_k) w_nk|^2 from the
+ * orbitals (kappa_k = k + A/c at the orbitals' time; k in the length gauge),
+ * grad rho and lap rho by the same 9-point differences, v_x = 0 where
+ * rho < 1e-30; plus PZ81 correlation. TB09: c = -0.012 + 1.023 sqrt(g),
+ * g = (1/Omega) int |grad rho| / rho, re-evaluated with every potential
+ * update; BJ: c = 1. These potentials have no energy functional: the energy
+ * reports the LDA exchange-correlation energy of the density. */
+enum { TDDFT_XC_NONE = 0, TDDFT_XC_PZ81 = 1, TDDFT_XC_TB09 = 2, TDDFT_XC_BJ = 3 };
 
 #define TDDFT_FLAG_ALLOW_UNSTABLE 0x1u /* skip the Taylor stability refusal      */
 #define TDDFT_FLAG_DEBUG_SYNC 0x2u     /* synchronise and check after each kernel */
@@ -89,7 +101,7 @@ typedef struct {
                              stencil and Taylor terms; FP64 density, current,
                              Poisson solve, norms and projector inner products */
   int32_t hartree;        /* 0 off, 1 on                                          */
-  int32_t xc;             /* TDDFT_XC_NONE or TDDFT_XC_PZ81                       */
+  int32_t xc;             /* TDDFT_XC_NONE, _PZ81, _TB09 or _BJ                   */
   int32_t gauge;          /* TDDFT_VELOCITY, or TDDFT_LENGTH (isolated only)      */
   uint32_t flags;         /* TDDFT_FLAG_*                                         */
   void *stream;           /* hipStream_t for all work, or NULL (default stream)   */
@@ -148,6 +160,10 @@ tddft_status tddft_set_orbitals(tddft_ctx *ctx, const double *psi);
 /* Total energy: sum_k w_k sum_n 2 <w|h_kin + V_loc + V_NL|w> + 1/2 int rho V_H
  * + int rho eps_xc (ion-ion constant omitted), at the last A seen. */
 tddft_status tddft_energy(tddft_ctx *ctx, double *E);
+
+/* The mixing parameter c of the BJ / TB09 exchange at the last potential
+ * update (1 for BJ). ESTATE for the other xc choices. */
+tddft_status tddft_xc_parameter(tddft_ctx *ctx, double *c);
 
 /* Orbital norms <w|w>, [n_k][n_orb]. */
 tddft_status tddft_norms(tddft_ctx *ctx, double *norms);

@@ -23,13 +23,24 @@ STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "EUNSTABLE",
 PERIODIC, ISOLATED = 0, 1
 C128, MIXED = 0, 1
 VELOCITY, LENGTH = 0, 1
-XC_NONE, XC_PZ81 = 0, 1
+XC_NONE, XC_PZ81, XC_TB09, XC_BJ = 0, 1, 2, 3
+_XC_CODES = {None: XC_NONE, False: XC_NONE, True: XC_PZ81, "lda": XC_PZ81, "tb09": XC_TB09, "bj": XC_BJ}
+
+
+def xc_code(xc) -> int:
+    """Library code of a system's xc choice: False/None, True or "lda", "tb09", "bj"."""
+    try:
+        return _XC_CODES[xc]
+    except (KeyError, TypeError):
+        raise ValueError(f"unknown xc choice {xc!r}") from None
+
 FLAG_ALLOW_UNSTABLE, FLAG_DEBUG_SYNC, FLAG_NO_GRAPH, FLAG_STREAMING, FLAG_NO_TUNE = 1, 2, 4, 8, 16
 FLAG_PREDICTOR_CORRECTOR = 32
 
 EXPORTED = ["tddft_abi_version", "tddft_init", "tddft_set_potential", "tddft_propagate",
             "tddft_density_current", "tddft_get_orbitals", "tddft_set_orbitals", "tddft_energy",
-            "tddft_norms", "tddft_dipole", "tddft_kick", "tddft_ground_state", "tddft_set_reference",
+            "tddft_norms", "tddft_xc_parameter", "tddft_dipole", "tddft_kick", "tddft_ground_state",
+            "tddft_set_reference",
             "tddft_excited_electrons", "tddft_last_timing", "tddft_time_kernel",
             "tddft_last_error", "tddft_free", "tddft_batch_create", "tddft_batch_set_potential",
             "tddft_batch_propagate", "tddft_batch_cell", "tddft_batch_last_timing", "tddft_batch_report",
@@ -104,6 +115,7 @@ def load_library(path: str = LIB_PATH):
     lib.tddft_set_orbitals.argtypes = [C.c_void_p, _dp]
     lib.tddft_energy.argtypes = [C.c_void_p, _dp]
     lib.tddft_norms.argtypes = [C.c_void_p, _dp]
+    lib.tddft_xc_parameter.argtypes = [C.c_void_p, _dp]
     lib.tddft_dipole.argtypes = [C.c_void_p, _dp]
     lib.tddft_kick.argtypes = [C.c_void_p, C.c_double, C.c_int32]
     lib.tddft_ground_state.argtypes = [C.c_void_p, C.c_int32, C.c_double, _dp]
@@ -116,7 +128,7 @@ def load_library(path: str = LIB_PATH):
     lib.tddft_free.argtypes = [C.c_void_p]
     lib.tddft_free.restype = None
     for name in ("tddft_init", "tddft_set_potential", "tddft_propagate", "tddft_density_current",
-                 "tddft_get_orbitals", "tddft_set_orbitals", "tddft_energy", "tddft_norms",
+                 "tddft_get_orbitals", "tddft_set_orbitals", "tddft_energy", "tddft_norms", "tddft_xc_parameter",
                  "tddft_dipole", "tddft_kick", "tddft_last_timing", "tddft_time_kernel"):
         getattr(lib, name).restype = C.c_int
     lib.tddft_batch_create.argtypes = [C.c_int32, C.POINTER(Config), C.POINTER(_dp), C.POINTER(C.c_void_p)]
@@ -223,7 +235,7 @@ class TDDFT:
         cfg.dt = s.dt
         cfg.precision = MIXED if prec == "mixed" else C128
         cfg.hartree = int(bool(s.hartree))
-        cfg.xc = XC_PZ81 if s.xc else XC_NONE
+        cfg.xc = xc_code(s.xc)
         cfg.gauge = LENGTH if s.gauge == "length" else VELOCITY
         cfg.flags = flags
         if torch_memory:
@@ -297,6 +309,12 @@ class TDDFT:
         e = C.c_double()
         self._check(self.lib.tddft_energy(self.h, C.byref(e)))
         return e.value
+
+    def xc_parameter(self) -> float:
+        """The BJ / TB09 mixing parameter c of the last potential update."""
+        v = C.c_double()
+        self._check(self.lib.tddft_xc_parameter(self.h, C.byref(v)))
+        return v.value
 
     def norms(self) -> np.ndarray:
         out = np.empty((self.n_k, self.n_orb))
@@ -389,7 +407,7 @@ def _config_for(system, precision, flags):
     cfg.dt = s.dt
     cfg.precision = MIXED if precision == "mixed" else C128
     cfg.hartree = int(bool(s.hartree))
-    cfg.xc = XC_PZ81 if s.xc else XC_NONE
+    cfg.xc = xc_code(s.xc)
     cfg.gauge = LENGTH if s.gauge == "length" else VELOCITY
     cfg.flags = flags
     return cfg, (kpt, kw)

@@ -57,6 +57,9 @@ struct tddft_ctx {
   float* Vf = nullptr;
   double* rho_part = nullptr;
   int rho_chunk = 64, rho_nchunks = 0;
+  // BJ / TB09 exchange: kinetic energy density, its chunk partials, v_x,
+  // per-block sums of |grad rho| / rho and (c, g)
+  double *tau = nullptr, *tau_part = nullptr, *vx_mgga = nullptr, *gpart = nullptr, *cval = nullptr;
   double2* fft = nullptr;
   double* Kfft = nullptr;
   int M[3] = {0, 0, 0};
@@ -245,12 +248,32 @@ typename Vec2<T>::type* as2(void* p) {
 // ---------------------------------------------------------------------------
 // enqueue helpers
 
+MggaArgs mgga_args(const tddft_ctx* c) {
+  MggaArgs a{};
+  a.g = c->g;
+  std::memcpy(a.d1, c->dh, sizeof(a.d1));
+  for (int mu = 0; mu < 3; ++mu)
+    for (int m = 0; m < 5; ++m) a.d2[mu][m] = -2.0 * c->lap[mu][m];
+  return a;
+}
+
+bool is_mgga(const tddft_ctx* c) { return c->cfg.xc == TDDFT_XC_TB09 || c->cfg.xc == TDDFT_XC_BJ; }
+
 template <typename T>
 tddft_status enqueue_density_potential(tddft_ctx* c) {
   const int N = (int)c->N;
-  LAUNCH(launch_rho_partial<T>(as2<T>(c->W), c->kw_d, c->cfg.n_orb, c->cfg.n_k, N, c->rho_chunk,
-                               c->rho_part, c->stream),
-         "rho_partial");
+  const bool mgga = is_mgga(c);
+  if (mgga) {
+    // rho and the kinetic energy density with kappa at the orbitals' time
+    LAUNCH(launch_rho_tau_partial<T>(as2<T>(c->W), c->kw_d, c->kappaJ, mgga_args(c), c->rho_chunk, c->rho_part,
+                                     c->tau_part, c->stream),
+           "rho_tau_partial");
+    LAUNCH(launch_rho_reduce(c->tau_part, c->rho_nchunks, N, c->tau, c->stream), "tau_reduce");
+  } else {
+    LAUNCH(launch_rho_partial<T>(as2<T>(c->W), c->kw_d, c->cfg.n_orb, c->cfg.n_k, N, c->rho_chunk,
+                                 c->rho_part, c->stream),
+           "rho_partial");
+  }
   LAUNCH(launch_rho_reduce(c->rho_part, c->rho_nchunks, N, c->rho, c->stream), "rho_reduce");
   if (!c->potential_set) return TDDFT_OK;
   if (c->cfg.hartree) {
@@ -262,9 +285,13 @@ tddft_status enqueue_density_potential(tddft_ctx* c) {
     for (int ax = 0; ax < 3; ++ax)
       LAUNCH(launch_fft_axis(c->fft, c->M[0], c->M[1], c->M[2], ax, +1, c->stream), "fft inv");
   }
+  if (mgga)
+    LAUNCH(launch_mgga_potential(c->rho, c->tau, mgga_args(c), c->cfg.xc == TDDFT_XC_TB09, c->dV, c->volume,
+                                 c->gpart, c->cval, c->vx_mgga, c->stream),
+           "mgga exchange");
   LAUNCH(launch_xc_assemble(c->fft, c->g.n1, c->g.n2, c->g.n3, c->M[0], c->M[1], c->M[2], c->vh_scale,
-                            c->rho, c->Vloc, c->cfg.hartree, c->cfg.xc, c->Vd, c->Vf, c->vh, c->exc,
-                            c->stream),
+                            c->rho, c->Vloc, c->cfg.hartree, c->cfg.xc, c->vx_mgga, c->Vd, c->Vf, c->vh,
+                            c->exc, c->stream),
          "xc_assemble");
   return TDDFT_OK;
 }
@@ -742,7 +769,8 @@ tddft_status tddft_init(const tddft_config* cfg, const double* psi0, tddft_ctx**
   if (cfg->gauge != TDDFT_VELOCITY && cfg->gauge != TDDFT_LENGTH) return bad("gauge");
   if (cfg->gauge == TDDFT_LENGTH && cfg->boundary != TDDFT_ISOLATED)
     return bad("length gauge needs an isolated box");
-  if (cfg->xc != TDDFT_XC_NONE && cfg->xc != TDDFT_XC_PZ81) return bad("xc");
+  if (cfg->xc != TDDFT_XC_NONE && cfg->xc != TDDFT_XC_PZ81 && cfg->xc != TDDFT_XC_TB09 && cfg->xc != TDDFT_XC_BJ)
+    return bad("xc");
   if ((cfg->dev_alloc == nullptr) != (cfg->dev_free == nullptr)) return bad("dev_alloc and dev_free go together");
   c->kpt.assign(cfg->kpt, cfg->kpt + 3 * cfg->n_k);
   c->kw.assign(cfg->kw, cfg->kw + cfg->n_k);
@@ -839,6 +867,10 @@ tddft_status tddft_init(const tddft_config* cfg, const double* psi0, tddft_ctx**
   c->rho_chunk = 64;
   c->rho_nchunks = (int)((c->n_orb_tot + c->rho_chunk - 1) / c->rho_chunk);
   if ((st = dalloc_t(c, (size_t)c->rho_nchunks * N, &c->rho_part))) return cleanup(st);
+  if (is_mgga(c) && ((st = dalloc_t(c, (size_t)c->rho_nchunks * N, &c->tau_part)) || (st = dalloc_t(c, N, &c->tau)) ||
+                     (st = dalloc_t(c, N, &c->vx_mgga)) || (st = dalloc_t(c, (N + 255) / 256, &c->gpart)) ||
+                     (st = dalloc_t(c, 2, &c->cval))))
+    return cleanup(st);
   const size_t Mt = (size_t)c->M[0] * c->M[1] * c->M[2];
   if ((st = dalloc_t(c, Mt, &c->fft)) || (st = dalloc_t(c, Mt, &c->Kfft))) return cleanup(st);
   if ((st = dalloc_t(c, 3 * (size_t)cfg->n_k, &c->kpt_d)) || (st = dalloc_t(c, (size_t)cfg->n_k, &c->kw_d)) ||
@@ -863,6 +895,14 @@ tddft_status tddft_init(const tddft_config* cfg, const double* psi0, tddft_ctx**
     return cleanup(fail(c, TDDFT_EDEVICE, "initial fill failed"));
   if (launch_set_int(c->nanflag, 0, c->stream) != hipSuccess)
     return cleanup(fail(c, TDDFT_EDEVICE, "flag reset failed"));
+  {
+    // kappa, kappaJ and the field at A = 0 until the first step sets them
+    const double Az[6] = {0, 0, 0, 0, 0, 0};
+    if (hipMemcpyAsync(c->Aobs, Az, sizeof(Az), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+        launch_step_params(c->Aobs, c->counter, 0, c->kpt_d, cfg->n_k, c->ent_x, 0, cfg->gauge, cfg->dt, c->kappa,
+                           c->kappaJ, c->efield, c->phA, c->phAJ, c->Alast, c->stream) != hipSuccess)
+      return cleanup(fail(c, TDDFT_EDEVICE, "initial field parameters failed"));
+  }
   if ((st = potential_dispatch(c)) != TDDFT_OK) return cleanup(st);
   if (hipMemcpyAsync(c->rho0, c->rho, N * sizeof(double), hipMemcpyDeviceToDevice, c->stream) != hipSuccess ||
       hipStreamSynchronize(c->stream) != hipSuccess)
@@ -1187,6 +1227,18 @@ tddft_status tddft_energy(tddft_ctx* c, double* E) {
   HIP_TRY(hipMemcpyAsync(gs, c->sums, sizeof(gs), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   *E = sc[3] + (c->cfg.hartree ? gs[0] : 0.0) + (c->cfg.xc ? gs[1] : 0.0);
+  return TDDFT_OK;
+}
+
+tddft_status tddft_xc_parameter(tddft_ctx* c, double* cpar) {
+  if (!c || !cpar) return c ? fail(c, TDDFT_EINVAL, "null c") : TDDFT_EINVAL;
+  if (c->poisoned) return fail(c, TDDFT_ESTATE, "context poisoned: " + c->err);
+  if (!is_mgga(c)) return fail(c, TDDFT_ESTATE, "the mixing parameter belongs to the BJ / TB09 exchange");
+  if (!c->potential_set) return fail(c, TDDFT_ESTATE, "xc_parameter before set_potential");
+  double v[2];
+  HIP_TRY(hipMemcpyAsync(v, c->cval, sizeof(v), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  *cpar = v[0];
   return TDDFT_OK;
 }
 

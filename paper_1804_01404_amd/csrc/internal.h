@@ -124,6 +124,14 @@ struct FusedArgs {
   T lapc[3][4];            // off-centre Laplacian weights -1/2 c_m / h_mu^2, stage precision
 };
 
+// Becke-Johnson / Tran-Blaha exchange (k_mgga.hip): grid and the plain
+// 9-point derivative weights
+struct MggaArgs {
+  Geometry g;
+  double d1[3][4];         // d_m / h_mu
+  double d2[3][5];         // c_m / h_mu^2
+};
+
 // ---- launchers (defined in the .hip files) --------------------------------
 template <typename T>
 hipError_t launch_stage(int mode, int bc, const StageArgs<T>& a, hipStream_t s);
@@ -160,8 +168,14 @@ hipError_t launch_pack_rho(const double* rho, int n1, int n2, int n3, int M1, in
 hipError_t launch_scale_real(double2* data, const double* K, size_t total, hipStream_t s);
 hipError_t launch_xc_assemble(const double2* data, int n1, int n2, int n3, int M1, int M2, int M3,
                               double vh_scale, const double* rho, const double* Vloc, int hartree,
-                              int xc, double* Vd, float* Vf, double* vh, double* exc,
+                              int xc, const double* vx_mgga, double* Vd, float* Vf, double* vh, double* exc,
                               hipStream_t s);
+template <typename T>
+hipError_t launch_rho_tau_partial(const typename Vec2<T>::type* w, const double* kw, const double* kappa,
+                                  const MggaArgs& a, int chunk, double* part_rho, double* part_tau,
+                                  hipStream_t s);
+hipError_t launch_mgga_potential(const double* rho, const double* tau, const MggaArgs& a, int tb09, double dV,
+                                 double volume, double* gpart, double* cval, double* vx, hipStream_t s);
 
 hipError_t launch_finish(const double* obs, int tiles, const double* jnl, int use_nl,
                          const double* kw, const double* kappaJ, int n_orb, int n_k, double dV,

@@ -330,7 +330,9 @@ hipError_t launch_scale_real(double2* data, const double* K, size_t total, hipSt
 // ---------------------------------------------------------------- LDA + V
 // Perdew-Zunger 1981, spin-unpolarised; r_s >= 1 uses the Pade form in
 // sqrt(r_s), r_s < 1 the high-density logarithmic form; rho < 1e-30 -> 0.
-__device__ void pz81(double rho, double* v, double* e) {
+// exchange_too = 0 leaves out the LDA exchange potential (the BJ / TB09
+// exchange replaces it); e is always the full LDA energy density
+__device__ void pz81(double rho, int exchange_too, double* v, double* e) {
   if (!(rho >= 1e-30)) {
     *v = 0.0;
     *e = 0.0;
@@ -354,13 +356,15 @@ __device__ void pz81(double rho, double* v, double* e) {
     ec = A * l + B + C * rs * l + D * rs;
     vc = A * l + (B - A * third) + 2.0 * third * C * rs * l + (2.0 * D - C) * third * rs;
   }
-  *v = vx + vc;
+  *v = exchange_too ? vx + vc : vc;
   *e = ex + ec;
 }
 
+// xc: 0 none, 1 PZ81, 2 and 3 the exchange in vx_mgga plus PZ81 correlation
 __global__ void k_xc_assemble(const double2* data, int n1, int n2, int n3, int M1, int M2,
                               double vh_scale, const double* rho, const double* Vloc, int hartree,
-                              int xc, double* Vd, float* Vf, double* vh_out, double* exc) {
+                              int xc, const double* vx_mgga, double* Vd, float* Vf, double* vh_out,
+                              double* exc) {
   const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t N = (size_t)n1 * n2 * n3;
   if (p >= N) return;
@@ -370,7 +374,10 @@ __global__ void k_xc_assemble(const double2* data, int n1, int n2, int n3, int M
   double vh = 0.0;
   if (hartree) vh = data[((size_t)z * M2 + y) * M1 + x].x * vh_scale;
   double vxc = 0.0, e = 0.0;
-  if (xc) pz81(rho[p], &vxc, &e);
+  if (xc) {
+    pz81(rho[p], xc == 1, &vxc, &e);
+    if (xc >= 2) vxc += vx_mgga[p];
+  }
   const double v = Vloc[p] + vh + vxc;
   Vd[p] = v;
   Vf[p] = (float)v;
@@ -380,12 +387,12 @@ __global__ void k_xc_assemble(const double2* data, int n1, int n2, int n3, int M
 
 hipError_t launch_xc_assemble(const double2* data, int n1, int n2, int n3, int M1, int M2, int M3,
                               double vh_scale, const double* rho, const double* Vloc, int hartree,
-                              int xc, double* Vd, float* Vf, double* vh, double* exc,
+                              int xc, const double* vx_mgga, double* Vd, float* Vf, double* vh, double* exc,
                               hipStream_t s) {
   (void)M3;
   const size_t N = (size_t)n1 * n2 * n3;
   hipLaunchKernelGGL(k_xc_assemble, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, data, n1, n2,
-                     n3, M1, M2, vh_scale, rho, Vloc, hartree, xc, Vd, Vf, vh, exc);
+                     n3, M1, M2, vh_scale, rho, Vloc, hartree, xc, vx_mgga, Vd, Vf, vh, exc);
   return hipGetLastError();
 }
 

@@ -1,0 +1,296 @@
+// Becke-Johnson and Tran-Blaha exchange potentials (Sec. 4.1 names both as
+// alternatives to the adiabatic LDA; the formulas are the published ones:
+// Becke and Johnson 2006, Tran and Blaha 2009, with the Becke-Roussel 1989
+// exchange-hole potential at gamma = 1). Spin-saturated: rho_s = rho/2,
+// t_s = tau/2.
+//
+//   tau(r)  = sum_k w_k sum_n |(grad_h + i kappa_k) w_nk(r)|^2   (= 2 x 1/2 |.|^2)
+//   v_x     = c v_BR + (3c - 2) (1/pi) sqrt(5/12) sqrt(2 t_s / rho_s)
+//   v_BR    = -(1 - e^-x - x e^-x / 2) / b,   b^3 = x^3 e^-x / (8 pi rho_s)
+//   x       : x e^(-2x/3) / (x - 2) = (2/3) pi^(2/3) rho_s^(5/3) / Q_s
+//   Q_s     = (lap rho_s - 2 (T_s - |grad rho_s|^2 / (4 rho_s))) / 6,  T_s = tau
+//   c       = 1 (BJ) or -0.012 + 1.023 sqrt(g), g = (1/Omega) int |grad rho| / rho (TB09)
+//
+// kappa_k = k + A/c for the A at the orbitals' time (kappaJ of the last step),
+// grad and lap of rho use the same 9-point differences as the Hamiltonian,
+// and points with rho < 1e-30 get v_x = 0. Everything is FP64; reductions
+// run in a fixed order.
+#include "internal.h"
+
+namespace td {
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kRhoMin = 1e-30;
+
+// neighbour offset along one axis: j + m wrapped (periodic) or -1 outside
+__device__ __forceinline__ int nb(int j, int m, int n, int periodic) {
+  int q = j + m;
+  if (periodic) {
+    q = q < 0 ? q + n : (q >= n ? q - n : q);
+    return q;
+  }
+  return (q < 0 || q >= n) ? -1 : q;
+}
+
+// the 9-point first derivatives of a real grid field at (x, y, z)
+__device__ void grad_field(const double* f, const MggaArgs& a, int x, int y, int z, double out[3]) {
+  const Geometry& g = a.g;
+  const size_t row = (size_t)g.n1;
+  const size_t plane = (size_t)g.n1 * g.n2;
+  const size_t base_x = (size_t)z * plane + (size_t)y * row;
+  const size_t base_y = (size_t)z * plane + x;
+  const size_t base_z = (size_t)y * row + x;
+  double d[3] = {0.0, 0.0, 0.0};
+  for (int m = 1; m <= kHalf; ++m) {
+    const int xp = nb(x, m, g.n1, g.periodic), xm = nb(x, -m, g.n1, g.periodic);
+    const int yp = nb(y, m, g.n2, g.periodic), ym = nb(y, -m, g.n2, g.periodic);
+    const int zp = nb(z, m, g.n3, g.periodic), zm = nb(z, -m, g.n3, g.periodic);
+    const double fxp = xp >= 0 ? f[base_x + xp] : 0.0, fxm = xm >= 0 ? f[base_x + xm] : 0.0;
+    const double fyp = yp >= 0 ? f[base_y + yp * row] : 0.0, fym = ym >= 0 ? f[base_y + ym * row] : 0.0;
+    const double fzp = zp >= 0 ? f[base_z + zp * plane] : 0.0, fzm = zm >= 0 ? f[base_z + zm * plane] : 0.0;
+    d[0] += a.d1[0][m - 1] * (fxp - fxm);
+    d[1] += a.d1[1][m - 1] * (fyp - fym);
+    d[2] += a.d1[2][m - 1] * (fzp - fzm);
+  }
+  out[0] = d[0];
+  out[1] = d[1];
+  out[2] = d[2];
+}
+
+// the 9-point Laplacian of a real grid field at (x, y, z)
+__device__ double lap_field(const double* f, const MggaArgs& a, int x, int y, int z) {
+  const Geometry& g = a.g;
+  const size_t row = (size_t)g.n1;
+  const size_t plane = (size_t)g.n1 * g.n2;
+  const size_t p = (size_t)z * plane + (size_t)y * row + x;
+  const double f0 = f[p];
+  double s = (a.d2[0][0] + a.d2[1][0] + a.d2[2][0]) * f0;
+  const size_t base_x = (size_t)z * plane + (size_t)y * row;
+  const size_t base_y = (size_t)z * plane + x;
+  const size_t base_z = (size_t)y * row + x;
+  for (int m = 1; m <= kHalf; ++m) {
+    const int xp = nb(x, m, g.n1, g.periodic), xm = nb(x, -m, g.n1, g.periodic);
+    const int yp = nb(y, m, g.n2, g.periodic), ym = nb(y, -m, g.n2, g.periodic);
+    const int zp = nb(z, m, g.n3, g.periodic), zm = nb(z, -m, g.n3, g.periodic);
+    const double sx = (xp >= 0 ? f[base_x + xp] : 0.0) + (xm >= 0 ? f[base_x + xm] : 0.0);
+    const double sy = (yp >= 0 ? f[base_y + yp * row] : 0.0) + (ym >= 0 ? f[base_y + ym * row] : 0.0);
+    const double sz = (zp >= 0 ? f[base_z + zp * plane] : 0.0) + (zm >= 0 ? f[base_z + zm * plane] : 0.0);
+    s += a.d2[0][m] * sx + a.d2[1][m] * sy + a.d2[2][m] * sz;
+  }
+  return s;
+}
+
+__device__ __forceinline__ double br_f(double x) { return x * exp(-2.0 * x / 3.0) / (x - 2.0); }
+
+// Root of x e^(-2x/3) / (x - 2) = y: (0, 2) for y < 0, (2, inf) for y > 0,
+// 2 for y = +-inf; bisection until the midpoint meets an end of the bracket.
+__device__ double br_root(double y) {
+  if (!isfinite(y)) return 2.0;
+  double lo, hi;
+  if (y < 0.0) {
+    lo = 0.0;
+    hi = 2.0;
+  } else {
+    lo = 2.0;
+    hi = 4.0;
+    for (int i = 0; i < 64 && br_f(hi) > y; ++i) {
+      lo = hi;
+      hi *= 2.0;
+    }
+  }
+  for (int i = 0; i < 2200; ++i) {
+    const double mid = 0.5 * (lo + hi);
+    if (!(mid > lo && mid < hi)) break;
+    if (br_f(mid) > y)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- rho and tau
+// part_rho[c][p] = sum_{o in chunk c} 2 w_k |w_o(p)|^2 and
+// part_tau[c][p] = sum_{o in chunk c} w_k |(grad_h + i kappa_k) w_o(p)|^2, in order.
+template <typename T>
+__global__ __launch_bounds__(256) void k_rho_tau_partial(const typename Vec2<T>::type* __restrict__ w,
+                                                         const double* __restrict__ kw,
+                                                         const double* __restrict__ kappa, MggaArgs a, int chunk,
+                                                         double* __restrict__ part_rho,
+                                                         double* __restrict__ part_tau) {
+  const Geometry& g = a.g;
+  const int N = g.n1 * g.n2 * g.n3;
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= N) return;
+  const int x = p % g.n1, y = (p / g.n1) % g.n2, z = p / (g.n1 * g.n2);
+  // flat offsets of the 24 neighbours, -1 outside an isolated box
+  int off[3][2 * kHalf];
+  for (int m = 1; m <= kHalf; ++m) {
+    int q;
+    q = nb(x, m, g.n1, g.periodic);
+    off[0][2 * (m - 1)] = q < 0 ? -1 : p - x + q;
+    q = nb(x, -m, g.n1, g.periodic);
+    off[0][2 * (m - 1) + 1] = q < 0 ? -1 : p - x + q;
+    q = nb(y, m, g.n2, g.periodic);
+    off[1][2 * (m - 1)] = q < 0 ? -1 : p + (q - y) * g.n1;
+    q = nb(y, -m, g.n2, g.periodic);
+    off[1][2 * (m - 1) + 1] = q < 0 ? -1 : p + (q - y) * g.n1;
+    q = nb(z, m, g.n3, g.periodic);
+    off[2][2 * (m - 1)] = q < 0 ? -1 : p + (q - z) * g.n1 * g.n2;
+    q = nb(z, -m, g.n3, g.periodic);
+    off[2][2 * (m - 1) + 1] = q < 0 ? -1 : p + (q - z) * g.n1 * g.n2;
+  }
+  const int n_tot = g.n_orb * g.n_k;
+  const int o0 = blockIdx.y * chunk;
+  const int o1 = min(n_tot, o0 + chunk);
+  double acc_r = 0.0, acc_t = 0.0;
+  for (int o = o0; o < o1; ++o) {
+    const int k = o / g.n_orb;
+    const auto* wo = w + (size_t)o * N;
+    const auto c0 = wo[p];
+    const double re = (double)c0.x, im = (double)c0.y;
+    double t = 0.0;
+    for (int mu = 0; mu < 3; ++mu) {
+      double dr = 0.0, di = 0.0;
+      for (int m = 0; m < kHalf; ++m) {
+        const int qp = off[mu][2 * m], qm = off[mu][2 * m + 1];
+        double pr = 0.0, pi = 0.0, mr = 0.0, mi = 0.0;
+        if (qp >= 0) {
+          const auto v = wo[qp];
+          pr = (double)v.x;
+          pi = (double)v.y;
+        }
+        if (qm >= 0) {
+          const auto v = wo[qm];
+          mr = (double)v.x;
+          mi = (double)v.y;
+        }
+        dr += a.d1[mu][m] * (pr - mr);
+        di += a.d1[mu][m] * (pi - mi);
+      }
+      // (d + i kappa w)
+      const double km = kappa[3 * k + mu];
+      const double gr = dr - km * im, gi = di + km * re;
+      t += gr * gr + gi * gi;
+    }
+    acc_r += 2.0 * kw[k] * (re * re + im * im);
+    acc_t += kw[k] * t;
+  }
+  part_rho[(size_t)blockIdx.y * N + p] = acc_r;
+  part_tau[(size_t)blockIdx.y * N + p] = acc_t;
+}
+
+template <typename T>
+hipError_t launch_rho_tau_partial(const typename Vec2<T>::type* w, const double* kw, const double* kappa,
+                                  const MggaArgs& a, int chunk, double* part_rho, double* part_tau,
+                                  hipStream_t s) {
+  const int N = a.g.n1 * a.g.n2 * a.g.n3;
+  const int nchunks = (a.g.n_orb * a.g.n_k + chunk - 1) / chunk;
+  hipLaunchKernelGGL((k_rho_tau_partial<T>), dim3((N + 255) / 256, nchunks), dim3(256), 0, s, w, kw, kappa, a,
+                     chunk, part_rho, part_tau);
+  return hipGetLastError();
+}
+template hipError_t launch_rho_tau_partial<double>(const double2*, const double*, const double*, const MggaArgs&,
+                                                   int, double*, double*, hipStream_t);
+template hipError_t launch_rho_tau_partial<float>(const float2*, const double*, const double*, const MggaArgs&,
+                                                  int, double*, double*, hipStream_t);
+
+// ---------------------------------------------------------------- c of TB09
+// gpart[b] = sum over the points of block b of |grad_h rho| / rho (rho >= 1e-30),
+// combined by a fixed pairwise tree.
+__global__ __launch_bounds__(256) void k_mgga_gpart(const double* __restrict__ rho, MggaArgs a,
+                                                    double* __restrict__ gpart) {
+  __shared__ double red[256];
+  const Geometry& g = a.g;
+  const int N = g.n1 * g.n2 * g.n3;
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  double v = 0.0;
+  if (p < N && rho[p] >= kRhoMin) {
+    const int x = p % g.n1, y = (p / g.n1) % g.n2, z = p / (g.n1 * g.n2);
+    double d[3];
+    grad_field(rho, a, x, y, z, d);
+    v = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) / rho[p];
+  }
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) gpart[blockIdx.x] = red[0];
+}
+
+// one workgroup: g = dV / Omega * sum_b gpart[b] (thread t sums b = t, t + 256,
+// ... in order, then the tree); cval[0] = c, cval[1] = g
+__global__ __launch_bounds__(256) void k_mgga_c(const double* __restrict__ gpart, int nblocks, double scale,
+                                                int tb09, double* __restrict__ cval) {
+  __shared__ double red[256];
+  double v = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += 256) v += gpart[b];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double gg = red[0] * scale;
+    cval[0] = tb09 ? -0.012 + 1.023 * sqrt(gg) : 1.0;
+    cval[1] = gg;
+  }
+}
+
+// ---------------------------------------------------------------- v_x
+__global__ __launch_bounds__(256) void k_mgga_vx(const double* __restrict__ rho, const double* __restrict__ tau,
+                                                 const double* __restrict__ cval, MggaArgs a,
+                                                 double* __restrict__ vx) {
+  const Geometry& g = a.g;
+  const int N = g.n1 * g.n2 * g.n3;
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= N) return;
+  const double r = rho[p];
+  if (!(r >= kRhoMin)) {
+    vx[p] = 0.0;
+    return;
+  }
+  const int x = p % g.n1, y = (p / g.n1) % g.n2, z = p / (g.n1 * g.n2);
+  double d[3];
+  grad_field(rho, a, x, y, z, d);
+  const double lap = lap_field(rho, a, x, y, z);
+  const double c = cval[0];
+  // one spin channel of the saturated density
+  const double rs = 0.5 * r;
+  const double gsq = 0.25 * (d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+  const double ls = 0.5 * lap;
+  const double ts = 0.5 * tau[p];
+  const double Ts = 2.0 * ts;
+  const double D = Ts - 0.25 * gsq / rs;
+  const double Q = (ls - 2.0 * D) / 6.0;
+  const double yv = (2.0 / 3.0) * pow(kPi, 2.0 / 3.0) * pow(rs, 5.0 / 3.0) / Q;
+  const double xr = br_root(yv);
+  const double ex = exp(-xr);
+  const double b = cbrt(xr * xr * xr * ex / (8.0 * kPi * rs));
+  const double vbr = -(1.0 - ex - 0.5 * xr * ex) / b;
+  const double kin = sqrt(5.0 / 12.0) / kPi * sqrt(2.0 * ts / rs);
+  vx[p] = c * vbr + (3.0 * c - 2.0) * kin;
+}
+
+hipError_t launch_mgga_potential(const double* rho, const double* tau, const MggaArgs& a, int tb09, double dV,
+                                 double volume, double* gpart, double* cval, double* vx, hipStream_t s) {
+  const int N = a.g.n1 * a.g.n2 * a.g.n3;
+  const int nb = (N + 255) / 256;
+  hipLaunchKernelGGL(k_mgga_gpart, dim3(nb), dim3(256), 0, s, rho, a, gpart);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_mgga_c, dim3(1), dim3(256), 0, s, gpart, nb, dV / volume, tb09, cval);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_mgga_vx, dim3(nb), dim3(256), 0, s, rho, tau, cval, a, vx);
+  return hipGetLastError();
+}
+
+}  // namespace td

@@ -104,7 +104,7 @@ def _cfg(**kw):
 
 @pytest.mark.parametrize("bad", [dict(n=[7, 16, 16]), dict(dt=0.0), dict(precision=7),
                                  dict(gauge=1), dict(n_orb=0), dict(abi_version=99),
-                                 dict(struct_size=8), dict(xc=3), dict(boundary=5)])
+                                 dict(struct_size=8), dict(xc=4), dict(xc=-1), dict(boundary=5)])
 def test_init_rejects_bad_config_without_device(bad):
     from paper_1804_01404_amd import binding
     lib = binding.load_library()
