@@ -198,6 +198,19 @@ def accuracy_report():
     return out
 
 
+def bench_mgga(system, precision, lda_ms, steps=60, warmup=10):
+    """The same cell and path with the Tran-Blaha exchange (Sec. 4.1): step time,
+    its ratio to the LDA step, and the density pass that also forms tau."""
+    import copy
+    import numpy as np
+    s = copy.copy(system)
+    s.xc = "tb09"
+    ms, dev_ms, kern, J = time_path(s, precision, steps, warmup)
+    return {"xc": "tb09", "ms_per_step": ms, "device_ms_per_step": dev_ms, "lda_ms_per_step": lda_ms,
+            "ratio_to_lda": ms / lda_ms, "density_tau_ms": kern["density_ms"],
+            "fused_ms": kern["fused_ms"], "current_finite": bool(np.all(np.isfinite(J)))}
+
+
 def bench_batch(steps=30, warmup=8):
     """The uneven-batch path on 64 seeded cells (grids 12..32, up to 32
     orbitals and 8 k-points each: the 64-cell workload with the orbital and
@@ -277,6 +290,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the uneven-batch line")
     ap.add_argument("--no-multiscale", action="store_true", help="skip the learned multiscale line")
     ap.add_argument("--no-accuracy", action="store_true", help="skip the 1000-step accuracy report")
+    ap.add_argument("--no-mgga", action="store_true", help="skip the Tran-Blaha exchange line")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="also run a plain device copy of this many MB (a known-size "
                          "reference for the HBM byte counters of a profiler run)")
@@ -367,6 +381,8 @@ def main():
         out["twin"] = {"precision": other, "value": og / (ms2 * 1e-3), "ms_per_step": ms2,
                        "kernels_ms": kern2,
                        "stage_GBs": 3 * (16 if other == "c128" else 8) * og / (kern2["stage_ms"] * 1e-3) / 1e9}
+    if not args.no_mgga:
+        out["mgga"] = bench_mgga(s, args.precision, ms)
     if not args.no_accuracy:
         out["accuracy"] = accuracy_report()
     if not args.no_batch:

@@ -215,7 +215,10 @@ enum { TDDFT_KERNEL_STAGE = 0, TDDFT_KERNEL_PROJECT = 1, TDDFT_KERNEL_OBSERVE = 
  * contents are scratch between steps, so the state is unchanged.
  * TDDFT_KERNEL_FUSED is the whole four-stage update of a context that takes the
  * LDS-resident step (EINVAL otherwise); the orbitals are saved to the stage
- * buffers before and restored after, so the state is unchanged too. Requires
+ * buffers before and restored after, so the state is unchanged too.
+ * TDDFT_KERNEL_DENSITY is the pass that sums the density over the orbitals
+ * (with the kinetic energy density under BJ / TB09) into its partial sums,
+ * which are scratch between steps. Requires
  * set_potential; EINVAL for an unknown kernel or reps < 1. */
 tddft_status tddft_time_kernel(tddft_ctx *ctx, int32_t which, int32_t reps, double *ms_per_launch);
 

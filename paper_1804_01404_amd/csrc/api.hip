@@ -607,6 +607,10 @@ tddft_status launch_one(tddft_ctx* c, int which) {
     LAUNCH(launch_observe<T>(c->bc, oa, c->stream), "observe");
   } else if (which == TDDFT_KERNEL_FUSED) {
     LAUNCH(launch_fused<T>(fused_args<T>(c), c->stream), "fused step");
+  } else if (is_mgga(c)) {
+    LAUNCH(launch_rho_tau_partial<T>(as2<T>(c->W), c->kw_d, c->kappaJ, mgga_args(c), c->rho_chunk, c->rho_part,
+                                     c->tau_part, c->stream),
+           "rho_tau_partial");
   } else {
     LAUNCH(launch_rho_partial<T>(as2<T>(c->W), c->kw_d, c->cfg.n_orb, c->cfg.n_k, (int)c->N, c->rho_chunk,
                                  c->rho_part, c->stream),

@@ -116,7 +116,12 @@ __device__ double br_root(double y) {
 // ---------------------------------------------------------------- rho and tau
 // part_rho[c][p] = sum_{o in chunk c} 2 w_k |w_o(p)|^2 and
 // part_tau[c][p] = sum_{o in chunk c} w_k |(grad_h + i kappa_k) w_o(p)|^2, in order.
-template <typename T>
+// The 24 neighbour loads of an orbital carry no branch (outside an isolated
+// box the index points back at p and the value is masked to 0), so they
+// issue back to back. Launch ids are mapped so that the point blocks of one
+// orbital chunk run on one XCD and share its L2: hardware block b runs on
+// XCD b mod 8, and the blocks of each XCD take consecutive logical ids.
+template <typename T, bool PERIODIC>
 __global__ __launch_bounds__(256) void k_rho_tau_partial(const typename Vec2<T>::type* __restrict__ w,
                                                          const double* __restrict__ kw,
                                                          const double* __restrict__ kappa, MggaArgs a, int chunk,
@@ -124,50 +129,51 @@ __global__ __launch_bounds__(256) void k_rho_tau_partial(const typename Vec2<T>:
                                                          double* __restrict__ part_tau) {
   const Geometry& g = a.g;
   const int N = g.n1 * g.n2 * g.n3;
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nbx = (N + 255) / 256;
+  const int total = gridDim.x, b8 = blockIdx.x % 8, q8 = total / 8, r8 = total % 8;
+  const int L = b8 * q8 + min(b8, r8) + blockIdx.x / 8;
+  const int cy = L / nbx;
+  const int p = (L % nbx) * blockDim.x + threadIdx.x;
   if (p >= N) return;
   const int x = p % g.n1, y = (p / g.n1) % g.n2, z = p / (g.n1 * g.n2);
-  // flat offsets of the 24 neighbours, -1 outside an isolated box
+  // flat indices of the 24 neighbours (+m, -m per axis); outside an isolated box: p, masked
   int off[3][2 * kHalf];
+  bool in[3][2 * kHalf];
   for (int m = 1; m <= kHalf; ++m) {
-    int q;
-    q = nb(x, m, g.n1, g.periodic);
-    off[0][2 * (m - 1)] = q < 0 ? -1 : p - x + q;
-    q = nb(x, -m, g.n1, g.periodic);
-    off[0][2 * (m - 1) + 1] = q < 0 ? -1 : p - x + q;
-    q = nb(y, m, g.n2, g.periodic);
-    off[1][2 * (m - 1)] = q < 0 ? -1 : p + (q - y) * g.n1;
-    q = nb(y, -m, g.n2, g.periodic);
-    off[1][2 * (m - 1) + 1] = q < 0 ? -1 : p + (q - y) * g.n1;
-    q = nb(z, m, g.n3, g.periodic);
-    off[2][2 * (m - 1)] = q < 0 ? -1 : p + (q - z) * g.n1 * g.n2;
-    q = nb(z, -m, g.n3, g.periodic);
-    off[2][2 * (m - 1) + 1] = q < 0 ? -1 : p + (q - z) * g.n1 * g.n2;
+    const int qs[6] = {nb(x, m, g.n1, PERIODIC), nb(x, -m, g.n1, PERIODIC), nb(y, m, g.n2, PERIODIC),
+                       nb(y, -m, g.n2, PERIODIC), nb(z, m, g.n3, PERIODIC), nb(z, -m, g.n3, PERIODIC)};
+    const int js[3] = {x, y, z};
+    const int st[3] = {1, g.n1, g.n1 * g.n2};
+    for (int mu = 0; mu < 3; ++mu)
+      for (int sgn = 0; sgn < 2; ++sgn) {
+        const int q = qs[2 * mu + sgn];
+        in[mu][2 * (m - 1) + sgn] = q >= 0;
+        off[mu][2 * (m - 1) + sgn] = q >= 0 ? p + (q - js[mu]) * st[mu] : p;
+      }
   }
   const int n_tot = g.n_orb * g.n_k;
-  const int o0 = blockIdx.y * chunk;
+  const int o0 = cy * chunk;
   const int o1 = min(n_tot, o0 + chunk);
   double acc_r = 0.0, acc_t = 0.0;
   for (int o = o0; o < o1; ++o) {
     const int k = o / g.n_orb;
     const auto* wo = w + (size_t)o * N;
+    typename Vec2<T>::type v[3][2 * kHalf];
+    for (int mu = 0; mu < 3; ++mu)
+      for (int j = 0; j < 2 * kHalf; ++j) v[mu][j] = wo[off[mu][j]];
     const auto c0 = wo[p];
     const double re = (double)c0.x, im = (double)c0.y;
     double t = 0.0;
     for (int mu = 0; mu < 3; ++mu) {
       double dr = 0.0, di = 0.0;
       for (int m = 0; m < kHalf; ++m) {
-        const int qp = off[mu][2 * m], qm = off[mu][2 * m + 1];
-        double pr = 0.0, pi = 0.0, mr = 0.0, mi = 0.0;
-        if (qp >= 0) {
-          const auto v = wo[qp];
-          pr = (double)v.x;
-          pi = (double)v.y;
-        }
-        if (qm >= 0) {
-          const auto v = wo[qm];
-          mr = (double)v.x;
-          mi = (double)v.y;
+        double pr = (double)v[mu][2 * m].x, pi = (double)v[mu][2 * m].y;
+        double mr = (double)v[mu][2 * m + 1].x, mi = (double)v[mu][2 * m + 1].y;
+        if (!PERIODIC) {
+          pr = in[mu][2 * m] ? pr : 0.0;
+          pi = in[mu][2 * m] ? pi : 0.0;
+          mr = in[mu][2 * m + 1] ? mr : 0.0;
+          mi = in[mu][2 * m + 1] ? mi : 0.0;
         }
         dr += a.d1[mu][m] * (pr - mr);
         di += a.d1[mu][m] * (pi - mi);
@@ -180,8 +186,8 @@ __global__ __launch_bounds__(256) void k_rho_tau_partial(const typename Vec2<T>:
     acc_r += 2.0 * kw[k] * (re * re + im * im);
     acc_t += kw[k] * t;
   }
-  part_rho[(size_t)blockIdx.y * N + p] = acc_r;
-  part_tau[(size_t)blockIdx.y * N + p] = acc_t;
+  part_rho[(size_t)cy * N + p] = acc_r;
+  part_tau[(size_t)cy * N + p] = acc_t;
 }
 
 template <typename T>
@@ -190,8 +196,13 @@ hipError_t launch_rho_tau_partial(const typename Vec2<T>::type* w, const double*
                                   hipStream_t s) {
   const int N = a.g.n1 * a.g.n2 * a.g.n3;
   const int nchunks = (a.g.n_orb * a.g.n_k + chunk - 1) / chunk;
-  hipLaunchKernelGGL((k_rho_tau_partial<T>), dim3((N + 255) / 256, nchunks), dim3(256), 0, s, w, kw, kappa, a,
-                     chunk, part_rho, part_tau);
+  const dim3 grid(((N + 255) / 256) * nchunks);
+  if (a.g.periodic)
+    hipLaunchKernelGGL((k_rho_tau_partial<T, true>), grid, dim3(256), 0, s, w, kw, kappa, a, chunk, part_rho,
+                       part_tau);
+  else
+    hipLaunchKernelGGL((k_rho_tau_partial<T, false>), grid, dim3(256), 0, s, w, kw, kappa, a, chunk, part_rho,
+                       part_tau);
   return hipGetLastError();
 }
 template hipError_t launch_rho_tau_partial<double>(const double2*, const double*, const double*, const MggaArgs&,
