@@ -17,9 +17,11 @@
 //   D: register r of lane l holds D[l / 16 + 4 r][l % 16], r = 0..3.
 //
 // Stage mode writes E_p u_p (m = 0) for the add-back of the next stage.
-// Moment mode loops over all atoms of an orbital group and reduces the
-// nonlocal current sum_p 2 E_p Im(conj(v_p) u_p) (v = moments 1..3) and the
-// nonlocal energy sum_p E_p |u_p|^2 per orbital.
+// Moment mode writes, per orbital and atom, the nonlocal current
+// sum_p 2 E_p Im(conj(v_p) u_p) (v = moments 1..3) and the nonlocal energy
+// sum_p E_p |u_p|^2 into a partial table [orbital][atom][4]; k_moment_reduce
+// then sums the atoms of each orbital in order. Both modes run one wavefront
+// per (orbital group, atom).
 #include "internal.h"
 
 namespace td {
@@ -34,18 +36,11 @@ __global__ __launch_bounds__(256) void k_project(ProjArgs<T> a) {
   const int n_groups = (a.n_orb_tot + 7) / 8;
   const int n_atoms = a.nl.n_atoms;
   const int item = blockIdx.x * 4 + wave;
-  const int total = a.moments ? n_groups : n_groups * n_atoms;
+  const int total = n_groups * n_atoms;
   if (item >= total) return;  // wave-uniform
-  int grp, at0, at1;
-  if (a.moments) {
-    grp = item;
-    at0 = 0;
-    at1 = n_atoms;
-  } else {
-    grp = item / n_atoms;
-    at0 = item - grp * n_atoms;
-    at1 = at0 + 1;
-  }
+  const int grp = item / n_atoms;
+  const int at0 = item - grp * n_atoms;
+  const int at1 = at0 + 1;
   const int row = lane & 15;   // A row / B and D column
   const int kk = lane >> 4;    // A column / B row / D row block
   const int o_row = grp * 8 + (row >> 1);
@@ -107,6 +102,7 @@ __global__ __launch_bounds__(256) void k_project(ProjArgs<T> a) {
     }
   }
   if (a.moments) {
+    double* part = reinterpret_cast<double*>(a.Eu);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       // sum over p: lanes 4p+m of the same row block (xor over bits 2 and 3)
@@ -116,19 +112,36 @@ __global__ __launch_bounds__(256) void k_project(ProjArgs<T> a) {
       const int o = grp * 8 + (kk >> 1) + 2 * r;
       if (p == 0 && (kk & 1) == 0 && o < a.n_orb_tot) {
         const int slot = (m == 0) ? 3 : m - 1;
-        a.jnl[(size_t)o * 4 + slot] = v;
+        part[((size_t)o * n_atoms + at0) * 4 + slot] = v;
       }
     }
   }
 }
 
+// jnl[o][slot] = sum over atoms, in order, of the moment-mode partials
+__global__ void k_moment_reduce(const double* __restrict__ part, int n_atoms, int n_orb_tot,
+                                double* __restrict__ jnl) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_orb_tot * 4) return;
+  const int o = i >> 2, slot = i & 3;
+  double s = 0.0;
+  for (int at = 0; at < n_atoms; ++at) s += part[((size_t)o * n_atoms + at) * 4 + slot];
+  jnl[i] = s;
+}
+
+// Moment mode uses Eu (free between the last stage and the next step's first
+// projection) as its [orbital][atom][4] partial table.
 template <typename T>
 hipError_t launch_project(const ProjArgs<T>& a, hipStream_t s) {
   const int n_groups = (a.n_orb_tot + 7) / 8;
-  const long total = a.moments ? n_groups : (long)n_groups * a.nl.n_atoms;
+  const long total = (long)n_groups * a.nl.n_atoms;
   if (total == 0) return hipSuccess;
   const dim3 grid((unsigned)((total + 3) / 4));
   hipLaunchKernelGGL((k_project<T>), grid, dim3(256), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !a.moments) return e;
+  hipLaunchKernelGGL(k_moment_reduce, dim3((unsigned)((4 * a.n_orb_tot + 255) / 256)), dim3(256), 0, s,
+                     reinterpret_cast<const double*>(a.Eu), a.nl.n_atoms, a.n_orb_tot, a.jnl);
   return hipGetLastError();
 }
 
