@@ -309,6 +309,9 @@ StageArgs<T> stage_args(tddft_ctx* c) {
   std::memcpy(a.lap, c->lap, sizeof(a.lap));
   std::memcpy(a.dh, c->dh, sizeof(a.dh));
   a.cdiag = c->cdiag;
+  a.coef = reinterpret_cast<const T*>(c->coef);
+  for (int mu = 0; mu < 3; ++mu)
+    for (int m = 0; m < 4; ++m) a.lapc[mu][m] = (T)c->lap[mu][m + 1];
   return a;
 }
 
@@ -360,9 +363,19 @@ tddft_status enqueue_observe(tddft_ctx* c, int bump) {
 template <typename T>
 FusedArgs<T> fused_args(tddft_ctx* c);
 
-// stencil coefficients of the fused step from the kappa just set
+// stencil coefficients of the step from the kappa just set (and, for the
+// fused step, the combined projector phases)
 tddft_status enqueue_coef(tddft_ctx* c) {
-  if (!c->fused) return TDDFT_OK;
+  if (!c->fused) {
+    if (c->mixed)
+      LAUNCH(launch_coef_table<float>(c->kappa, c->cfg.n_k, c->dh, c->cdiag, reinterpret_cast<float*>(c->coef),
+                                      c->stream),
+             "stage coefficients");
+    else
+      LAUNCH(launch_coef_table<double>(c->kappa, c->cfg.n_k, c->dh, c->cdiag, c->coef, c->stream),
+             "stage coefficients");
+    return TDDFT_OK;
+  }
   if (c->mixed)
     LAUNCH(launch_fused_coef<float>(fused_args<float>(c), c->stream), "fused coefficients");
   else
@@ -1349,7 +1362,9 @@ tddft_status tddft_ground_state(tddft_ctx* c, int32_t n_iter, double tau, double
                               c->cfg.gauge, c->cfg.dt, c->kappa, c->kappaJ, c->efield, c->phA, c->phAJ,
                               c->Alast, c->stream),
            "step_params");
-    tddft_status st = c->mixed ? ground_state_iteration<float>(c, tau) : ground_state_iteration<double>(c, tau);
+    tddft_status st = enqueue_coef(c);
+    if (st != TDDFT_OK) return st;
+    st = c->mixed ? ground_state_iteration<float>(c, tau) : ground_state_iteration<double>(c, tau);
     if (st != TDDFT_OK) return st;
     if (energies) {
       st = tddft_energy(c, &energies[it]);

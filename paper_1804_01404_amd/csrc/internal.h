@@ -68,6 +68,8 @@ struct StageArgs {
   double cdiag;            // sum_mu -1/2 c_0 / h_mu^2
   double tau;              // dt / s: u_{s-1} = w + (tau_re - i tau) h u_s
   double tau_re;           // 0 in real time; -tau_imag / s for imaginary time
+  const T* coef;           // [n_k][kCoef] kappa_mu d_m / h_mu and the diagonal, stage precision
+  T lapc[3][4];            // off-centre Laplacian weights -1/2 c_m / h_mu^2, stage precision
 };
 
 template <typename T>
@@ -145,6 +147,9 @@ template <typename T>
 hipError_t launch_fused(const FusedArgs<T>& a, hipStream_t s);
 template <typename T>
 hipError_t launch_fused_coef(const FusedArgs<T>& a, hipStream_t s);
+template <typename T>
+hipError_t launch_coef_table(const double* kappa, int n_k, const double dh[3][4], double cdiag, T* coef,
+                             hipStream_t s);
 bool fused_supported(const Geometry& g, int n_atoms, size_t elem);
 size_t fused_lds_bytes(const Geometry& g, int n_atoms, size_t elem);
 int fused_column_split(int n);

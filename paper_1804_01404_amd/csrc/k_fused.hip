@@ -478,6 +478,20 @@ hipError_t launch_fused_coef(const FusedArgs<T>& a, hipStream_t s) {
 template hipError_t launch_fused_coef<double>(const FusedArgs<double>&, hipStream_t);
 template hipError_t launch_fused_coef<float>(const FusedArgs<float>&, hipStream_t);
 
+// the per-k coefficient table alone (the per-stage kernels read it too)
+template <typename T>
+hipError_t launch_coef_table(const double* kappa, int n_k, const double dh[3][4], double cdiag, T* coef,
+                             hipStream_t s) {
+  FusedCoefIn in;
+  for (int i = 0; i < 3; ++i)
+    for (int m = 0; m < 4; ++m) in.dh[i][m] = dh[i][m];
+  in.cdiag = cdiag;
+  hipLaunchKernelGGL((k_fused_coef<T>), dim3((unsigned)((n_k + 63) / 64)), dim3(64), 0, s, kappa, n_k, in, coef);
+  return hipGetLastError();
+}
+template hipError_t launch_coef_table<double>(const double*, int, const double[3][4], double, double*, hipStream_t);
+template hipError_t launch_coef_table<float>(const double*, int, const double[3][4], double, float*, hipStream_t);
+
 size_t fused_lds_bytes(const Geometry& g, int n_atoms, size_t elem) {
   const size_t N = (size_t)g.n1 * g.n2 * g.n3;
   return ((N * elem + 15) & ~(size_t)15) + (size_t)n_atoms * kMaxProj * sizeof(double2) + 16 * 8 * sizeof(double) +

@@ -28,6 +28,14 @@ __device__ __forceinline__ T2 zero2() {
   return z;
 }
 
+// planes of u, w and V in flight ahead of the current one: two for complex
+// FP32 on tiled grids, one otherwise (measured on 20^3 and 96^3 cells; a
+// deeper queue costs complex128 more in registers than it gains)
+template <typename T, int BC>
+constexpr int stage_prefetch() {
+  return (sizeof(T) == 4 && BC != kPeriodicPlane) ? 2 : 1;
+}
+
 template <typename T, int MODE, int BC>
 __global__ __launch_bounds__(1024) void k_stage(StageArgs<T> a) {
   using T2 = typename Vec2<T>::type;
@@ -98,19 +106,21 @@ __global__ __launch_bounds__(1024) void k_stage(StageArgs<T> a) {
     return src[(size_t)z * plane + y * n1 + x];
   };
 
-  // per-step, per-k coefficients (uniform across the workgroup)
-  const double kx = a.kappa[3 * k + 0], ky = a.kappa[3 * k + 1], kz = a.kappa[3 * k + 2];
+  // per-step, per-k coefficients (uniform across the workgroup): the k-point's
+  // table row is read with scalar loads and the weights come as stage-precision
+  // kernel arguments, so none of them occupies vector registers
+  const T* __restrict__ ck = a.coef + (size_t)k * kCoef;
   T cx[4], cy[4], cz[4], bx[4], by[4], bz[4];
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
-    cx[m] = (T)a.lap[0][m + 1];
-    cy[m] = (T)a.lap[1][m + 1];
-    cz[m] = (T)a.lap[2][m + 1];
-    bx[m] = (T)(kx * a.dh[0][m]);
-    by[m] = (T)(ky * a.dh[1][m]);
-    bz[m] = (T)(kz * a.dh[2][m]);
+    cx[m] = a.lapc[0][m];
+    cy[m] = a.lapc[1][m];
+    cz[m] = a.lapc[2][m];
+    bx[m] = ck[m];
+    by[m] = ck[4 + m];
+    bz[m] = ck[8 + m];
   }
-  const double diag_d = a.cdiag + 0.5 * (kx * kx + ky * ky + kz * kz);
+  const T diag_t = ck[12];
   const T tau = (T)a.tau;
   const T tau_re = (T)a.tau_re;
   T ext = 0, ez = 0;
@@ -122,44 +132,78 @@ __global__ __launch_bounds__(1024) void k_stage(StageArgs<T> a) {
   }
   const T zc = (T)(0.5 * (n3 - 1));
 
+  // u, w and V are fetched PF planes ahead of their use, so that a plane's
+  // loads have that many barrier-separated iterations to arrive
+  constexpr int PF = stage_prefetch<T, BC>();
   T2 q[9];
 #pragma unroll
   for (int i = 0; i < 8; ++i) q[i] = load_col(i - 4);
-  T2 nxt = load_col(4);
-  // w and V of the next plane are fetched one plane ahead, like u
-  T2 w_nxt = z2;
-  T v_nxt = 0;
-  if (active) {
-    if (MODE != kFirst) w_nxt = a.w[base + col];
-    v_nxt = a.V[col];
+  T2 nxt[PF];
+#pragma unroll
+  for (int d = 0; d < PF; ++d) nxt[d] = load_col(4 + d);
+  T2 wr[PF];
+  T vr[PF];
+#pragma unroll
+  for (int d = 0; d < PF; ++d) {
+    wr[d] = z2;
+    vr[d] = 0;
+    if (active && d < n3) {
+      if (MODE != kFirst) wr[d] = a.w[base + (size_t)d * plane + col];
+      vr[d] = a.V[(size_t)d * plane + col];
+    }
   }
 
+  // tile-edge threads also stage the x/y halo of their tile (4 points out,
+  // wrapped or zero), one plane ahead like the column values
+  const bool hxm = BC != kPeriodicPlane && active && tx < 4;
+  const bool hxp = BC != kPeriodicPlane && active && tx >= TX - 4;
+  const bool hym = BC != kPeriodicPlane && active && ty < 4;
+  const bool hyp = BC != kPeriodicPlane && active && ty >= TY - 4;
+  T2 hal[4] = {z2, z2, z2, z2};
+  auto load_halo = [&](int z) {
+    if (hxm) hal[0] = load_xy(gx - 4, gy, z);
+    if (hxp) hal[1] = load_xy(gx + 4, gy, z);
+    if (hym) hal[2] = load_xy(gx, gy - 4, z);
+    if (hyp) hal[3] = load_xy(gx, gy + 4, z);
+  };
+  if (BC != kPeriodicPlane) load_halo(0);
+
   for (int z = 0; z < n3; ++z) {
-    q[8] = nxt;
-    if (z + 1 < n3) nxt = load_col(z + 5);
+    q[8] = nxt[0];
     const size_t pz = (size_t)z * plane + col;
-    T2 wv = (MODE == kFirst) ? q[4] : w_nxt;
-    const T vv = v_nxt;
-    if (active && z + 1 < n3) {
-      if (MODE != kFirst) w_nxt = a.w[base + pz + plane];
-      v_nxt = a.V[pz + plane];
+    T2 wv = (MODE == kFirst) ? q[4] : wr[0];
+    const T vv = vr[0];
+#pragma unroll
+    for (int d = 0; d + 1 < PF; ++d) {
+      nxt[d] = nxt[d + 1];
+      wr[d] = wr[d + 1];
+      vr[d] = vr[d + 1];
+    }
+    if (z + PF < n3) {
+      nxt[PF - 1] = load_col(z + 4 + PF);
+      if (active) {
+        if (MODE != kFirst) wr[PF - 1] = a.w[base + pz + (size_t)PF * plane];
+        vr[PF - 1] = a.V[pz + (size_t)PF * plane];
+      }
     }
 
     T2* buf = lds + (z & 1) * lsz;
     if (active) {
       buf[lc] = q[4];
       if (BC != kPeriodicPlane) {
-        if (tx < 4) buf[lc - 4] = load_xy(gx - 4, gy, z);
-        if (tx >= TX - 4) buf[lc + 4] = load_xy(gx + 4, gy, z);
-        if (ty < 4) buf[lc - 4 * LW] = load_xy(gx, gy - 4, z);
-        if (ty >= TY - 4) buf[lc + 4 * LW] = load_xy(gx, gy + 4, z);
+        // this plane's halo values, loaded one plane ahead
+        if (hxm) buf[lc - 4] = hal[0];
+        if (hxp) buf[lc + 4] = hal[1];
+        if (hym) buf[lc - 4 * LW] = hal[2];
+        if (hyp) buf[lc + 4 * LW] = hal[3];
+        if (z + 1 < n3) load_halo(z + 1);
       }
     }
     __syncthreads();
 
     if (active) {
       const T2 u = q[4];
-      T dg = (T)diag_d + vv;
+      T dg = diag_t + vv;
       if (a.efield) dg += ext + ez * ((T)z - zc);
       T hr = dg * u.x;
       T hi = dg * u.y;
