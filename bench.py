@@ -211,6 +211,23 @@ def bench_mgga(system, precision, lda_ms, steps=60, warmup=10):
             "fused_ms": kern["fused_ms"], "current_finite": bool(np.all(np.isfinite(J)))}
 
 
+def bench_cluster(steps=10, warmup=3, n_orb=64):
+    """The isolated-cluster shape (96^3 box, 256 atoms with s+p projectors,
+    length gauge) on the per-stage path, with n_orb of its 512 orbitals: step
+    rate and the middle Horner stage against the HBM roof."""
+    import numpy as np
+    import synth
+    s = synth.single_cell_config(2, n_orb=n_orb, nsteps=steps + warmup)
+    ms, dev_ms, kern, J = time_path(s, "mixed", steps, warmup)
+    stage_bytes = 3 * 8 * s.og
+    return {"workload": f"cluster-96^3: 256 atoms, {n_orb} of 512 orbitals, Gamma, length gauge",
+            "og_per_step": s.og, "ms_per_step": ms, "value": s.og / (ms * 1e-3), "unit": "og-steps/s",
+            "stage_ms": kern["stage_ms"], "stage_GBs": stage_bytes / (kern["stage_ms"] * 1e-3) / 1e9,
+            "stage_frac_hbm": stage_bytes / (kern["stage_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "observe_ms": kern["observe_ms"], "project_ms": kern["project_ms"],
+            "current_finite": bool(np.all(np.isfinite(J)))}
+
+
 def bench_batch(steps=30, warmup=8):
     """The uneven-batch path on 64 seeded cells (grids 12..32, up to 32
     orbitals and 8 k-points each: the 64-cell workload with the orbital and
@@ -291,6 +308,7 @@ def main():
     ap.add_argument("--no-multiscale", action="store_true", help="skip the learned multiscale line")
     ap.add_argument("--no-accuracy", action="store_true", help="skip the 1000-step accuracy report")
     ap.add_argument("--no-mgga", action="store_true", help="skip the Tran-Blaha exchange line")
+    ap.add_argument("--no-cluster", action="store_true", help="skip the 96^3 cluster line")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="also run a plain device copy of this many MB (a known-size "
                          "reference for the HBM byte counters of a profiler run)")
@@ -383,6 +401,8 @@ def main():
                        "stage_GBs": 3 * (16 if other == "c128" else 8) * og / (kern2["stage_ms"] * 1e-3) / 1e9}
     if not args.no_mgga:
         out["mgga"] = bench_mgga(s, args.precision, ms)
+    if not args.no_cluster:
+        out["cluster"] = bench_cluster()
     if not args.no_accuracy:
         out["accuracy"] = accuracy_report()
     if not args.no_batch:
