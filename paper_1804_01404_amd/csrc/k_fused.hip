@@ -27,6 +27,34 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Wavefront sums of eight values at once by recursive halving: at each of the
+// exchanges over lane bits 5, 4, 3 a lane keeps half of its values and sends
+// the other half, so 4 + 2 + 1 shuffles leave value j = (lane >> 3) & 7
+// summed over those bits; three more finish the sum over bits 2..0. Every lane
+// returns the full sum of value (lane >> 3) & 7 (11 shuffles instead of 48).
+__device__ __forceinline__ double wave_sum8(const double (&v)[8], int lane) {
+  double a[4];
+  const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const double send = b5 ? v[i] : v[i + 4], keep = b5 ? v[i + 4] : v[i];
+    a[i] = keep + __shfl_xor(send, 32, 64);
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const double send = b4 ? a[i] : a[i + 2], keep = b4 ? a[i + 2] : a[i];
+    a[i] = keep + __shfl_xor(send, 16, 64);
+  }
+  {
+    const double send = b3 ? a[0] : a[1], keep = b3 ? a[1] : a[0];
+    a[0] = keep + __shfl_xor(send, 8, 64);
+  }
+  a[0] += __shfl_xor(a[0], 4, 64);
+  a[0] += __shfl_xor(a[0], 2, 64);
+  a[0] += __shfl_xor(a[0], 1, 64);
+  return a[0];
+}
+
 // in-plane neighbour offsets of one column (periodic wrap) and its own offset
 struct Nbr {
   int xp[4], xm[4], yp[4], ym[4];
@@ -252,18 +280,13 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, const int o, u
             acc[2 * p + 1] += b * gi;
           }
         }
-#pragma unroll
-        for (int i = 0; i < 2 * kMaxProj; ++i) acc[i] = wave_sum(acc[i]);
-        if (lane < kMaxProj) {
-          double re = acc[0], im = acc[1];
-#pragma unroll
-          for (int p = 1; p < kMaxProj; ++p)
-            if (lane == p) {
-              re = acc[2 * p];
-              im = acc[2 * p + 1];
-            }
-          const double E = a.nl.atom_E[at * kMaxProj + lane] * a.dV;
-          eu[at * kMaxProj + lane] = make_double2(E * re, E * im);
+        // value 2p (real) sits in lanes 16p.., value 2p + 1 (imaginary) 8 lanes up
+        const double tot = wave_sum8(acc, lane);
+        const double im = __shfl_down(tot, 8, 64);
+        if ((lane & 15) == 0) {
+          const int p = lane >> 4;
+          const double E = a.nl.atom_E[at * kMaxProj + p] * a.dV;
+          eu[at * kMaxProj + p] = make_double2(E * tot, E * im);
         }
       }
       __syncthreads();
@@ -353,13 +376,16 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, const int o, u
     for (int at = wave; at < n_atoms; at += nwaves) {
       double jat[4] = {0, 0, 0, 0};
       const int e0 = a.nl.atom_start[at], e1 = a.nl.atom_start[at + 1];
-      double up[kMaxProj][2];
+      double up[2];
       // pass m = 0: u_p; passes m = 1..3: v_p = <x_m beta_p^kappa | w>
+      // lane 16p owns projector p: its u_p (pass 0) and its share of jat
+      const int pl = lane >> 4;
+      const double Epl = a.nl.atom_E[at * kMaxProj + pl];
 #pragma unroll 1
       for (int m = 0; m < 4; ++m) {
-        double acc[kMaxProj][2];
+        double acc[2 * kMaxProj];
 #pragma unroll
-        for (int p = 0; p < kMaxProj; ++p) acc[p][0] = acc[p][1] = 0.0;
+        for (int i = 0; i < 2 * kMaxProj; ++i) acc[i] = 0.0;
         for (int e = e0 + lane; e < e1; e += 64) {
           const T2 v = u[a.nl.ent_idx[e]];
           const double2 p1 = phk[e], p2 = a.phAJ[e];
@@ -370,22 +396,25 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, const int o, u
 #pragma unroll
           for (int p = 0; p < kMaxProj; ++p) {
             const double b = a.ent_beta[(size_t)e * kMaxProj + p];
-            acc[p][0] += b * gr;
-            acc[p][1] += b * gi;
+            acc[2 * p] += b * gr;
+            acc[2 * p + 1] += b * gi;
           }
         }
+        const double tot = wave_sum8(acc, lane);
+        const double r = tot * a.dV, i = __shfl_down(tot, 8, 64) * a.dV;
+        if (m == 0) {
+          up[0] = r;
+          up[1] = i;
+          jat[3] = Epl * (r * r + i * i);
+        } else {
+          jat[m - 1] = 2.0 * Epl * (r * up[1] - i * up[0]);
+        }
+      }
+      // sum over the projectors (lanes 0, 16, 32, 48)
 #pragma unroll
-        for (int p = 0; p < kMaxProj; ++p) {
-          const double E = a.nl.atom_E[at * kMaxProj + p];
-          const double r = wave_sum(acc[p][0]) * a.dV, i = wave_sum(acc[p][1]) * a.dV;
-          if (m == 0) {
-            up[p][0] = r;
-            up[p][1] = i;
-            jat[3] += E * (r * r + i * i);
-          } else {
-            jat[m - 1] += 2.0 * E * (r * up[p][1] - i * up[p][0]);
-          }
-        }
+      for (int i = 0; i < 4; ++i) {
+        jat[i] += __shfl_xor(jat[i], 16, 64);
+        jat[i] += __shfl_xor(jat[i], 32, 64);
       }
       if (lane == 0) {
 #pragma unroll
