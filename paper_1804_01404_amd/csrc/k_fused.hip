@@ -27,6 +27,30 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Wavefront sums of 16 values by recursive halving over lane bits 5..2 (8 +
+// 4 + 2 + 1 shuffles, then two over bits 1 and 0): every lane returns the full
+// sum of value lane >> 2.
+__device__ __forceinline__ double wave_sum16(const double (&v)[16], int lane) {
+  double a[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const bool hi = lane & 32;
+    const double send = hi ? v[i] : v[i + 8], keep = hi ? v[i + 8] : v[i];
+    a[i] = keep + __shfl_xor(send, 32, 64);
+  }
+#pragma unroll
+  for (int w = 4, bit = 16; w >= 1; w >>= 1, bit >>= 1) {
+#pragma unroll
+    for (int i = 0; i < w; ++i) {
+      const bool hi = lane & bit;
+      const double send = hi ? a[i] : a[i + w], keep = hi ? a[i + w] : a[i];
+      a[i] = keep + __shfl_xor(send, bit, 64);
+    }
+  }
+  a[0] += __shfl_xor(a[0], 2, 64);
+  return a[0] + __shfl_xor(a[0], 1, 64);
+}
+
 // Wavefront sums of eight values at once by recursive halving: at each of the
 // exchanges over lane bits 5, 4, 3 a lane keeps half of its values and sends
 // the other half, so 4 + 2 + 1 shuffles leave value j = (lane >> 3) & 7
@@ -371,54 +395,52 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, const int o, u
   __syncthreads();
 
   // ---- nonlocal current and energy at t_{n+1}: moments (1, x, y, z) of the
-  // projections with the phase of A_{n+1}; one wavefront per atom
+  // projections with the phase of A_{n+1}; one wavefront per atom, two
+  // moments per gather of the sphere values
   if (n_atoms > 0) {
     for (int at = wave; at < n_atoms; at += nwaves) {
-      double jat[4] = {0, 0, 0, 0};
       const int e0 = a.nl.atom_start[at], e1 = a.nl.atom_start[at + 1];
-      double up[2];
-      // pass m = 0: u_p; passes m = 1..3: v_p = <x_m beta_p^kappa | w>
-      // lane 16p owns projector p: its u_p (pass 0) and its share of jat
-      const int pl = lane >> 4;
-      const double Epl = a.nl.atom_E[at * kMaxProj + pl];
+      // lane 32 mm + 8 p holds the real part of the pass's moment mm of
+      // projector p and receives the imaginary part from 4 lanes up
+      const int pl = (lane >> 3) & 3, mml = lane >> 5;
+      const double E = a.nl.atom_E[at * kMaxProj + pl];
+      double ur = 0.0, ui = 0.0;
 #pragma unroll 1
-      for (int m = 0; m < 4; ++m) {
-        double acc[2 * kMaxProj];
+      for (int pass = 0; pass < 2; ++pass) {
+        // value 8 mm + 2 p + (0 real, 1 imaginary) for moments m = 2 pass + mm
+        double acc[16];
 #pragma unroll
-        for (int i = 0; i < 2 * kMaxProj; ++i) acc[i] = 0.0;
+        for (int i = 0; i < 16; ++i) acc[i] = 0.0;
         for (int e = e0 + lane; e < e1; e += 64) {
           const T2 v = u[a.nl.ent_idx[e]];
           const double2 p1 = phk[e], p2 = a.phAJ[e];
           const double pr = p1.x * p2.x - p1.y * p2.y, pim = p1.x * p2.y + p1.y * p2.x;
-          const double mom = (m == 0) ? 1.0 : a.ent_x[3 * (size_t)e + (m - 1)];
-          const double gr = mom * (pr * (double)v.x - pim * (double)v.y);
-          const double gi = mom * (pr * (double)v.y + pim * (double)v.x);
+          const double gr = pr * (double)v.x - pim * (double)v.y;
+          const double gi = pr * (double)v.y + pim * (double)v.x;
+          const double m0 = pass == 0 ? 1.0 : a.ent_x[3 * (size_t)e + 1];
+          const double m1 = a.ent_x[3 * (size_t)e + 2 * pass];
 #pragma unroll
           for (int p = 0; p < kMaxProj; ++p) {
             const double b = a.ent_beta[(size_t)e * kMaxProj + p];
-            acc[2 * p] += b * gr;
-            acc[2 * p + 1] += b * gi;
+            const double br = b * gr, bi = b * gi;
+            acc[2 * p] += m0 * br;
+            acc[2 * p + 1] += m0 * bi;
+            acc[8 + 2 * p] += m1 * br;
+            acc[8 + 2 * p + 1] += m1 * bi;
           }
         }
-        const double tot = wave_sum8(acc, lane);
-        const double r = tot * a.dV, i = __shfl_down(tot, 8, 64) * a.dV;
-        if (m == 0) {
-          up[0] = r;
-          up[1] = i;
-          jat[3] = Epl * (r * r + i * i);
-        } else {
-          jat[m - 1] = 2.0 * Epl * (r * up[1] - i * up[0]);
+        const double tot = wave_sum16(acc, lane) * a.dV;
+        const double im = __shfl_down(tot, 4, 64);
+        if (pass == 0) {
+          ur = __shfl(tot, 8 * pl, 64);
+          ui = __shfl(im, 8 * pl, 64);
         }
-      }
-      // sum over the projectors (lanes 0, 16, 32, 48)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        jat[i] += __shfl_xor(jat[i], 16, 64);
-        jat[i] += __shfl_xor(jat[i], 32, 64);
-      }
-      if (lane == 0) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) ja[at * 4 + i] = jat[i];
+        // E_p |u_p|^2 for m = 0, 2 E_p Im(conj(v_p) u_p) for m = 1..3, summed over p
+        const int m = 2 * pass + mml;
+        double c = (m == 0) ? E * (ur * ur + ui * ui) : 2.0 * E * (tot * ui - im * ur);
+        c += __shfl_xor(c, 8, 64);
+        c += __shfl_xor(c, 16, 64);
+        if ((lane & 31) == 0) ja[at * 4 + (m == 0 ? 3 : m - 1)] = c;
       }
     }
   }
