@@ -556,15 +556,18 @@ bool fused_supported(const Geometry& g, int n_atoms, size_t elem) {
   return fused_lds_bytes(g, n_atoms, elem) <= 160 * 1024;
 }
 
+// Workgroup size: the column threads, rounded up to eight wavefronts so that
+// the nonlocal phases (one wavefront per atom) run the eight atoms of a
+// diamond cell side by side; the extra wavefronts idle through the stencil.
+// Results do not depend on the count (inactive threads add exact zeros).
 template <int N, int ZS>
 constexpr int fused_threads() {
-  return ZS * (((N * N + 63) / 64) * 64);
+  return ZS * (((N * N + 63) / 64) * 64) < 512 ? 512 : ZS * (((N * N + 63) / 64) * 64);
 }
 
 template <typename T, int N, int ZS>
 static void launch_n(bool periodic, const FusedArgs<T>& a, size_t lds, hipStream_t s) {
-  constexpr int HALF = ((N * N + 63) / 64) * 64;
-  constexpr int threads = ZS * HALF;
+  constexpr int threads = fused_threads<N, ZS>();
   constexpr int bound = threads <= 512 ? 512 : 1024;
   const dim3 grid((unsigned)((size_t)a.g.n_orb * a.g.n_k));
   if (periodic)
