@@ -284,37 +284,44 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, const int o, u
   const double2* __restrict__ phkA = a.phkA + (size_t)k * S;  // exp(i kappa . x_e) of this step
   __syncthreads();
 
-#pragma unroll 1
-  for (int s = 4; s >= 1; --s) {
-    // ---- projections of u_s: one wavefront per atom, FP64
-    if (n_atoms > 0) {
-      for (int at = wave; at < n_atoms; at += nwaves) {
-        const int e0 = a.nl.atom_start[at], e1 = a.nl.atom_start[at + 1];
-        double acc[2 * kMaxProj] = {0, 0, 0, 0, 0, 0, 0, 0};
-        for (int e = e0 + lane; e < e1; e += 64) {
-          const T2 v = u[a.nl.ent_idx[e]];
-          const double2 ph = phkA[e];
-          const double pr = ph.x, pim = ph.y;
-          const double gr = pr * (double)v.x - pim * (double)v.y;
-          const double gi = pr * (double)v.y + pim * (double)v.x;
+  // ---- projections of u_s: one wavefront per atom, FP64
+  auto project = [&]() {
+    for (int at = wave; at < n_atoms; at += nwaves) {
+      const int e0 = a.nl.atom_start[at], e1 = a.nl.atom_start[at + 1];
+      double acc[2 * kMaxProj] = {0, 0, 0, 0, 0, 0, 0, 0};
+      for (int e = e0 + lane; e < e1; e += 64) {
+        const T2 v = u[a.nl.ent_idx[e]];
+        const double2 ph = phkA[e];
+        const double pr = ph.x, pim = ph.y;
+        const double gr = pr * (double)v.x - pim * (double)v.y;
+        const double gi = pr * (double)v.y + pim * (double)v.x;
 #pragma unroll
-          for (int p = 0; p < kMaxProj; ++p) {
-            const double b = a.ent_beta[(size_t)e * kMaxProj + p];
-            acc[2 * p] += b * gr;
-            acc[2 * p + 1] += b * gi;
-          }
-        }
-        // value 2p (real) sits in lanes 16p.., value 2p + 1 (imaginary) 8 lanes up
-        const double tot = wave_sum8(acc, lane);
-        const double im = __shfl_down(tot, 8, 64);
-        if ((lane & 15) == 0) {
-          const int p = lane >> 4;
-          const double E = a.nl.atom_E[at * kMaxProj + p] * a.dV;
-          eu[at * kMaxProj + p] = make_double2(E * tot, E * im);
+        for (int p = 0; p < kMaxProj; ++p) {
+          const double b = a.ent_beta[(size_t)e * kMaxProj + p];
+          acc[2 * p] += b * gr;
+          acc[2 * p + 1] += b * gi;
         }
       }
-      __syncthreads();
+      // value 2p (real) sits in lanes 16p.., value 2p + 1 (imaginary) 8 lanes up
+      const double tot = wave_sum8(acc, lane);
+      const double im = __shfl_down(tot, 8, 64);
+      if ((lane & 15) == 0) {
+        const int p = lane >> 4;
+        const double E = a.nl.atom_E[at * kMaxProj + p] * a.dV;
+        eu[at * kMaxProj + p] = make_double2(E * tot, E * im);
+      }
     }
+    __syncthreads();
+  };
+  // With disjoint spheres (one colour) every sphere point belongs to one
+  // atom, so the wavefront that adds an atom's nonlocal term of stage s to
+  // its points can go on to form that atom's projections of the completed
+  // u_{s-1} without waiting for the other atoms: one barrier fewer per stage.
+  const bool one_colour = a.n_colors == 1;
+  if (n_atoms > 0) project();
+
+#pragma unroll 1
+  for (int s = 4; s >= 1; --s) {
     // ---- local part of h u_s and the Horner update
     const T tau = (T)(a.dt / s);
     {
@@ -337,32 +344,86 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, const int o, u
     // Atoms of one colour have disjoint spheres, colours run in a fixed order.
     if (n_atoms > 0) {
       const double taud = a.dt / s;
-      for (int cl = 0; cl < a.n_colors; ++cl) {
-        for (int ii = a.color_start[cl] + wave; ii < a.color_start[cl + 1]; ii += nwaves) {
-          const int at = a.color_atoms[ii];
+      if (one_colour) {
+        for (int at = wave; at < n_atoms; at += nwaves) {
           const int e0 = a.nl.atom_start[at], e1 = a.nl.atom_start[at + 1];
-          double2 E4[kMaxProj];
+          {
+            double2 E4[kMaxProj];
 #pragma unroll
-          for (int p = 0; p < kMaxProj; ++p) E4[p] = eu[at * kMaxProj + p];
-          for (int e = e0 + lane; e < e1; e += 64) {
-            const int idx = a.nl.ent_idx[e];
-            const double2 ph = phkA[e];
-            const double pr = ph.x, pim = ph.y;
-            double sr = 0.0, si = 0.0;
+            for (int p = 0; p < kMaxProj; ++p) E4[p] = eu[at * kMaxProj + p];
+            for (int e = e0 + lane; e < e1; e += 64) {
+              const int idx = a.nl.ent_idx[e];
+              const double2 ph = phkA[e];
+              const double pr = ph.x, pim = ph.y;
+              double sr = 0.0, si = 0.0;
 #pragma unroll
-            for (int p = 0; p < kMaxProj; ++p) {
-              const double b = a.ent_beta[(size_t)e * kMaxProj + p];
-              sr += b * E4[p].x;
-              si += b * E4[p].y;
+              for (int p = 0; p < kMaxProj; ++p) {
+                const double b = a.ent_beta[(size_t)e * kMaxProj + p];
+                sr += b * E4[p].x;
+                si += b * E4[p].y;
+              }
+              const double cr = pr * sr + pim * si, ci = pr * si - pim * sr;
+              T2 v = u[idx];
+              v.x += (T)(taud * ci);
+              v.y -= (T)(taud * cr);
+              u[idx] = v;
             }
-            const double cr = pr * sr + pim * si, ci = pr * si - pim * sr;
-            T2 v = u[idx];
-            v.x += (T)(taud * ci);
-            v.y -= (T)(taud * cr);
-            u[idx] = v;
+          }
+          // the same lanes read back the same points: no barrier needed
+          if (s > 1) {
+            double acc[2 * kMaxProj] = {0, 0, 0, 0, 0, 0, 0, 0};
+            for (int e = e0 + lane; e < e1; e += 64) {
+              const T2 v = u[a.nl.ent_idx[e]];
+              const double2 ph = phkA[e];
+              const double pr = ph.x, pim = ph.y;
+              const double gr = pr * (double)v.x - pim * (double)v.y;
+              const double gi = pr * (double)v.y + pim * (double)v.x;
+#pragma unroll
+              for (int p = 0; p < kMaxProj; ++p) {
+                const double b = a.ent_beta[(size_t)e * kMaxProj + p];
+                acc[2 * p] += b * gr;
+                acc[2 * p + 1] += b * gi;
+              }
+            }
+            const double tot = wave_sum8(acc, lane);
+            const double im = __shfl_down(tot, 8, 64);
+            if ((lane & 15) == 0) {
+              const int p = lane >> 4;
+              const double E = a.nl.atom_E[at * kMaxProj + p] * a.dV;
+              eu[at * kMaxProj + p] = make_double2(E * tot, E * im);
+            }
           }
         }
         __syncthreads();
+      } else {
+        for (int cl = 0; cl < a.n_colors; ++cl) {
+          for (int ii = a.color_start[cl] + wave; ii < a.color_start[cl + 1]; ii += nwaves) {
+            const int at = a.color_atoms[ii];
+            const int e0 = a.nl.atom_start[at], e1 = a.nl.atom_start[at + 1];
+            double2 E4[kMaxProj];
+#pragma unroll
+            for (int p = 0; p < kMaxProj; ++p) E4[p] = eu[at * kMaxProj + p];
+            for (int e = e0 + lane; e < e1; e += 64) {
+              const int idx = a.nl.ent_idx[e];
+              const double2 ph = phkA[e];
+              const double pr = ph.x, pim = ph.y;
+              double sr = 0.0, si = 0.0;
+#pragma unroll
+              for (int p = 0; p < kMaxProj; ++p) {
+                const double b = a.ent_beta[(size_t)e * kMaxProj + p];
+                sr += b * E4[p].x;
+                si += b * E4[p].y;
+              }
+              const double cr = pr * sr + pim * si, ci = pr * si - pim * sr;
+              T2 v = u[idx];
+              v.x += (T)(taud * ci);
+              v.y -= (T)(taud * cr);
+              u[idx] = v;
+            }
+          }
+          __syncthreads();
+        }
+        if (s > 1) project();
       }
     }
   }
