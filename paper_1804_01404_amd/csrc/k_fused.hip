@@ -172,6 +172,10 @@ __device__ __forceinline__ void stencil_part(const typename Vec2<T>::type* u, co
 template <typename T, int N, int ZN, int Z0, bool PERIODIC>
 __device__ __forceinline__ void observe_part(const typename Vec2<T>::type* u, const double (&dh)[3][4],
                                              const Nbr& nb, const bool (&ok)[16], double (&sv)[4]) {
+  // Summed over the whole grid, Im(conj(w) D w) with the antisymmetric
+  // difference D = sum_m d_m (S_m - S_-m) equals 2 sum_m d_m Im(conj(w) S_m w)
+  // (shift r -> r - m in the backward half; zero outside an isolated box), so
+  // each point needs only its forward neighbours.
   using T2 = typename Vec2<T>::type;
   constexpr int plane = N * N;
 #pragma unroll
@@ -179,31 +183,24 @@ __device__ __forceinline__ void observe_part(const typename Vec2<T>::type* u, co
     const int z = Z0 + zz;
     const T2* pl = u + z * plane;
     const T2 cv = pl[nb.c];
-    T dxr = 0, dxi = 0, dyr = 0, dyi = 0, dzr = 0, dzi = 0;
+    const double cr = (double)cv.x, ci = (double)cv.y;
+    double px = 0, py = 0, pz = 0;
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-      const T d0 = (T)dh[0][m], d1 = (T)dh[1][m], d2 = (T)dh[2][m];
-      T2 p = lds_xy<T, PERIODIC>(pl, nb.xp[m], ok[m]);
-      T2 n = lds_xy<T, PERIODIC>(pl, nb.xm[m], ok[4 + m]);
-      dxr += d0 * (p.x - n.x);
-      dxi += d0 * (p.y - n.y);
-      p = lds_xy<T, PERIODIC>(pl, nb.yp[m], ok[8 + m]);
-      n = lds_xy<T, PERIODIC>(pl, nb.ym[m], ok[12 + m]);
-      dyr += d1 * (p.x - n.x);
-      dyi += d1 * (p.y - n.y);
-      const int zp = z + m + 1, zm = z - m - 1;
-      T2 q, r;
-      q.x = q.y = r.x = r.y = 0;
-      if (PERIODIC || zp < N) q = u[(zp % N) * plane + nb.c];
-      if (PERIODIC || zm >= 0) r = u[((zm + N) % N) * plane + nb.c];
-      dzr += d2 * (q.x - r.x);
-      dzi += d2 * (q.y - r.y);
+      const T2 p = lds_xy<T, PERIODIC>(pl, nb.xp[m], ok[m]);
+      const T2 q = lds_xy<T, PERIODIC>(pl, nb.yp[m], ok[8 + m]);
+      const int zp = z + m + 1;
+      T2 r;
+      r.x = r.y = 0;
+      if (PERIODIC || zp < N) r = u[(zp % N) * plane + nb.c];
+      px += dh[0][m] * (cr * (double)p.y - ci * (double)p.x);
+      py += dh[1][m] * (cr * (double)q.y - ci * (double)q.x);
+      pz += dh[2][m] * (cr * (double)r.y - ci * (double)r.x);
     }
-    const double cr = (double)cv.x, ci = (double)cv.y;
     sv[0] += cr * cr + ci * ci;
-    sv[1] += cr * (double)dxi - ci * (double)dxr;
-    sv[2] += cr * (double)dyi - ci * (double)dyr;
-    sv[3] += cr * (double)dzi - ci * (double)dzr;
+    sv[1] += 2.0 * px;
+    sv[2] += 2.0 * py;
+    sv[3] += 2.0 * pz;
   }
 }
 
