@@ -167,8 +167,8 @@ __device__ __forceinline__ void stencil_part(const typename Vec2<T>::type* u, co
   }
 }
 
-// norm and momentum sums of w_new for the planes Z0 .. Z0 + ZN - 1: the
-// differences in the stage precision, products and sums in FP64
+// norm and momentum sums of w_new for the planes Z0 .. Z0 + ZN - 1, products
+// and sums in FP64 from the stage-precision values
 template <typename T, int N, int ZN, int Z0, bool PERIODIC>
 __device__ __forceinline__ void observe_part(const typename Vec2<T>::type* u, const double (&dh)[3][4],
                                              const Nbr& nb, const bool (&ok)[16], double (&sv)[4]) {
