@@ -228,7 +228,8 @@ void tddft_free(tddft_ctx *ctx);
 /* ---- Batches of independent cells -------------------------------------
  * Many cells with their own grid, orbital and k-point counts, atoms and
  * field tables advance together: one hipGraph-captured batch step holds, per
- * group of cells with the same cubic grid (12, 16 or 20 points per axis), one
+ * group of cells with the same cubic grid (12, 16 or 20 points per axis, or
+ * 24 for complex FP32 orbitals: the orbital must fit in LDS), one
  * persistent launch of the fused step whose workgroups pull (cell, orbital)
  * items from a device queue, largest cells first; other cells run the
  * per-stage kernels on forked streams inside the same graph. The persistent

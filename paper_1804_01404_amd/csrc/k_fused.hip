@@ -1,6 +1,6 @@
 // Whole time step of one orbital with the orbital resident in LDS.
 //
-// For cubic cells whose orbital fits in LDS (n = 12, 16 or 20 per axis,
+// For cubic cells whose orbital fits in LDS (n = 12, 16, 20 or 24 per axis,
 // N * sizeof(complex) + tables <= 160 KB), one workgroup owns one orbital and
 // runs all four Horner stages u_{s-1} = w + (-i dt / s) h u_s, s = 4..1
 // (Program Summary: fourth-order truncated Taylor expansion; Sec. 4.1,
@@ -609,7 +609,7 @@ size_t fused_lds_bytes(const Geometry& g, int n_atoms, size_t elem) {
 
 bool fused_supported(const Geometry& g, int n_atoms, size_t elem) {
   const int n = g.n3;
-  if (n != 12 && n != 16 && n != 20) return false;
+  if (n != 12 && n != 16 && n != 20 && n != 24) return false;
   if (g.n1 != n || g.n2 != n) return false;
   return fused_lds_bytes(g, n_atoms, elem) <= 160 * 1024;
 }
@@ -623,10 +623,17 @@ constexpr int fused_threads() {
   return ZS * (((N * N + 63) / 64) * 64) < 512 ? 512 : ZS * (((N * N + 63) / 64) * 64);
 }
 
+// launch bound: 512, or the exact count above it (24^3: 576 threads, one
+// workgroup per CU by LDS, so up to 168 registers per lane)
+template <int N, int ZS>
+constexpr int fused_bound() {
+  return fused_threads<N, ZS>() <= 512 ? 512 : fused_threads<N, ZS>();
+}
+
 template <typename T, int N, int ZS>
 static void launch_n(bool periodic, const FusedArgs<T>& a, size_t lds, hipStream_t s) {
   constexpr int threads = fused_threads<N, ZS>();
-  constexpr int bound = threads <= 512 ? 512 : 1024;
+  constexpr int bound = fused_bound<N, ZS>();
   const dim3 grid((unsigned)((size_t)a.g.n_orb * a.g.n_k));
   if (periodic)
     hipLaunchKernelGGL((k_fused<T, N, ZS, true, bound>), grid, dim3(threads), lds, s, a);
@@ -643,14 +650,16 @@ hipError_t launch_fused(const FusedArgs<T>& a, hipStream_t s) {
   switch (a.g.n3) {
     case 12: launch_n<T, 12, 2>(per, a, lds, s); break;
     case 16: launch_n<T, 16, 2>(per, a, lds, s); break;
-    default: launch_n<T, 20, 1>(per, a, lds, s); break;
+    case 20: launch_n<T, 20, 1>(per, a, lds, s); break;
+    default: launch_n<T, 24, 1>(per, a, lds, s); break;
   }
   return hipGetLastError();
 }
 
 // Column split per grid size, fixed so that every path computes the same
 // bits: measured on MI355X, splitting the 12^3 and 16^3 columns between two
-// wavefronts is faster; at 20^3 the split spills registers and is slower.
+// wavefronts is faster; at 20^3 the split spills registers and is slower, and
+// at 24^3 (576 column threads) two halves would exceed 1024 threads.
 int fused_column_split(int n) { return n <= 16 ? 2 : 1; }
 
 template hipError_t launch_fused<double>(const FusedArgs<double>&, hipStream_t);
@@ -660,7 +669,7 @@ template <typename T, int N, int ZS>
 static void launch_pers_n(bool periodic, const FusedArgs<T>* cells, const int2* items, int n_items,
                           int* queue, int wgs, size_t lds, hipStream_t s) {
   constexpr int threads = fused_threads<N, ZS>();
-  constexpr int bound = threads <= 512 ? 512 : 1024;
+  constexpr int bound = fused_bound<N, ZS>();
   if (periodic)
     hipLaunchKernelGGL((k_fused_persistent<T, N, ZS, true, bound>), dim3(wgs), dim3(threads), lds, s, cells,
                        items, n_items, queue);
@@ -685,6 +694,7 @@ hipError_t launch_fused_persistent(int n, int zs, bool periodic, const FusedArgs
       case 12: launch_pers_n<T, 12, 1>(periodic, cells, items, n_items, queue, wgs, lds, s); break;
       case 16: launch_pers_n<T, 16, 1>(periodic, cells, items, n_items, queue, wgs, lds, s); break;
       case 20: launch_pers_n<T, 20, 1>(periodic, cells, items, n_items, queue, wgs, lds, s); break;
+      case 24: launch_pers_n<T, 24, 1>(periodic, cells, items, n_items, queue, wgs, lds, s); break;
       default: return hipErrorInvalidValue;
     }
   }
