@@ -28,16 +28,23 @@ namespace td {
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
 
-template <typename T>
+// SPLIT = 1: four (group, atom) items per workgroup, one per wavefront.
+// SPLIT = 4 (few items: small cells): one item per workgroup, its sphere
+// entries dealt out to the four wavefronts in turn, the four partial tiles
+// summed in wavefront order through LDS, so a wavefront's serial loop over
+// the sphere is a quarter as long.
+template <typename T, int SPLIT>
 __global__ __launch_bounds__(256) void k_project(ProjArgs<T> a) {
   using T2 = typename Vec2<T>::type;
+  __shared__ double dpart[SPLIT > 1 ? SPLIT : 1][4][64];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int n_groups = (a.n_orb_tot + 7) / 8;
   const int n_atoms = a.nl.n_atoms;
-  const int item = blockIdx.x * 4 + wave;
+  const int item = SPLIT > 1 ? (int)blockIdx.x : (int)blockIdx.x * 4 + wave;
+  const int sub = SPLIT > 1 ? wave : 0;
   const int total = n_groups * n_atoms;
-  if (item >= total) return;  // wave-uniform
+  if (item >= total) return;  // uniform over the wavefront (over the workgroup when split)
   const int grp = item / n_atoms;
   const int at0 = item - grp * n_atoms;
   const int at1 = at0 + 1;
@@ -57,7 +64,7 @@ __global__ __launch_bounds__(256) void k_project(ProjArgs<T> a) {
   for (int at = at0; at < at1; ++at) {
     const int e0 = a.nl.atom_start[at], e1 = a.nl.atom_start[at + 1];
     d4_t acc = {0.0, 0.0, 0.0, 0.0};
-    for (int eb = e0; eb < e1; eb += 4) {
+    for (int eb = e0 + 4 * sub; eb < e1; eb += 4 * SPLIT) {
       const int e = eb + kk;
       double av = 0.0, bv = 0.0;
       if (e < e1) {
@@ -74,6 +81,19 @@ __global__ __launch_bounds__(256) void k_project(ProjArgs<T> a) {
         }
       }
       acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+    }
+    if (SPLIT > 1) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) dpart[wave][r][lane] = acc[r];
+      __syncthreads();
+      if (wave != 0) return;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        double v = dpart[0][r][lane];
+#pragma unroll
+        for (int w = 1; w < SPLIT; ++w) v += dpart[w][r][lane];
+        acc[r] = v;
+      }
     }
     // acc[r] = D[kk + 4r][j]: orbital (kk >> 1) + 2r of the group, real part
     // for even kk, imaginary part for odd kk; the partner lane l ^ 16 holds
@@ -136,8 +156,11 @@ hipError_t launch_project(const ProjArgs<T>& a, hipStream_t s) {
   const int n_groups = (a.n_orb_tot + 7) / 8;
   const long total = (long)n_groups * a.nl.n_atoms;
   if (total == 0) return hipSuccess;
-  const dim3 grid((unsigned)((total + 3) / 4));
-  hipLaunchKernelGGL((k_project<T>), grid, dim3(256), 0, s, a);
+  // fewer items than four wavefronts per CU: split each item over a workgroup
+  if (total < 1024)
+    hipLaunchKernelGGL((k_project<T, 4>), dim3((unsigned)total), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_project<T, 1>), dim3((unsigned)((total + 3) / 4)), dim3(256), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !a.moments) return e;
   hipLaunchKernelGGL(k_moment_reduce, dim3((unsigned)((4 * a.n_orb_tot + 255) / 256)), dim3(256), 0, s,
