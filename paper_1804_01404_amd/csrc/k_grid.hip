@@ -284,8 +284,11 @@ hipError_t launch_fft_axis(double2* data, int M1, int M2, int M3, int axis, int 
     }
   }
   if (rem != 1) return hipErrorInvalidValue;
-  const int B = max(1, min(256, 2048 / plan.M));
   const long nlines = (long)M1 * M2 * M3 / plan.M;
+  // lines per workgroup: up to 2048 points, but small boxes are spread over at
+  // least 64 workgroups (each line is transformed the same way wherever it runs)
+  int B = max(1, min(256, 2048 / plan.M));
+  while (B > 1 && nlines / B < 64) B /= 2;
   const size_t lds = (size_t)2 * B * plan.M * sizeof(double2);
   hipLaunchKernelGGL(k_fft_axis, dim3((unsigned)((nlines + B - 1) / B)), dim3(256), lds, s, data, M1,
                      M2, M3, axis, sign, B, plan);
