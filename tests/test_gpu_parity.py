@@ -17,7 +17,7 @@ import synth
 from synth.systems import build_system, rng_for
 from oracle import tdks
 from gpu_helpers import announce, gpu_run, max_rel_series, oracle_run, rel_l2
-from oracle_helpers import tiny_periodic
+from oracle_helpers import tiny_isolated, tiny_periodic
 
 pytestmark = pytest.mark.gpu
 C = 137.035999084
@@ -300,15 +300,21 @@ def test_full_size_diamond20_k512_sampled(flags):
         assert rel_l2(g["rho"], rho_host) < (1e-13 if prec == "c128" else 1e-7)
 
 
-def test_fused_24_cubed_mixed_matches_oracle():
+@pytest.mark.parametrize("boundary", ["periodic", "isolated"])
+def test_fused_24_cubed_mixed_matches_oracle(boundary):
     """The largest LDS-resident grid (24^3, complex FP32 only: 110 KB of
     orbital, one workgroup per CU) against the oracle, with projectors,
-    Hartree + LDA and a pulse."""
+    Hartree + LDA and a pulse (velocity gauge with two k-points, or an
+    isolated box in the length gauge)."""
     from paper_1804_01404_amd.binding import TDDFT, KERNEL_FUSED
-    k = np.array([[0.0, 0.0, 0.0], [0.13, -0.07, 0.21]])
     nsteps = 8
-    A = synth.cos2_pulse_table(nsteps, 0.02, 0.05, 0.6, 0.16, 0.0, [1.0, 0.0, 0.5])
-    s = tiny_periodic(n=24, L=12.0, n_orb=4, kpts=k, nsteps=nsteps, A=A, dt=0.02, real=False, seed=7711)
+    if boundary == "periodic":
+        k = np.array([[0.0, 0.0, 0.0], [0.13, -0.07, 0.21]])
+        A = synth.cos2_pulse_table(nsteps, 0.02, 0.05, 0.6, 0.16, 0.0, [1.0, 0.0, 0.5])
+        s = tiny_periodic(n=24, L=12.0, n_orb=4, kpts=k, nsteps=nsteps, A=A, dt=0.02, real=False, seed=7711)
+    else:
+        A = synth.cos2_pulse_table(nsteps, 0.02, 0.02, 0.6, 0.16, 0.0, [0.0, 1.0, 1.0])
+        s = tiny_isolated(n=24, h=0.5, n_orb=4, nsteps=nsteps, A=A, seed=7712)
     with TDDFT(s, precision="mixed") as t:
         t.set_potential()
         assert t.time_kernel(KERNEL_FUSED, 1) > 0   # the LDS-resident step is the path taken
