@@ -263,18 +263,21 @@ template <typename T>
 tddft_status enqueue_density_potential(tddft_ctx* c) {
   const int N = (int)c->N;
   const bool mgga = is_mgga(c);
+  // with a single chunk of orbitals the partial sums are the sums: write them
+  // in place and skip the reduction (0 + x = x, the same bits)
+  const bool one = c->rho_nchunks == 1;
   if (mgga) {
     // rho and the kinetic energy density with kappa at the orbitals' time
-    LAUNCH(launch_rho_tau_partial<T>(as2<T>(c->W), c->kw_d, c->kappaJ, mgga_args(c), c->rho_chunk, c->rho_part,
-                                     c->tau_part, c->stream),
+    LAUNCH(launch_rho_tau_partial<T>(as2<T>(c->W), c->kw_d, c->kappaJ, mgga_args(c), c->rho_chunk,
+                                     one ? c->rho : c->rho_part, one ? c->tau : c->tau_part, c->stream),
            "rho_tau_partial");
-    LAUNCH(launch_rho_reduce(c->tau_part, c->rho_nchunks, N, c->tau, c->stream), "tau_reduce");
+    if (!one) LAUNCH(launch_rho_reduce(c->tau_part, c->rho_nchunks, N, c->tau, c->stream), "tau_reduce");
   } else {
     LAUNCH(launch_rho_partial<T>(as2<T>(c->W), c->kw_d, c->cfg.n_orb, c->cfg.n_k, N, c->rho_chunk,
-                                 c->rho_part, c->stream),
+                                 one ? c->rho : c->rho_part, c->stream),
            "rho_partial");
   }
-  LAUNCH(launch_rho_reduce(c->rho_part, c->rho_nchunks, N, c->rho, c->stream), "rho_reduce");
+  if (!one) LAUNCH(launch_rho_reduce(c->rho_part, c->rho_nchunks, N, c->rho, c->stream), "rho_reduce");
   if (!c->potential_set) return TDDFT_OK;
   if (c->cfg.hartree) {
     LAUNCH(launch_pack_rho(c->rho, c->g.n1, c->g.n2, c->g.n3, c->M[0], c->M[1], c->M[2], c->fft, c->stream),
