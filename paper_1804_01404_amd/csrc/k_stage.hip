@@ -294,7 +294,8 @@ template <typename T, int BC>
 __global__ __launch_bounds__(1024) void k_observe(ObserveArgs<T> a) {
   using T2 = typename Vec2<T>::type;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  double2* lds = reinterpret_cast<double2*>(smem_raw);
+  // the plane is staged in the stage precision and widened on read (exact)
+  T2* lds = reinterpret_cast<T2*>(smem_raw);
   __shared__ double red[16][6];
 
   const Geometry& g = a.g;
@@ -367,14 +368,20 @@ __global__ __launch_bounds__(1024) void k_observe(ObserveArgs<T> a) {
     if (z + 1 < n3) nxt = load_col(z + 5);
     const double vl = vl_nxt;
     if (active && z + 1 < n3) vl_nxt = a.Vloc[(size_t)(z + 1) * plane + col];
-    double2* buf = lds + (z & 1) * lsz;
+    T2* buf = lds + (z & 1) * lsz;
+    auto narrow = [](double2 v) {
+      T2 r;
+      r.x = (T)v.x;
+      r.y = (T)v.y;
+      return r;
+    };
     if (active) {
-      buf[lc] = q[4];
+      buf[lc] = narrow(q[4]);
       if (BC != kPeriodicPlane) {
-        if (tx < 4) buf[lc - 4] = load_xy(gx - 4, gy, z);
-        if (tx >= TX - 4) buf[lc + 4] = load_xy(gx + 4, gy, z);
-        if (ty < 4) buf[lc - 4 * LW] = load_xy(gx, gy - 4, z);
-        if (ty >= TY - 4) buf[lc + 4 * LW] = load_xy(gx, gy + 4, z);
+        if (tx < 4) buf[lc - 4] = narrow(load_xy(gx - 4, gy, z));
+        if (tx >= TX - 4) buf[lc + 4] = narrow(load_xy(gx + 4, gy, z));
+        if (ty < 4) buf[lc - 4 * LW] = narrow(load_xy(gx, gy - 4, z));
+        if (ty >= TY - 4) buf[lc + 4 * LW] = narrow(load_xy(gx, gy + 4, z));
       }
     }
     __syncthreads();
@@ -384,13 +391,13 @@ __global__ __launch_bounds__(1024) void k_observe(ObserveArgs<T> a) {
       double dxr = 0, dxi = 0, dyr = 0, dyi = 0, dzr = 0, dzi = 0;
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
-        double2 p = buf[oxp[m]], n = buf[oxm[m]];
+        double2 p = up(buf[oxp[m]]), n = up(buf[oxm[m]]);
         lr += a.lap[0][m + 1] * (p.x + n.x);
         li += a.lap[0][m + 1] * (p.y + n.y);
         dxr += a.dh[0][m] * (p.x - n.x);
         dxi += a.dh[0][m] * (p.y - n.y);
-        p = buf[oyp[m]];
-        n = buf[oym[m]];
+        p = up(buf[oyp[m]]);
+        n = up(buf[oym[m]]);
         lr += a.lap[1][m + 1] * (p.x + n.x);
         li += a.lap[1][m + 1] * (p.y + n.y);
         dyr += a.dh[1][m] * (p.x - n.x);
@@ -469,7 +476,7 @@ template <typename T>
 hipError_t launch_observe(int bc, const ObserveArgs<T>& a, hipStream_t s) {
   const dim3 grid((unsigned)((size_t)a.g.n_orb * a.g.n_k * a.g.tiles_x * a.g.tiles_y));
   const dim3 block(block_threads(a.g));
-  const size_t lds = lds_elems(bc, a.g) * sizeof(double2);
+  const size_t lds = lds_elems(bc, a.g) * sizeof(typename Vec2<T>::type);
   switch (bc) {
     case kPeriodicPlane:
       hipLaunchKernelGGL((k_observe<T, kPeriodicPlane>), grid, block, lds, s, a);
