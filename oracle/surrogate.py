@@ -7,7 +7,7 @@ library.
 The surrogate replaces the microscopic cell of the multiscale coupling
 (Sec. 5, Eqs. Maxwell_ms and TDKS_ms) by a map from the recent history of the
 vector potential at one macroscopic point to the current there. The paper has
-no such network; its form is this build's reading:
+no such network; the form taken here is a reading:
 
 * input x = (A(t_{n-W+1}), ..., A(t_n)) / a_scale, a causal window of W
   macroscopic samples (zeros before t = 0);
