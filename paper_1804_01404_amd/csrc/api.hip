@@ -280,11 +280,11 @@ tddft_status enqueue_density_potential(tddft_ctx* c) {
   if (!one) LAUNCH(launch_rho_reduce(c->rho_part, c->rho_nchunks, N, c->rho, c->stream), "rho_reduce");
   if (!c->potential_set) return TDDFT_OK;
   if (c->cfg.hartree) {
-    LAUNCH(launch_pack_rho(c->rho, c->g.n1, c->g.n2, c->g.n3, c->M[0], c->M[1], c->M[2], c->fft, c->stream),
-           "pack_rho");
+    // the x pass packs rho into the M-box, the z pass applies the kernel K
     for (int ax = 0; ax < 3; ++ax)
-      LAUNCH(launch_fft_axis(c->fft, c->M[0], c->M[1], c->M[2], ax, -1, c->stream), "fft fwd");
-    LAUNCH(launch_scale_real(c->fft, c->Kfft, (size_t)c->M[0] * c->M[1] * c->M[2], c->stream), "poisson");
+      LAUNCH(launch_fft_axis(c->fft, c->M[0], c->M[1], c->M[2], ax, -1, c->stream, ax == 0 ? c->rho : nullptr,
+                             c->g.n1, c->g.n2, c->g.n3, ax == 2 ? c->Kfft : nullptr),
+             "fft fwd");
     for (int ax = 0; ax < 3; ++ax)
       LAUNCH(launch_fft_axis(c->fft, c->M[0], c->M[1], c->M[2], ax, +1, c->stream), "fft inv");
   }

@@ -167,10 +167,11 @@ hipError_t launch_rho_partial(const typename Vec2<T>::type* w, const double* kw,
                               int N, int chunk, double* part, hipStream_t s);
 hipError_t launch_rho_reduce(const double* part, int nchunks, int N, double* rho, hipStream_t s);
 
-hipError_t launch_fft_axis(double2* data, int M1, int M2, int M3, int axis, int sign, hipStream_t s);
-hipError_t launch_pack_rho(const double* rho, int n1, int n2, int n3, int M1, int M2, int M3,
-                           double2* data, hipStream_t s);
-hipError_t launch_scale_real(double2* data, const double* K, size_t total, hipStream_t s);
+// rho (with n1..n3): the first pass reads the density into the M-box itself;
+// K: the pass multiplies what it stores by K (the Poisson kernel)
+hipError_t launch_fft_axis(double2* data, int M1, int M2, int M3, int axis, int sign, hipStream_t s,
+                           const double* rho = nullptr, int n1 = 0, int n2 = 0, int n3 = 0,
+                           const double* K = nullptr);
 hipError_t launch_xc_assemble(const double2* data, int n1, int n2, int n3, int M1, int M2, int M3,
                               double vh_scale, const double* rho, const double* Vloc, int hartree,
                               int xc, const double* vx_mgga, double* Vd, float* Vf, double* vh, double* exc,

@@ -211,8 +211,18 @@ __device__ void stockham_stage(const double2* in, double2* out, int B, int M, in
   }
 }
 
+// Optional ends of the Poisson solve, so that they cost no launch of their
+// own: rho (n1 x n2 x n3, zero beyond it in the M-box) is read in place of
+// data by the first (x) pass, and the stored result is multiplied by K by the
+// last forward (z) pass.
+struct FFTEnds {
+  const double* rho;
+  int n1, n2, n3;
+  const double* K;
+};
+
 __global__ __launch_bounds__(256) void k_fft_axis(double2* data, int M1, int M2, int M3, int axis,
-                                                  int sign, int B, FFTPlan plan) {
+                                                  int sign, int B, FFTPlan plan, FFTEnds ends) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double2* buf0 = reinterpret_cast<double2*>(smem_raw);
   const int M = plan.M;
@@ -240,7 +250,15 @@ __global__ __launch_bounds__(256) void k_fft_axis(double2* data, int M1, int M2,
       e = i / nl;
       line = i - e * nl;
     }
-    buf0[line * M + e] = data[line_base(L0 + line) + (long)e * stride];
+    const long gi = line_base(L0 + line) + (long)e * stride;
+    if (ends.rho) {
+      const int x = (int)(gi % M1), y = (int)((gi / M1) % M2), z = (int)(gi / ((long)M1 * M2));
+      double v = 0.0;
+      if (x < ends.n1 && y < ends.n2 && z < ends.n3) v = ends.rho[((size_t)z * ends.n2 + y) * ends.n1 + x];
+      buf0[line * M + e] = make_double2(v, 0.0);
+    } else {
+      buf0[line * M + e] = data[gi];
+    }
   }
   __syncthreads();
   double2* in = buf0;
@@ -267,11 +285,18 @@ __global__ __launch_bounds__(256) void k_fft_axis(double2* data, int M1, int M2,
       e = i / nl;
       line = i - e * nl;
     }
-    data[line_base(L0 + line) + (long)e * stride] = in[line * M + e];
+    const long gi = line_base(L0 + line) + (long)e * stride;
+    double2 v = in[line * M + e];
+    if (ends.K) {
+      const double k = ends.K[gi];
+      v = make_double2(v.x * k, v.y * k);
+    }
+    data[gi] = v;
   }
 }
 
-hipError_t launch_fft_axis(double2* data, int M1, int M2, int M3, int axis, int sign, hipStream_t s) {
+hipError_t launch_fft_axis(double2* data, int M1, int M2, int M3, int axis, int sign, hipStream_t s,
+                           const double* rho, int n1, int n2, int n3, const double* K) {
   FFTPlan plan;
   plan.M = axis == 0 ? M1 : (axis == 1 ? M2 : M3);
   plan.nf = 0;
@@ -290,43 +315,9 @@ hipError_t launch_fft_axis(double2* data, int M1, int M2, int M3, int axis, int 
   int B = max(1, min(256, 2048 / plan.M));
   while (B > 1 && nlines / B < 64) B /= 2;
   const size_t lds = (size_t)2 * B * plan.M * sizeof(double2);
+  FFTEnds ends{rho, n1, n2, n3, K};
   hipLaunchKernelGGL(k_fft_axis, dim3((unsigned)((nlines + B - 1) / B)), dim3(256), lds, s, data, M1,
-                     M2, M3, axis, sign, B, plan);
-  return hipGetLastError();
-}
-
-// rho (n1 x n2 x n3) into the corner of the M-box, zero elsewhere
-__global__ void k_pack_rho(const double* rho, int n1, int n2, int n3, int M1, int M2, int M3,
-                           double2* data) {
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long total = (long)M1 * M2 * M3;
-  if (i >= total) return;
-  const int x = (int)(i % M1);
-  const int y = (int)((i / M1) % M2);
-  const int z = (int)(i / ((long)M1 * M2));
-  double v = 0.0;
-  if (x < n1 && y < n2 && z < n3) v = rho[((size_t)z * n2 + y) * n1 + x];
-  data[i] = make_double2(v, 0.0);
-}
-
-hipError_t launch_pack_rho(const double* rho, int n1, int n2, int n3, int M1, int M2, int M3,
-                           double2* data, hipStream_t s) {
-  const long total = (long)M1 * M2 * M3;
-  hipLaunchKernelGGL(k_pack_rho, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, rho, n1, n2,
-                     n3, M1, M2, M3, data);
-  return hipGetLastError();
-}
-
-__global__ void k_scale_real(double2* data, const double* K, size_t total) {
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= total) return;
-  const double k = K[i];
-  data[i] = make_double2(data[i].x * k, data[i].y * k);
-}
-
-hipError_t launch_scale_real(double2* data, const double* K, size_t total, hipStream_t s) {
-  hipLaunchKernelGGL(k_scale_real, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, data, K,
-                     total);
+                     M2, M3, axis, sign, B, plan, ends);
   return hipGetLastError();
 }
 
