@@ -356,7 +356,7 @@ tddft_status enqueue_observe(tddft_ctx* c, int bump) {
     pa.jnl = c->jnl;
     LAUNCH(launch_project<T>(pa, c->stream), "project moments");
   }
-  LAUNCH(launch_finish(c->obs, c->g.tiles_x * c->g.tiles_y, c->jnl, nl ? 1 : 0, c->kw_d, c->kappaJ,
+  LAUNCH(launch_finish(c->obs, c->g.tiles_x * c->g.tiles_y * c->g.zslabs, c->jnl, nl ? 1 : 0, c->kw_d, c->kappaJ,
                        c->cfg.n_orb, c->cfg.n_k, c->dV, c->volume, c->counter, bump, c->Jtab, c->scalars,
                        c->nanflag, c->stream),
          "finish");
@@ -838,6 +838,12 @@ tddft_status tddft_init(const tddft_config* cfg, const double* psi0, tddft_ctx**
   }
   g.tiles_x = g.n1 / g.TX;
   g.tiles_y = g.n2 / g.TY;
+  // per-stage kernels of cells with few orbitals: split z into slabs of at
+  // least 8 planes until there are about a thousand workgroups
+  g.zslabs = 1;
+  while (g.zslabs < 8 && (long)c->n_orb_tot * g.tiles_x * g.tiles_y * g.zslabs < 1024 &&
+         g.n3 / (2 * g.zslabs) >= 8)
+    g.zslabs *= 2;
   const double h[3] = {g.h1, g.h2, g.h3};
   c->cdiag = 0;
   for (int mu = 0; mu < 3; ++mu) {
@@ -905,7 +911,7 @@ tddft_status tddft_init(const tddft_config* cfg, const double* psi0, tddft_ctx**
       (st = dalloc_t(c, 3, &c->efield)) || (st = dalloc_t(c, 3, &c->Alast)) || (st = dalloc_t(c, 6, &c->Aobs)) ||
       (st = dalloc_t(c, 1, &c->counter)) || (st = dalloc_t(c, 1, &c->nanflag)) ||
       (st = dalloc_t(c, 8, &c->scalars)) || (st = dalloc_t(c, 8, &c->sums)) ||
-      (st = dalloc_t(c, c->n_orb_tot * g.tiles_x * g.tiles_y * 8, &c->obs)) ||
+      (st = dalloc_t(c, c->n_orb_tot * g.tiles_x * g.tiles_y * g.zslabs * 8, &c->obs)) ||
       (st = dalloc_t(c, c->n_orb_tot * 4, &c->jnl)) || (st = dalloc_t(c, 1, &c->phA)) ||
       (st = dalloc_t(c, 1, &c->phAJ)) || (st = dalloc_t(c, 3, &c->ent_x)))
     return cleanup(st);
@@ -1272,7 +1278,7 @@ tddft_status tddft_norms(tddft_ctx* c, double* norms) {
   if (c->poisoned) return fail(c, TDDFT_ESTATE, "context poisoned: " + c->err);
   tddft_status st = observe_now(c);
   if (st != TDDFT_OK) return st;
-  const int tiles = c->g.tiles_x * c->g.tiles_y;
+  const int tiles = c->g.tiles_x * c->g.tiles_y * c->g.zslabs;
   std::vector<double> obs(c->n_orb_tot * tiles * 8);
   HIP_TRY(hipMemcpy(obs.data(), c->obs, obs.size() * sizeof(double), hipMemcpyDeviceToHost));
   for (size_t o = 0; o < c->n_orb_tot; ++o) {

@@ -42,8 +42,10 @@ struct Geometry {
   double h1, h2, h3;
   int periodic;
   int n_orb, n_k;         // orbitals per k-point, k-points
-  // tiling of the stage kernels
+  // tiling of the stage kernels: xy tiles, and z split into zslabs slabs when
+  // there are too few (orbital, tile) workgroups to fill the chip
   int TX, TY, tiles_x, tiles_y;
+  int zslabs;
 };
 
 template <typename T> struct Vec2;

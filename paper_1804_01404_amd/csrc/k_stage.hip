@@ -47,8 +47,15 @@ __global__ __launch_bounds__(1024) void k_stage(StageArgs<T> a) {
   const int plane = n1 * n2;
   const size_t N = (size_t)plane * n3;
   const int ntiles = g.tiles_x * g.tiles_y;
-  const int o = blockIdx.x / ntiles;
-  const int tile = blockIdx.x - o * ntiles;
+  const int nz = g.zslabs;
+  const int o = blockIdx.x / (ntiles * nz);
+  const int rem = blockIdx.x - o * ntiles * nz;
+  const int tile = rem / nz;
+  const int slab = rem - tile * nz;
+  // planes z0 .. z1 - 1 of the column (the whole column unless split)
+  const int zlen = (n3 + nz - 1) / nz;
+  const int z0 = slab * zlen;
+  const int z1 = min(n3, z0 + zlen);
   const int k = o / g.n_orb;
   const int TX = g.TX, TY = g.TY;
   const int tid = threadIdx.x;
@@ -137,19 +144,19 @@ __global__ __launch_bounds__(1024) void k_stage(StageArgs<T> a) {
   constexpr int PF = stage_prefetch<T, BC>();
   T2 q[9];
 #pragma unroll
-  for (int i = 0; i < 8; ++i) q[i] = load_col(i - 4);
+  for (int i = 0; i < 8; ++i) q[i] = load_col(z0 + i - 4);
   T2 nxt[PF];
 #pragma unroll
-  for (int d = 0; d < PF; ++d) nxt[d] = load_col(4 + d);
+  for (int d = 0; d < PF; ++d) nxt[d] = load_col(z0 + 4 + d);
   T2 wr[PF];
   T vr[PF];
 #pragma unroll
   for (int d = 0; d < PF; ++d) {
     wr[d] = z2;
     vr[d] = 0;
-    if (active && d < n3) {
-      if (MODE != kFirst) wr[d] = a.w[base + (size_t)d * plane + col];
-      vr[d] = a.V[(size_t)d * plane + col];
+    if (active && z0 + d < z1) {
+      if (MODE != kFirst) wr[d] = a.w[base + (size_t)(z0 + d) * plane + col];
+      vr[d] = a.V[(size_t)(z0 + d) * plane + col];
     }
   }
 
@@ -166,9 +173,9 @@ __global__ __launch_bounds__(1024) void k_stage(StageArgs<T> a) {
     if (hym) hal[2] = load_xy(gx, gy - 4, z);
     if (hyp) hal[3] = load_xy(gx, gy + 4, z);
   };
-  if (BC != kPeriodicPlane) load_halo(0);
+  if (BC != kPeriodicPlane) load_halo(z0);
 
-  for (int z = 0; z < n3; ++z) {
+  for (int z = z0; z < z1; ++z) {
     q[8] = nxt[0];
     const size_t pz = (size_t)z * plane + col;
     T2 wv = (MODE == kFirst) ? q[4] : wr[0];
@@ -179,7 +186,7 @@ __global__ __launch_bounds__(1024) void k_stage(StageArgs<T> a) {
       wr[d] = wr[d + 1];
       vr[d] = vr[d + 1];
     }
-    if (z + PF < n3) {
+    if (z + PF < z1) {
       nxt[PF - 1] = load_col(z + 4 + PF);
       if (active) {
         if (MODE != kFirst) wr[PF - 1] = a.w[base + pz + (size_t)PF * plane];
@@ -196,7 +203,7 @@ __global__ __launch_bounds__(1024) void k_stage(StageArgs<T> a) {
         if (hxp) buf[lc + 4] = hal[1];
         if (hym) buf[lc - 4 * LW] = hal[2];
         if (hyp) buf[lc + 4 * LW] = hal[3];
-        if (z + 1 < n3) load_halo(z + 1);
+        if (z + 1 < z1) load_halo(z + 1);
       }
     }
     __syncthreads();
@@ -303,8 +310,15 @@ __global__ __launch_bounds__(1024) void k_observe(ObserveArgs<T> a) {
   const int plane = n1 * n2;
   const size_t N = (size_t)plane * n3;
   const int ntiles = g.tiles_x * g.tiles_y;
-  const int o = blockIdx.x / ntiles;
-  const int tile = blockIdx.x - o * ntiles;
+  const int nz = g.zslabs;
+  const int o = blockIdx.x / (ntiles * nz);
+  const int rem = blockIdx.x - o * ntiles * nz;
+  const int tile = rem / nz;
+  const int slab = rem - tile * nz;
+  // planes z0 .. z1 - 1 of the column (the whole column unless split)
+  const int zlen = (n3 + nz - 1) / nz;
+  const int z0 = slab * zlen;
+  const int z1 = min(n3, z0 + zlen);
   const int TX = g.TX, TY = g.TY;
   const int tid = threadIdx.x;
   const int tx = tid % TX, ty = tid / TX;
@@ -360,14 +374,14 @@ __global__ __launch_bounds__(1024) void k_observe(ObserveArgs<T> a) {
   double s_norm = 0, s_px = 0, s_py = 0, s_pz = 0, s_kin = 0, s_v = 0;
   double2 q[9];
 #pragma unroll
-  for (int i = 0; i < 8; ++i) q[i] = load_col(i - 4);
-  double2 nxt = load_col(4);  // the column one plane ahead, and V_loc
-  double vl_nxt = active ? a.Vloc[col] : 0.0;
-  for (int z = 0; z < n3; ++z) {
+  for (int i = 0; i < 8; ++i) q[i] = load_col(z0 + i - 4);
+  double2 nxt = load_col(z0 + 4);  // the column one plane ahead, and V_loc
+  double vl_nxt = active ? a.Vloc[(size_t)z0 * plane + col] : 0.0;
+  for (int z = z0; z < z1; ++z) {
     q[8] = nxt;
-    if (z + 1 < n3) nxt = load_col(z + 5);
+    if (z + 1 < z1) nxt = load_col(z + 5);
     const double vl = vl_nxt;
-    if (active && z + 1 < n3) vl_nxt = a.Vloc[(size_t)(z + 1) * plane + col];
+    if (active && z + 1 < z1) vl_nxt = a.Vloc[(size_t)(z + 1) * plane + col];
     T2* buf = lds + (z & 1) * lsz;
     auto narrow = [](double2 v) {
       T2 r;
@@ -436,7 +450,7 @@ __global__ __launch_bounds__(1024) void k_observe(ObserveArgs<T> a) {
     const int nw = (blockDim.x + 63) / 64;
     double s = 0;
     for (int w = 0; w < nw; ++w) s += red[w][tid];
-    a.out[((size_t)o * ntiles + tile) * 8 + tid] = s;
+    a.out[(((size_t)o * ntiles + tile) * nz + slab) * 8 + tid] = s;
   }
 }
 
@@ -448,7 +462,7 @@ static size_t lds_elems(int bc, const Geometry& g) {
 template <typename T, int MODE>
 static hipError_t stage_bc(int bc, const StageArgs<T>& a, hipStream_t s) {
   using T2 = typename Vec2<T>::type;
-  const dim3 grid((unsigned)((size_t)a.g.n_orb * a.g.n_k * a.g.tiles_x * a.g.tiles_y));
+  const dim3 grid((unsigned)((size_t)a.g.n_orb * a.g.n_k * a.g.tiles_x * a.g.tiles_y * a.g.zslabs));
   const dim3 block(block_threads(a.g));
   const size_t lds = lds_elems(bc, a.g) * sizeof(T2);
   switch (bc) {
@@ -474,7 +488,7 @@ hipError_t launch_stage(int mode, int bc, const StageArgs<T>& a, hipStream_t s) 
 
 template <typename T>
 hipError_t launch_observe(int bc, const ObserveArgs<T>& a, hipStream_t s) {
-  const dim3 grid((unsigned)((size_t)a.g.n_orb * a.g.n_k * a.g.tiles_x * a.g.tiles_y));
+  const dim3 grid((unsigned)((size_t)a.g.n_orb * a.g.n_k * a.g.tiles_x * a.g.tiles_y * a.g.zslabs));
   const dim3 block(block_threads(a.g));
   const size_t lds = lds_elems(bc, a.g) * sizeof(typename Vec2<T>::type);
   switch (bc) {
