@@ -243,9 +243,11 @@ __global__ __launch_bounds__(1024) void k_stage(StageArgs<T> a) {
 // for the sphere entries of one colour (atoms whose spheres share no grid
 // point, so the entries of one launch touch distinct points); colours run in
 // a fixed order. Eu holds E_p u_p (h^3 included) from the projection of u_s.
-// One thread per (entry, k-point), looping over the k-point's orbitals.
+// One thread per (entry, k-point, block of ob orbitals), looping over the
+// block's orbitals; every (entry, orbital) pair is a distinct point of a
+// distinct orbital, so the blocks need no ordering among themselves.
 template <typename T>
-__global__ void k_nl_addback(StageArgs<T> a, const int* __restrict__ ents, int n_ents) {
+__global__ void k_nl_addback(StageArgs<T> a, const int* __restrict__ ents, int n_ents, int ob) {
   using T2 = typename Vec2<T>::type;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int k = blockIdx.y;
@@ -264,8 +266,9 @@ __global__ void k_nl_addback(StageArgs<T> a, const int* __restrict__ ents, int n
 #pragma unroll
   for (int p = 0; p < kMaxProj; ++p) b[p] = B[p * kMoments];
   const int idx = a.nl.ent_idx[e];
-  // the entry's table values serve every orbital of this k-point
-  for (int j = 0; j < n_orb; ++j) {
+  // the entry's table values serve the block's orbitals of this k-point
+  const int j0 = blockIdx.z * ob, j1 = min(n_orb, j0 + ob);
+  for (int j = j0; j < j1; ++j) {
     const size_t o = (size_t)k * n_orb + j;
     const double2* eu = a.Eu + (o * a.nl.n_atoms + at) * kMaxProj;
     double sr = 0.0, si = 0.0;
@@ -286,8 +289,14 @@ __global__ void k_nl_addback(StageArgs<T> a, const int* __restrict__ ents, int n
 template <typename T>
 hipError_t launch_nl_addback(const StageArgs<T>& a, const int* ents, int n_ents, int n_orb_tot, hipStream_t s) {
   if (n_ents <= 0) return hipSuccess;
-  const dim3 grid((unsigned)((n_ents + 255) / 256), (unsigned)(n_orb_tot / a.g.n_orb));
-  hipLaunchKernelGGL((k_nl_addback<T>), grid, dim3(256), 0, s, a, ents, n_ents);
+  const int nk = n_orb_tot / a.g.n_orb;
+  const int bx = (n_ents + 255) / 256;
+  // orbitals per thread: all of them when there are enough workgroups,
+  // fewer (down to 2) for small cells
+  int ob = a.g.n_orb;
+  while (ob > 2 && (long)bx * nk * ((a.g.n_orb + ob - 1) / ob) < 1024) ob = (ob + 1) / 2;
+  const dim3 grid((unsigned)bx, (unsigned)nk, (unsigned)((a.g.n_orb + ob - 1) / ob));
+  hipLaunchKernelGGL((k_nl_addback<T>), grid, dim3(256), 0, s, a, ents, n_ents, ob);
   return hipGetLastError();
 }
 
