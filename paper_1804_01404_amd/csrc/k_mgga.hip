@@ -190,12 +190,129 @@ __global__ __launch_bounds__(256) void k_rho_tau_partial(const typename Vec2<T>:
   part_tau[(size_t)cy * N + p] = acc_t;
 }
 
+// The same partial sums for periodic cells whose xy plane fits one workgroup:
+// a thread owns one column of a z slab (kTauSlab planes), the x/y
+// neighbours of the current plane come from LDS (double-buffered, one
+// barrier per plane) and the z neighbours from a queue in registers, so each
+// orbital value is read once from memory (plus the 8 halo planes of the
+// slab) instead of 25 times. Per point the orbitals are summed in the same
+// order as above.
+constexpr int kTauSlab = 10;
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_rho_tau_plane(const typename Vec2<T>::type* __restrict__ w,
+                                                        const double* __restrict__ kw,
+                                                        const double* __restrict__ kappa, MggaArgs a, int chunk,
+                                                        double* __restrict__ part_rho,
+                                                        double* __restrict__ part_tau) {
+  using T2 = typename Vec2<T>::type;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T2* pl = reinterpret_cast<T2*>(smem_raw);
+  const Geometry& g = a.g;
+  const int n1 = g.n1, n2 = g.n2, n3 = g.n3, plane = n1 * n2;
+  const size_t N = (size_t)plane * n3;
+  const int nsl = (n3 + kTauSlab - 1) / kTauSlab;
+  const int cy = blockIdx.x / nsl, slab = blockIdx.x - cy * nsl;
+  const int z0 = slab * kTauSlab, z1 = min(n3, z0 + kTauSlab);
+  const int tid = threadIdx.x;
+  const bool active = tid < plane;
+  const int col = active ? tid : 0;
+  const int x = col % n1, y = col / n1;
+  int ox[2 * kHalf], oy[2 * kHalf];  // +m, -m for m = 1..4, wrapped in the plane
+  for (int m = 1; m <= kHalf; ++m) {
+    ox[2 * (m - 1)] = y * n1 + (x + m) % n1;
+    ox[2 * (m - 1) + 1] = y * n1 + (x - m + n1) % n1;
+    oy[2 * (m - 1)] = ((y + m) % n2) * n1 + x;
+    oy[2 * (m - 1) + 1] = ((y - m + n2) % n2) * n1 + x;
+  }
+  double ar[kTauSlab], at[kTauSlab];
+#pragma unroll
+  for (int i = 0; i < kTauSlab; ++i) ar[i] = at[i] = 0.0;
+  const int n_tot = g.n_orb * g.n_k;
+  const int o0 = cy * chunk;
+  const int o1 = min(n_tot, o0 + chunk);
+  int step = 0;
+  for (int o = o0; o < o1; ++o) {
+    const int k = o / g.n_orb;
+    const T2* wo = w + (size_t)o * N;
+    auto ld = [&](int z) {
+      z = (z % n3 + n3) % n3;
+      return wo[(size_t)z * plane + col];
+    };
+    T2 q[9];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) q[i] = ld(z0 + i - 4);
+    T2 nxt = ld(z0 + 4);
+#pragma unroll
+    for (int zz = 0; zz < kTauSlab; ++zz) {
+      const int z = z0 + zz;
+      if (z < z1) {  // uniform over the workgroup
+        q[8] = nxt;
+        if (z + 1 < z1) nxt = ld(z + 5);
+        T2* buf = pl + (step & 1) * plane;
+        ++step;
+        if (active) buf[tid] = q[4];
+        __syncthreads();
+        if (active) {
+          const double re = (double)q[4].x, im = (double)q[4].y;
+          double t = 0.0;
+#pragma unroll
+          for (int mu = 0; mu < 3; ++mu) {
+            double dr = 0.0, di = 0.0;
+#pragma unroll
+            for (int m = 0; m < kHalf; ++m) {
+              T2 pv, mv;
+              if (mu == 0) {
+                pv = buf[ox[2 * m]];
+                mv = buf[ox[2 * m + 1]];
+              } else if (mu == 1) {
+                pv = buf[oy[2 * m]];
+                mv = buf[oy[2 * m + 1]];
+              } else {
+                pv = q[5 + m];
+                mv = q[3 - m];
+              }
+              dr += a.d1[mu][m] * ((double)pv.x - (double)mv.x);
+              di += a.d1[mu][m] * ((double)pv.y - (double)mv.y);
+            }
+            const double km = kappa[3 * k + mu];
+            const double gr = dr - km * im, gi = di + km * re;
+            t += gr * gr + gi * gi;
+          }
+          ar[zz] += 2.0 * kw[k] * (re * re + im * im);
+          at[zz] += kw[k] * t;
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) q[i] = q[i + 1];
+      }
+    }
+  }
+  if (active) {
+#pragma unroll
+    for (int zz = 0; zz < kTauSlab; ++zz) {
+      const int z = z0 + zz;
+      if (z < z1) {
+        part_rho[(size_t)cy * N + (size_t)z * plane + tid] = ar[zz];
+        part_tau[(size_t)cy * N + (size_t)z * plane + tid] = at[zz];
+      }
+    }
+  }
+}
+
 template <typename T>
 hipError_t launch_rho_tau_partial(const typename Vec2<T>::type* w, const double* kw, const double* kappa,
                                   const MggaArgs& a, int chunk, double* part_rho, double* part_tau,
                                   hipStream_t s) {
   const int N = a.g.n1 * a.g.n2 * a.g.n3;
   const int nchunks = (a.g.n_orb * a.g.n_k + chunk - 1) / chunk;
+  const int plane = a.g.n1 * a.g.n2;
+  if (a.g.periodic && plane <= 1024) {
+    const int nsl = (a.g.n3 + kTauSlab - 1) / kTauSlab;
+    const size_t lds = (size_t)2 * plane * sizeof(typename Vec2<T>::type);
+    hipLaunchKernelGGL((k_rho_tau_plane<T>), dim3((unsigned)(nchunks * nsl)), dim3(((plane + 63) / 64) * 64), lds,
+                       s, w, kw, kappa, a, chunk, part_rho, part_tau);
+    return hipGetLastError();
+  }
   const dim3 grid(((N + 255) / 256) * nchunks);
   if (a.g.periodic)
     hipLaunchKernelGGL((k_rho_tau_partial<T, true>), grid, dim3(256), 0, s, w, kw, kappa, a, chunk, part_rho,
