@@ -359,32 +359,55 @@ __global__ __launch_bounds__(1024) void k_observe(ObserveArgs<T> a) {
   const int col = gy * n1 + gx;
   const T2* __restrict__ src = a.w + base;
   const bool periodic = (BC != kIsolatedTile);
-  auto up = [](T2 v) { return make_double2((double)v.x, (double)v.y); };
-  auto load_col = [&](int z) -> double2 {
-    if (!active) return make_double2(0.0, 0.0);
-    if (!periodic && (z < 0 || z >= n3)) return make_double2(0.0, 0.0);
+  // differences and weighted sums in the stage precision, products and the
+  // running sums in FP64 (the same arithmetic as before for complex128)
+  const T2 zt = zero2<T2>();
+  auto load_col = [&](int z) -> T2 {
+    if (!active) return zt;
+    if (!periodic && (z < 0 || z >= n3)) return zt;
     int zz = z;
     if (periodic) {
       zz = z % n3;
       if (zz < 0) zz += n3;
     }
-    return up(src[(size_t)zz * plane + col]);
+    return src[(size_t)zz * plane + col];
   };
-  auto load_xy = [&](int x, int y, int z) -> double2 {
+  auto load_xy = [&](int x, int y, int z) -> T2 {
     if (periodic) {
       x = (x % n1 + n1) % n1;
       y = (y % n2 + n2) % n2;
     } else if (x < 0 || x >= n1 || y < 0 || y >= n2) {
-      return make_double2(0.0, 0.0);
+      return zt;
     }
-    return up(src[(size_t)z * plane + y * n1 + x]);
+    return src[(size_t)z * plane + y * n1 + x];
   };
+  // weights: the FP64 kernel arguments themselves for complex128, a copy in
+  // FP32 registers for complex FP32
+  T cl[3][4], cd[3][4];
+  if constexpr (sizeof(T) == 4) {
+#pragma unroll
+    for (int mu = 0; mu < 3; ++mu)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        cl[mu][m] = (T)a.lap[mu][m + 1];
+        cd[mu][m] = (T)a.dh[mu][m];
+      }
+  }
+  auto CL = [&](int mu, int m) -> T {
+    if constexpr (sizeof(T) == 8) return a.lap[mu][m + 1];
+    else return cl[mu][m];
+  };
+  auto CD = [&](int mu, int m) -> T {
+    if constexpr (sizeof(T) == 8) return a.dh[mu][m];
+    else return cd[mu][m];
+  };
+  const T cdiag = (T)a.cdiag;
 
   double s_norm = 0, s_px = 0, s_py = 0, s_pz = 0, s_kin = 0, s_v = 0;
-  double2 q[9];
+  T2 q[9];
 #pragma unroll
   for (int i = 0; i < 8; ++i) q[i] = load_col(z0 + i - 4);
-  double2 nxt = load_col(z0 + 4);  // the column one plane ahead, and V_loc
+  T2 nxt = load_col(z0 + 4);  // the column one plane ahead, and V_loc
   double vl_nxt = active ? a.Vloc[(size_t)z0 * plane + col] : 0.0;
   for (int z = z0; z < z1; ++z) {
     q[8] = nxt;
@@ -392,52 +415,47 @@ __global__ __launch_bounds__(1024) void k_observe(ObserveArgs<T> a) {
     const double vl = vl_nxt;
     if (active && z + 1 < z1) vl_nxt = a.Vloc[(size_t)(z + 1) * plane + col];
     T2* buf = lds + (z & 1) * lsz;
-    auto narrow = [](double2 v) {
-      T2 r;
-      r.x = (T)v.x;
-      r.y = (T)v.y;
-      return r;
-    };
     if (active) {
-      buf[lc] = narrow(q[4]);
+      buf[lc] = q[4];
       if (BC != kPeriodicPlane) {
-        if (tx < 4) buf[lc - 4] = narrow(load_xy(gx - 4, gy, z));
-        if (tx >= TX - 4) buf[lc + 4] = narrow(load_xy(gx + 4, gy, z));
-        if (ty < 4) buf[lc - 4 * LW] = narrow(load_xy(gx, gy - 4, z));
-        if (ty >= TY - 4) buf[lc + 4 * LW] = narrow(load_xy(gx, gy + 4, z));
+        if (tx < 4) buf[lc - 4] = load_xy(gx - 4, gy, z);
+        if (tx >= TX - 4) buf[lc + 4] = load_xy(gx + 4, gy, z);
+        if (ty < 4) buf[lc - 4 * LW] = load_xy(gx, gy - 4, z);
+        if (ty >= TY - 4) buf[lc + 4 * LW] = load_xy(gx, gy + 4, z);
       }
     }
     __syncthreads();
     if (active) {
-      const double2 u = q[4];
-      double lr = a.cdiag * u.x, li = a.cdiag * u.y;
-      double dxr = 0, dxi = 0, dyr = 0, dyi = 0, dzr = 0, dzi = 0;
+      const T2 u = q[4];
+      T lr = cdiag * u.x, li = cdiag * u.y;
+      T dxr = 0, dxi = 0, dyr = 0, dyi = 0, dzr = 0, dzi = 0;
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
-        double2 p = up(buf[oxp[m]]), n = up(buf[oxm[m]]);
-        lr += a.lap[0][m + 1] * (p.x + n.x);
-        li += a.lap[0][m + 1] * (p.y + n.y);
-        dxr += a.dh[0][m] * (p.x - n.x);
-        dxi += a.dh[0][m] * (p.y - n.y);
-        p = up(buf[oyp[m]]);
-        n = up(buf[oym[m]]);
-        lr += a.lap[1][m + 1] * (p.x + n.x);
-        li += a.lap[1][m + 1] * (p.y + n.y);
-        dyr += a.dh[1][m] * (p.x - n.x);
-        dyi += a.dh[1][m] * (p.y - n.y);
+        T2 p = buf[oxp[m]], n = buf[oxm[m]];
+        lr += CL(0, m) * (p.x + n.x);
+        li += CL(0, m) * (p.y + n.y);
+        dxr += CD(0, m) * (p.x - n.x);
+        dxi += CD(0, m) * (p.y - n.y);
+        p = buf[oyp[m]];
+        n = buf[oym[m]];
+        lr += CL(1, m) * (p.x + n.x);
+        li += CL(1, m) * (p.y + n.y);
+        dyr += CD(1, m) * (p.x - n.x);
+        dyi += CD(1, m) * (p.y - n.y);
         p = q[5 + m];
         n = q[3 - m];
-        lr += a.lap[2][m + 1] * (p.x + n.x);
-        li += a.lap[2][m + 1] * (p.y + n.y);
-        dzr += a.dh[2][m] * (p.x - n.x);
-        dzi += a.dh[2][m] * (p.y - n.y);
+        lr += CL(2, m) * (p.x + n.x);
+        li += CL(2, m) * (p.y + n.y);
+        dzr += CD(2, m) * (p.x - n.x);
+        dzi += CD(2, m) * (p.y - n.y);
       }
-      const double nn = u.x * u.x + u.y * u.y;
+      const double ux = (double)u.x, uy = (double)u.y;
+      const double nn = ux * ux + uy * uy;
       s_norm += nn;
-      s_px += u.x * dxi - u.y * dxr;
-      s_py += u.x * dyi - u.y * dyr;
-      s_pz += u.x * dzi - u.y * dzr;
-      s_kin += u.x * lr + u.y * li;
+      s_px += ux * (double)dxi - uy * (double)dxr;
+      s_py += ux * (double)dyi - uy * (double)dyr;
+      s_pz += ux * (double)dzi - uy * (double)dzr;
+      s_kin += ux * (double)lr + uy * (double)li;
       s_v += vl * nn;
     }
 #pragma unroll
