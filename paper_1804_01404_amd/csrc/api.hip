@@ -895,7 +895,7 @@ tddft_status tddft_init(const tddft_config* cfg, const double* psi0, tddft_ctx**
       (st = dalloc_t(c, N, &c->vh)) || (st = dalloc_t(c, N, &c->exc)) || (st = dalloc_t(c, N, &c->rho)) ||
       (st = dalloc_t(c, N, &c->rho0)))
     return cleanup(st);
-  c->rho_chunk = 64;
+  c->rho_chunk = is_mgga(c) ? rho_tau_chunk(c->g, (int)c->n_orb_tot) : 64;
   c->rho_nchunks = (int)((c->n_orb_tot + c->rho_chunk - 1) / c->rho_chunk);
   if ((st = dalloc_t(c, (size_t)c->rho_nchunks * N, &c->rho_part))) return cleanup(st);
   if (is_mgga(c) && ((st = dalloc_t(c, (size_t)c->rho_nchunks * N, &c->tau_part)) || (st = dalloc_t(c, N, &c->tau)) ||

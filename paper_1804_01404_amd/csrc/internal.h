@@ -182,6 +182,7 @@ template <typename T>
 hipError_t launch_rho_tau_partial(const typename Vec2<T>::type* w, const double* kw, const double* kappa,
                                   const MggaArgs& a, int chunk, double* part_rho, double* part_tau,
                                   hipStream_t s);
+int rho_tau_chunk(const Geometry& g, int n_tot);
 hipError_t launch_mgga_potential(const double* rho, const double* tau, const MggaArgs& a, int tb09, double dV,
                                  double volume, double* gpart, double* cval, double* vx, hipStream_t s);
 

@@ -96,16 +96,33 @@ template hipError_t launch_rho_partial<double>(const double2*, const double*, in
 template hipError_t launch_rho_partial<float>(const float2*, const double*, int, int, int, int,
                                               double*, hipStream_t);
 
-__global__ void k_rho_reduce(const double* part, int nchunks, int N, double* rho) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= N) return;
+// rho[p] = sum over chunks of part[c][p]. A workgroup takes 64 points and
+// kRedSlices slices: slice j sums chunks j, j + kRedSlices, ... in order, then
+// the slices combine by a fixed pairwise tree in LDS, so the result does not
+// depend on scheduling. One thread per point looping over every chunk would
+// leave the chip nearly idle (8000 points are 32 workgroups) behind a chain
+// of dependent loads.
+constexpr int kRedSlices = 16;
+
+__global__ __launch_bounds__(64 * kRedSlices) void k_rho_reduce(const double* __restrict__ part, int nchunks,
+                                                                int N, double* __restrict__ rho) {
+  __shared__ double red[kRedSlices][64];
+  const int i = threadIdx.x & 63, j = threadIdx.x >> 6;
+  const int p = blockIdx.x * 64 + i;
   double acc = 0.0;
-  for (int c = 0; c < nchunks; ++c) acc += part[(size_t)c * N + p];
-  rho[p] = acc;
+  if (p < N)
+    for (int c = j; c < nchunks; c += kRedSlices) acc += part[(size_t)c * N + p];
+  red[j][i] = acc;
+  __syncthreads();
+  for (int h = kRedSlices / 2; h > 0; h >>= 1) {
+    if (j < h) red[j][i] += red[j + h][i];
+    __syncthreads();
+  }
+  if (j == 0 && p < N) rho[p] = red[0][i];
 }
 
 hipError_t launch_rho_reduce(const double* part, int nchunks, int N, double* rho, hipStream_t s) {
-  hipLaunchKernelGGL(k_rho_reduce, dim3((N + 255) / 256), dim3(256), 0, s, part, nchunks, N, rho);
+  hipLaunchKernelGGL(k_rho_reduce, dim3((N + 63) / 64), dim3(64 * kRedSlices), 0, s, part, nchunks, N, rho);
   return hipGetLastError();
 }
 

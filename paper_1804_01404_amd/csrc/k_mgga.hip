@@ -258,7 +258,10 @@ __global__ __launch_bounds__(1024) void k_rho_tau_plane(const typename Vec2<T>::
           double t = 0.0;
 #pragma unroll
           for (int mu = 0; mu < 3; ++mu) {
-            double dr = 0.0, di = 0.0;
+            // the differences and their weighted sum in the orbitals' own
+            // precision (for complex FP32 an error at the orbitals' own
+            // rounding level), the kappa term and the square in FP64
+            T dr = 0, di = 0;
 #pragma unroll
             for (int m = 0; m < kHalf; ++m) {
               T2 pv, mv;
@@ -272,8 +275,9 @@ __global__ __launch_bounds__(1024) void k_rho_tau_plane(const typename Vec2<T>::
                 pv = q[5 + m];
                 mv = q[3 - m];
               }
-              dr += a.d1[mu][m] * ((double)pv.x - (double)mv.x);
-              di += a.d1[mu][m] * ((double)pv.y - (double)mv.y);
+              const T cm = (T)a.d1[mu][m];
+              dr += cm * (pv.x - mv.x);
+              di += cm * (pv.y - mv.y);
             }
             const double km = kappa[3 * k + mu];
             const double gr = dr - km * im, gi = di + km * re;
@@ -297,6 +301,19 @@ __global__ __launch_bounds__(1024) void k_rho_tau_plane(const typename Vec2<T>::
       }
     }
   }
+}
+
+// Orbitals per chunk of the partial sums. The plane sweep runs one workgroup
+// per (chunk, z slab), each walking its chunk's orbitals in order, so with 64
+// orbitals a chunk a 20^3 cell of 8192 orbitals fills only one workgroup per
+// compute unit; smaller chunks (down to 8) give at least about 1024
+// workgroups at the price of more partial planes to reduce.
+int rho_tau_chunk(const Geometry& g, int n_tot) {
+  const int plane = g.n1 * g.n2;
+  if (!(g.periodic && plane <= 1024)) return 64;
+  const int nsl = (g.n3 + kTauSlab - 1) / kTauSlab;
+  const long want = (long)n_tot * nsl / 1024;
+  return (int)std::max(8L, std::min(64L, want));
 }
 
 template <typename T>
