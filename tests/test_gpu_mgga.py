@@ -10,6 +10,8 @@ FP64 oracle, through the C ABI.
 * BJ on an isolated box in the length gauge (zero halo in grad rho, lap rho
   and tau);
 * the predictor-corrector step and the imaginary-time ground state with TB09;
+* 20 orbital k-points, so that the density and tau partial sums run in
+  three chunks (the last ragged) and are reduced;
 * a batch of TB09 cells equals their solo runs bit for bit.
 """
 import numpy as np
@@ -67,6 +69,30 @@ def test_periodic_pulse_matches_oracle(xc, flags):
     assert rel_l2(g["rho"], o["rho"]) < 1e-10
     assert np.max(np.abs(g["psi"] - o["psi"])) < 1e-10
     assert max_rel_series(g["J"], o["J"]) < 1e-8
+
+
+@pytest.mark.parametrize("flags", PATHS)
+@pytest.mark.parametrize("prec", ["c128", "mixed"])
+def test_tb09_several_density_chunks(prec, flags):
+    """20 orbital k-points: the density and tau partial sums run in three
+    chunks of 8 (the last one ragged) and are reduced, instead of being
+    written in place."""
+    k = np.array([[0.0, 0.0, 0.0], [0.17, -0.11, 0.23], [-0.2, 0.1, 0.05], [0.3, 0.3, -0.1], [0.0, -0.25, 0.15]])
+    nsteps = 5
+    A = synth.cos2_pulse_table(nsteps, 0.02, 0.05, 0.6, 0.1, 0.0, [0.5, 1.0, 0.0])
+    s = tiny_periodic(n=12, L=6.0, n_orb=4, kpts=k, nsteps=nsteps, A=A, dt=0.02, real=False, seed=7705)
+    s.xc = "tb09"
+    g = _gpu(s, prec, flags)
+    o = _oracle(s)
+    if prec == "c128":
+        assert abs(g["c1"] - o["c1"]) < 1e-12
+        assert rel_l2(g["rho"], o["rho"]) < 1e-10
+        assert np.max(np.abs(g["psi"] - o["psi"])) < 1e-10
+        assert max_rel_series(g["J"], o["J"]) < 1e-8
+    else:
+        assert abs(g["c1"] - o["c1"]) < 1e-6
+        assert rel_l2(g["rho"], o["rho"]) < 2e-6 * np.sqrt(nsteps)
+        assert max_rel_series(g["J"], o["J"]) < 1e-4
 
 
 def test_mixed_path_tb09():
