@@ -29,10 +29,10 @@ namespace td {
 typedef double d4_t __attribute__((ext_vector_type(4)));
 
 // SPLIT = 1: four (group, atom) items per workgroup, one per wavefront.
-// SPLIT = 4 (few items: small cells): one item per workgroup, its sphere
-// entries dealt out to the four wavefronts in turn, the four partial tiles
-// summed in wavefront order through LDS, so a wavefront's serial loop over
-// the sphere is a quarter as long.
+// SPLIT = 4 (few items: small cells, or few orbitals over many atoms): one
+// item per workgroup, its sphere entries dealt out to the four wavefronts in
+// turn, the four partial tiles summed in wavefront order through LDS, so a
+// wavefront's serial loop over the sphere is a quarter as long.
 template <typename T, int SPLIT>
 __global__ __launch_bounds__(256) void k_project(ProjArgs<T> a) {
   using T2 = typename Vec2<T>::type;
@@ -156,8 +156,11 @@ hipError_t launch_project(const ProjArgs<T>& a, hipStream_t s) {
   const int n_groups = (a.n_orb_tot + 7) / 8;
   const long total = (long)n_groups * a.nl.n_atoms;
   if (total == 0) return hipSuccess;
-  // fewer items than four wavefronts per CU: split each item over a workgroup
-  if (total < 1024)
+  // up to 16 items per CU (the 96^3 cluster: 8 orbital groups x 256 atoms):
+  // split each item over a workgroup, so that there are enough wavefronts to
+  // hide the latency of the sphere gathers and each serial chain is a quarter
+  // as long (0.075 -> 0.048 ms per projection on that shape)
+  if (total < 4096)
     hipLaunchKernelGGL((k_project<T, 4>), dim3((unsigned)total), dim3(256), 0, s, a);
   else
     hipLaunchKernelGGL((k_project<T, 1>), dim3((unsigned)((total + 3) / 4)), dim3(256), 0, s, a);
