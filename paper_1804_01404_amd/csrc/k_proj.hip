@@ -156,11 +156,12 @@ hipError_t launch_project(const ProjArgs<T>& a, hipStream_t s) {
   const int n_groups = (a.n_orb_tot + 7) / 8;
   const long total = (long)n_groups * a.nl.n_atoms;
   if (total == 0) return hipSuccess;
-  // up to 16 items per CU (the 96^3 cluster: 8 orbital groups x 256 atoms):
-  // split each item over a workgroup, so that there are enough wavefronts to
-  // hide the latency of the sphere gathers and each serial chain is a quarter
-  // as long (0.075 -> 0.048 ms per projection on that shape)
-  if (total < 4096)
+  // up to 64 items per CU: split each item over a workgroup, so that there
+  // are enough wavefronts to hide the latency of the sphere gathers and each
+  // serial chain is a quarter as long (the 96^3 cluster, 8 orbital groups x
+  // 256 atoms: 0.075 -> 0.048 ms per projection; the 20^3 cell with 512
+  // k-points on the per-stage path, 1024 groups x 8 atoms: 0.172 -> 0.140 ms)
+  if (total < 16384)
     hipLaunchKernelGGL((k_project<T, 4>), dim3((unsigned)total), dim3(256), 0, s, a);
   else
     hipLaunchKernelGGL((k_project<T, 1>), dim3((unsigned)((total + 3) / 4)), dim3(256), 0, s, a);
