@@ -11,7 +11,9 @@ FP64 oracle, through the C ABI.
   and tau);
 * the predictor-corrector step and the imaginary-time ground state with TB09;
 * 20 orbital k-points, so that the density and tau partial sums run in
-  three chunks (the last ragged) and are reduced;
+  three chunks (the last ragged) and are reduced; the full 20^3 x 512-k cell
+  (512 chunks): density against the downloaded orbitals, c against the
+  oracle's c of that density;
 * a batch of TB09 cells equals their solo runs bit for bit.
 """
 import numpy as np
@@ -93,6 +95,23 @@ def test_tb09_several_density_chunks(prec, flags):
         assert abs(g["c1"] - o["c1"]) < 1e-6
         assert rel_l2(g["rho"], o["rho"]) < 2e-6 * np.sqrt(nsteps)
         assert max_rel_series(g["J"], o["J"]) < 1e-4
+
+
+@pytest.mark.parametrize("flags", PATHS)
+def test_full_size_tb09_density_and_c(flags):
+    """The 20^3 cell with 512 k-points and TB09, one step: the density, summed
+    over 512 chunks of 16 orbitals beside the kinetic energy density and then
+    reduced, equals the density of the downloaded orbitals, and c equals the
+    oracle's c of that density."""
+    from oracle import mgga
+    s = synth.single_cell_config(1, nsteps=1)
+    s.xc = "tb09"
+    grid = tdks.Grid(s.n, s.cell, s.boundary)
+    for prec in ("c128", "mixed"):
+        g = _gpu(s, prec, flags)
+        rho_host = tdks.density(g["psi"], s.kw, grid)
+        assert rel_l2(g["rho"], rho_host) < (1e-13 if prec == "c128" else 1e-7)
+        assert abs(g["c1"] - mgga.tb09_c(rho_host, grid)) < (1e-10 if prec == "c128" else 1e-7)
 
 
 def test_mixed_path_tb09():
