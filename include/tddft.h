@@ -126,28 +126,46 @@ typedef struct {
 uint32_t tddft_abi_version(void);
 
 /* Create a context: validate cfg, allocate device state, upload psi0
- * ([n_k][n_orb][n3][n2][n1] complex128), form rho(0). Errors: EINVAL
- * (bad cfg, NULL psi0/out), ENOMEM, EDEVICE. On failure *out is NULL. */
+ * ([n_k][n_orb][n3][n2][n1] complex128), form rho(0) by Eq. rho (Sec. 3.1:
+ * rho = sum_k w_k sum_n 2 |w_nk|^2). The grid and boundary follow Sec. 2.1
+ * (uniform Cartesian grid; periodic cell or isolated box with vacuum beyond
+ * the faces), the k-points Sec. 4.1. Errors: EINVAL (bad cfg, NULL psi0/out),
+ * ENOMEM (an allocation, including one by dev_alloc, returned NULL),
+ * EDEVICE. On failure *out is NULL and nothing stays allocated. */
 tddft_status tddft_init(const tddft_config *cfg, const double *psi0, tddft_ctx **out);
 
-/* Install the ionic potential: v_loc [n3][n2][n1] (Ha) and n_atoms atom
- * projector tables (n_atoms may be 0, atoms then NULL). Recomputes the
- * Hartree and xc potentials from the current density and checks the
- * Taylor stability bound |lambda| dt <= 2 sqrt 2 (EUNSTABLE unless
- * TDDFT_FLAG_ALLOW_UNSTABLE). May be called again to replace the tables. */
+/* Install the ionic potential (Sec. 3.1: local part plus the separable
+ * Kleinman-Bylander nonlocal part; Sec. 4.1 for its phase exp(-i kappa.x)):
+ * v_loc [n3][n2][n1] (Ha) and n_atoms atom projector tables (n_atoms may be
+ * 0, atoms then NULL; the tables are copied). Recomputes the Hartree
+ * potential (Poisson equation of Sec. 3.1, by FFT: 4 pi / G^2 for periodic
+ * cells, the free-space kernel on a doubled box for isolated ones) and the
+ * xc potential from the current density, and checks the Taylor stability
+ * bound |lambda| dt <= 2 sqrt 2 (EUNSTABLE unless TDDFT_FLAG_ALLOW_UNSTABLE).
+ * Errors: EINVAL (NULL v_loc, non-finite values, an index out of the grid
+ * or repeated within an atom), ENOMEM, EDEVICE, EUNSTABLE. May be called
+ * again to replace the tables. */
 tddft_status tddft_set_potential(tddft_ctx *ctx, const double *v_loc, int32_t n_atoms,
                                  const tddft_atom *atoms);
 
-/* Advance nsteps steps of dt. A is the host table [nsteps + 1][3] of the
- * vector potential at t_n = n dt (velocity gauge: kappa = k + A/c at the step
- * midpoint; length gauge: E_n = -(A_{n+1} - A_n) / (c dt) enters as E.r).
- * The potential is frozen at rho(t_n) during a step. If J_out is not NULL it
- * receives [nsteps][3]: the current I(t_{n+1}) after each step. Errors:
- * ESTATE (no set_potential yet), EINVAL, EDEVICE, ENUMERIC. */
+/* Advance nsteps steps of dt (Program Summary: the fourth-order truncated
+ * Taylor expansion of exp(-i dt h); Sec. 4.1, Eq. TDKS_solid for h with the
+ * vector potential, Eq. TDKS for the isolated form). A is the host table
+ * [nsteps + 1][3] of the vector potential at t_n = n dt (velocity gauge:
+ * kappa = k + A/c at the step midpoint; length gauge: E_n = -(A_{n+1} - A_n)
+ * / (c dt) enters as E.r). The potential is frozen at rho(t_n) during a step;
+ * after it the density (Eq. rho), Hartree and xc potentials are rebuilt. If
+ * J_out is not NULL it receives [nsteps][3]: the current I(t_{n+1}) of
+ * Eq. macro_current (nonlocal part included) after each step. Errors:
+ * ESTATE (no set_potential yet, or a poisoned context), EINVAL (bad
+ * arguments, non-finite A), EUNSTABLE (|A| makes the step unstable),
+ * EDEVICE, ENUMERIC (NaN or Inf in the norms or the current: poisoned). */
 tddft_status tddft_propagate(tddft_ctx *ctx, int32_t nsteps, const double *A, double *J_out);
 
-/* Density [n3][n2][n1] (may be NULL) and current [3] (may be NULL) at the
- * current time; the current uses the last A seen (0 before any propagate). */
+/* Density [n3][n2][n1] (Eq. rho; may be NULL) and macroscopic current [3]
+ * (Eq. macro_current, nonlocal part included; may be NULL) at the current
+ * time; the current uses the last A seen (0 before any propagate). Errors:
+ * EINVAL, ESTATE (poisoned), EDEVICE. */
 tddft_status tddft_density_current(tddft_ctx *ctx, double *rho, double *J);
 
 /* Copy the orbitals back as complex128 [n_k][n_orb][n3][n2][n1]. */
@@ -157,8 +175,10 @@ tddft_status tddft_get_orbitals(tddft_ctx *ctx, double *psi);
  * potential; the device state then equals a fresh init from psi (resume). */
 tddft_status tddft_set_orbitals(tddft_ctx *ctx, const double *psi);
 
-/* Total energy: sum_k w_k sum_n 2 <w|h_kin + V_loc + V_NL|w> + 1/2 int rho V_H
- * + int rho eps_xc (ion-ion constant omitted), at the last A seen. */
+/* Total energy (Sec. 4.1: the electronic energy whose change is the
+ * excitation energy): sum_k w_k sum_n 2 <w|h_kin + V_loc + V_NL|w>
+ * + 1/2 int rho V_H + int rho eps_xc (ion-ion constant omitted), at the last
+ * A seen. Errors: EINVAL, ESTATE (no set_potential, or poisoned), EDEVICE. */
 tddft_status tddft_energy(tddft_ctx *ctx, double *E);
 
 /* The mixing parameter c of the BJ / TB09 exchange at the last potential
@@ -201,6 +221,14 @@ tddft_status tddft_set_reference(tddft_ctx *ctx);
  * starting value. ESTATE before tddft_set_reference. */
 tddft_status tddft_excited_electrons(tddft_ctx *ctx, double *n_ex);
 
+/* Electronic excitation energy (Sec. 4.1: the energy at time t minus that of
+ * the ground state), E_ex = E(t) - E(ref) in Ha per cell, with E(ref) the
+ * energy when tddft_set_reference was called (divide by the cell volume for
+ * the energy per unit volume). ESTATE before set_reference, and for the BJ /
+ * TB09 potentials, which have no energy functional: Sec. 4.1 takes the work
+ * of the field there (tddft_work). */
+tddft_status tddft_excitation_energy(tddft_ctx *ctx, double *E_ex);
+
 /* Mean device time per step of the last propagate, from HIP events (ms). */
 tddft_status tddft_last_timing(tddft_ctx *ctx, double *ms_per_step);
 
@@ -222,8 +250,49 @@ enum { TDDFT_KERNEL_STAGE = 0, TDDFT_KERNEL_PROJECT = 1, TDDFT_KERNEL_OBSERVE = 
  * set_potential; EINVAL for an unknown kernel or reps < 1. */
 tddft_status tddft_time_kernel(tddft_ctx *ctx, int32_t which, int32_t reps, double *ms_per_launch);
 
+/* Message of the last failure on ctx; with ctx NULL, of the last failed call
+ * on this thread that takes no context (the spectra and work entry points). */
 const char *tddft_last_error(const tddft_ctx *ctx);
 void tddft_free(tddft_ctx *ctx);
+
+/* ---- Spectra and work from time series --------------------------------
+ * Post-processing of one run's recorded series on the device. Host arrays in
+ * and out, as everywhere; each call allocates its device buffers, computes,
+ * copies back and frees before returning. Time integrals use the trapezoid
+ * rule on t_n = n dt, n = 0 .. n_t - 1, with T = (n_t - 1) dt. The mask is
+ * f(u) = 1 - 3u^2 + 2u^3 (Sec. 3.1). Every sum runs in a fixed order (same
+ * bits on every call). Errors: EINVAL (n_t < 2, n < 1, NULL pointer, dt or
+ * the kick zero or not finite, non-finite input, unknown flag), ENOMEM,
+ * EDEVICE; the message is tddft_last_error(NULL). */
+#define TDDFT_SPECTRUM_NO_MASK 0x1u        /* f = 1 instead of the cubic mask          */
+#define TDDFT_SPECTRUM_SUBTRACT_MEAN 0x2u  /* I -> I - mean(I) first (Sec. 4.2: removes a
+                                              small constant current so that sigma(0) = 0) */
+
+/* Conductivity of a periodic system after a kick A(t) = A0 theta(t)
+ * (Sec. 4.1, Eq. sigma_ft): sigma(w) = -(c / A0) int_0^T dt e^{i w t}
+ * f(t / T) I(t), one component. I [n_t]: the current at t_n (I[0] just after
+ * the kick); omega [n_w] (Ha); sigma [n_w][2] receives (re, im); eps
+ * ([n_w][2], may be NULL) the dielectric function eps = 1 + 4 pi i sigma / w
+ * (Sec. 4.1; not finite at w = 0). */
+tddft_status tddft_conductivity(int32_t n_t, const double *I, double dt, double A0, int32_t n_w,
+                                const double *omega, uint32_t flags, double *sigma, double *eps);
+
+/* Oscillator-strength distribution of an isolated system after an impulsive
+ * kick F0 (Sec. 3.1, Eq. distribution, in atomic units and per unit kick):
+ * df/dE = (2 E / pi) Im int_0^T f(t / T) d(t) e^{i E t} dt / F0, with the
+ * mask always applied. d [n_t]: one dipole component at t_n (d[0] = 0 at the
+ * kick); E [n_E] (Ha); dfdE [n_E]. */
+tddft_status tddft_oscillator_strength(int32_t n_t, const double *d, double dt, double F0, int32_t n_E,
+                                       const double *E, double *dfdE);
+
+/* Work of the field on the electrons of one cell (Sec. 4.1, W(t), the
+ * excitation energy for xc potentials without an energy functional):
+ * W_n = volume sum_{m<n} dt (I_m + I_{m+1}) / 2 . E_m with
+ * E_m = -(A_{m+1} - A_m) / (c dt), so that dE/dt = +volume I . E (the sign
+ * with I as in Eq. macro_current and E = -(1/c) dA/dt). I, A [n_t][3]: the
+ * current and the vector potential at t_n (A is the propagate table, I[0]
+ * the current before the first step); W [n_t] (Ha per cell). */
+tddft_status tddft_work(int32_t n_t, const double *I, const double *A, double dt, double volume, double *W);
 
 /* ---- Batches of independent cells -------------------------------------
  * Many cells with their own grid, orbital and k-point counts, atoms and

@@ -48,7 +48,8 @@ EXPORTED = ["tddft_abi_version", "tddft_init", "tddft_set_potential", "tddft_pro
             "tddft_nn_get_params", "tddft_nn_set_params", "tddft_nn_forward", "tddft_nn_loss_grad",
             "tddft_nn_adam_step", "tddft_nn_train", "tddft_nn_last_error", "tddft_nn_free",
             "tddft_ms_create", "tddft_ms_attach_surrogate", "tddft_ms_step", "tddft_ms_status",
-            "tddft_ms_last_error", "tddft_ms_free"]
+            "tddft_ms_last_error", "tddft_ms_free", "tddft_excitation_energy", "tddft_conductivity",
+            "tddft_oscillator_strength", "tddft_work"]
 KERNEL_STAGE, KERNEL_PROJECT, KERNEL_OBSERVE, KERNEL_DENSITY, KERNEL_FUSED = 0, 1, 2, 3, 4
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -175,6 +176,14 @@ def load_library(path: str = LIB_PATH):
     for name in ("tddft_nn_create", "tddft_nn_get_params", "tddft_nn_set_params", "tddft_nn_forward",
                  "tddft_nn_loss_grad", "tddft_nn_adam_step", "tddft_nn_train", "tddft_ms_create",
                  "tddft_ms_attach_surrogate", "tddft_ms_step", "tddft_ms_status"):
+        getattr(lib, name).restype = C.c_int
+    # spectra and work (no context)
+    lib.tddft_excitation_energy.argtypes = [C.c_void_p, _dp]
+    lib.tddft_conductivity.argtypes = [C.c_int32, _dp, C.c_double, C.c_double, C.c_int32, _dp, C.c_uint32,
+                                       _dp, _dp]
+    lib.tddft_oscillator_strength.argtypes = [C.c_int32, _dp, C.c_double, C.c_double, C.c_int32, _dp, _dp]
+    lib.tddft_work.argtypes = [C.c_int32, _dp, _dp, C.c_double, C.c_double, _dp]
+    for name in ("tddft_excitation_energy", "tddft_conductivity", "tddft_oscillator_strength", "tddft_work"):
         getattr(lib, name).restype = C.c_int
     if lib.tddft_abi_version() != ABI_VERSION:
         raise RuntimeError("libtddft.so ABI version mismatch")
@@ -342,6 +351,12 @@ class TDDFT:
         self._check(self.lib.tddft_excited_electrons(self.h, C.byref(v)))
         return v.value
 
+    def excitation_energy(self) -> float:
+        """E(t) - E(reference) in Ha per cell (LDA; see tddft_work for BJ / TB09)."""
+        v = C.c_double()
+        self._check(self.lib.tddft_excitation_energy(self.h, C.byref(v)))
+        return v.value
+
     def kick(self, F0: float, axis: int):
         self._check(self.lib.tddft_kick(self.h, float(F0), int(axis)))
 
@@ -373,6 +388,53 @@ class TDDFT:
 
     def __exit__(self, *a):
         self.close()
+
+
+SPECTRUM_NO_MASK, SPECTRUM_SUBTRACT_MEAN = 1, 2
+
+
+def _stateless_check(lib, st):
+    if st != OK:
+        msg = lib.tddft_last_error(None)
+        raise TDDFTError(st, msg.decode() if msg else "")
+
+
+def conductivity(I, dt: float, A0: float, omegas, *, mask: bool = True, subtract_mean: bool = False,
+                 dielectric: bool = False):
+    """sigma(omega) (complex) of one current component after a kick A0, and
+    optionally eps(omega), computed by the library's kernels."""
+    lib = load_library()
+    I = np.ascontiguousarray(I, dtype=np.float64)
+    om = np.ascontiguousarray(omegas, dtype=np.float64)
+    sig = np.empty(om.shape[0], dtype=np.complex128)
+    eps = np.empty(om.shape[0], dtype=np.complex128) if dielectric else None
+    flags = (0 if mask else SPECTRUM_NO_MASK) | (SPECTRUM_SUBTRACT_MEAN if subtract_mean else 0)
+    _stateless_check(lib, lib.tddft_conductivity(I.shape[0], _ptr(I), float(dt), float(A0), om.shape[0],
+                                                 _ptr(om), flags, _ptr(sig.view(np.float64)),
+                                                 _ptr(eps.view(np.float64)) if dielectric else None))
+    return (sig, eps) if dielectric else sig
+
+
+def oscillator_strength(d, dt: float, F0: float, energies):
+    """df/dE of one dipole component after a kick F0 (library kernels)."""
+    lib = load_library()
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    E = np.ascontiguousarray(energies, dtype=np.float64)
+    out = np.empty(E.shape[0])
+    _stateless_check(lib, lib.tddft_oscillator_strength(d.shape[0], _ptr(d), float(dt), float(F0), E.shape[0],
+                                                        _ptr(E), _ptr(out)))
+    return out
+
+
+def work(I, A, dt: float, volume: float):
+    """W(t_n) of the field on the electrons of one cell (library kernels)."""
+    lib = load_library()
+    I = np.ascontiguousarray(I, dtype=np.float64)
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    assert I.shape == A.shape and I.ndim == 2 and I.shape[1] == 3
+    W = np.empty(I.shape[0])
+    _stateless_check(lib, lib.tddft_work(I.shape[0], _ptr(I), _ptr(A), float(dt), float(volume), _ptr(W)))
+    return W
 
 
 def mfma_layout_check(A: np.ndarray, B: np.ndarray) -> np.ndarray:

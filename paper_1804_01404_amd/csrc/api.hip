@@ -89,6 +89,8 @@ struct tddft_ctx {
   void* Wsave = nullptr;    // predictor-corrector: the orbitals at t_n
   void* Wref = nullptr;     // reference (ground-state) orbitals for the excited-pair count
   double* Sk = nullptr;     // [n_k] occupied weight kept in the reference space
+  double E_ref = 0.0;       // energy of the reference state (excitation energy)
+  bool have_E_ref = false;
   double* Vsave = nullptr;  // predictor-corrector: V(t_n)
   double2 *phA = nullptr, *phAJ = nullptr;
   double* obs = nullptr;
@@ -752,7 +754,7 @@ extern "C" {
 
 uint32_t tddft_abi_version(void) { return TDDFT_ABI_VERSION; }
 
-const char* tddft_last_error(const tddft_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+const char* tddft_last_error(const tddft_ctx* ctx) { return ctx ? ctx->err.c_str() : stateless_error(); }
 
 void tddft_free(tddft_ctx* ctx) {
   if (!ctx) return;
@@ -1400,6 +1402,28 @@ tddft_status tddft_set_reference(tddft_ctx* c) {
   if (!c->Sk && (st = dalloc_t(c, (size_t)c->cfg.n_k, &c->Sk)) != TDDFT_OK) return st;
   LAUNCH(launch_copy8(c->W, c->Wref, wbytes, c->stream), "copy reference");
   HIP_TRY(hipStreamSynchronize(c->stream));
+  // the energy of the reference state, for the excitation energy (only where
+  // the potential comes from an energy functional)
+  c->have_E_ref = false;
+  if (c->potential_set && !is_mgga(c)) {
+    st = tddft_energy(c, &c->E_ref);
+    if (st != TDDFT_OK) return st;
+    c->have_E_ref = true;
+  }
+  return TDDFT_OK;
+}
+
+tddft_status tddft_excitation_energy(tddft_ctx* c, double* E_ex) {
+  if (!c || !E_ex) return c ? fail(c, TDDFT_EINVAL, "null E_ex") : TDDFT_EINVAL;
+  if (c->poisoned) return fail(c, TDDFT_ESTATE, "context poisoned: " + c->err);
+  if (!c->have_E_ref)
+    return fail(c, TDDFT_ESTATE,
+                is_mgga(c) ? "the BJ / TB09 potentials have no energy functional: use tddft_work on the current"
+                           : "excitation_energy before set_reference (with the potential set)");
+  double E = 0.0;
+  tddft_status st = tddft_energy(c, &E);
+  if (st != TDDFT_OK) return st;
+  *E_ex = E - c->E_ref;
   return TDDFT_OK;
 }
 

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 #include <cstddef>
 #include <cstdint>
+#include <algorithm>
 
 namespace td {
 
@@ -215,6 +216,22 @@ hipError_t launch_real_part(const double2* src, double* dst, size_t n, hipStream
 hipError_t launch_fill(double* p, double v, size_t n, hipStream_t s);
 hipError_t launch_copy8(const void* src, void* dst, size_t bytes, hipStream_t s);
 hipError_t launch_mid_potential(const double* Vn, double* Vd, float* Vf, size_t n, hipStream_t s);
+
+// ---- spectra and work from time series (k_spectra.hip) ----------------------
+constexpr int kSpecThreads = 256;    // frequencies per workgroup
+constexpr int kSpecChunksMax = 64;   // sample chunks summed in a fixed order
+int spec_chunks(int n_t);
+// scratch: 1 + spec_chunks(n_t) * n_w double2 (the mean, then the chunk partials)
+size_t spectrum_scratch_entries(int n_t, int n_w);
+// kind 0: out = scale * Z as [n_w][2] and eps ([n_w][2], may be null);
+// kind 1: out[j] = (2 w_j / pi) Im Z(w_j) * scale
+hipError_t launch_spectrum(const double* x, int n_t, double dt, const double* om, int n_w, int kind, double scale,
+                           int use_mask, int subtract_mean, double2* scratch, double* out, double* eps,
+                           hipStream_t s);
+hipError_t launch_work(const double* I, const double* A, int n_t, double dt, double volume, double* W, hipStream_t s);
+// message of the last failed call that has no context (thread-local)
+void set_stateless_error(const char* msg);
+const char* stateless_error();
 
 // ---- multiscale Maxwell (k_maxwell.hip) -----------------------------------
 hipError_t launch_fdtd_step(const double* A_now, const double* A_prev, const double* I, double* A_new, int n,

@@ -126,7 +126,36 @@ def test_null_arguments():
     assert lib.tddft_propagate(None, 1, None, None) == binding.EINVAL
     assert lib.tddft_energy(None, None) == binding.EINVAL
     lib.tddft_free(None)
-    assert lib.tddft_last_error(None) == b"null context"
+    assert lib.tddft_excitation_energy(None, None) == binding.EINVAL
+
+
+def test_spectra_reject_bad_arguments_without_device():
+    """The spectra and work entry points validate before any device work and
+    leave the reason in tddft_last_error(NULL)."""
+    from paper_1804_01404_amd import binding
+    lib = binding.load_library()
+    dp = C.POINTER(C.c_double)
+    I = np.zeros(8)
+    om = np.ones(3)
+    out = np.zeros(6)
+    p = lambda a: a.ctypes.data_as(dp)
+    assert lib.tddft_conductivity(1, p(I), 0.1, 1.0, 3, p(om), 0, p(out), None) == binding.EINVAL
+    assert b"bad sizes" in lib.tddft_last_error(None)
+    assert lib.tddft_conductivity(8, p(I), 0.1, 0.0, 3, p(om), 0, p(out), None) == binding.EINVAL
+    assert b"A0" in lib.tddft_last_error(None)
+    assert lib.tddft_conductivity(8, p(I), 0.1, 1.0, 3, p(om), 0x10, p(out), None) == binding.EINVAL
+    assert lib.tddft_conductivity(8, p(I), 0.0, 1.0, 3, p(om), 0, p(out), None) == binding.EINVAL
+    bad = I.copy()
+    bad[3] = np.nan
+    assert lib.tddft_conductivity(8, p(bad), 0.1, 1.0, 3, p(om), 0, p(out), None) == binding.EINVAL
+    assert b"not finite" in lib.tddft_last_error(None)
+    assert lib.tddft_oscillator_strength(8, p(I), 0.1, 0.0, 3, p(om), p(out)) == binding.EINVAL
+    assert lib.tddft_oscillator_strength(8, p(I), 0.1, 1e-3, 0, p(om), p(out)) == binding.EINVAL
+    A = np.zeros((8, 3))
+    assert lib.tddft_work(0, p(A), p(A), 0.1, 1.0, p(out)) == binding.EINVAL
+    assert lib.tddft_work(8, p(A), None, 0.1, 1.0, p(out)) == binding.EINVAL
+    assert lib.tddft_work(8, p(A), p(A), 0.1, float("inf"), p(out)) == binding.EINVAL
+    assert b"work" in lib.tddft_last_error(None)
 
 
 def test_product_path_has_no_oracle_dependency():
