@@ -85,6 +85,13 @@ enum { TDDFT_XC_NONE = 0, TDDFT_XC_PZ81 = 1, TDDFT_XC_TB09 = 2, TDDFT_XC_BJ = 3 
                                           redone from t_n under (V(t_n) + V(t_{n+1})) / 2.
                                           Twice the work per step; one more copy of
                                           the orbitals in device memory */
+#define TDDFT_FLAG_NORM_WATCHDOG 0x40u /* failure detection: propagate returns
+                                          ENUMERIC (and poisons the context) once an
+                                          orbital norm is further than 1e-3 from 1.
+                                          The fourth-order step conserves norms to
+                                          about 1e-6 per 1000 steps within its
+                                          stability bound, so a trip means growth
+                                          (ALLOW_UNSTABLE) or corrupted state */
 
 typedef struct {
   uint32_t abi_version;   /* TDDFT_ABI_VERSION                                  */

@@ -35,7 +35,7 @@ def xc_code(xc) -> int:
         raise ValueError(f"unknown xc choice {xc!r}") from None
 
 FLAG_ALLOW_UNSTABLE, FLAG_DEBUG_SYNC, FLAG_NO_GRAPH, FLAG_STREAMING, FLAG_NO_TUNE = 1, 2, 4, 8, 16
-FLAG_PREDICTOR_CORRECTOR = 32
+FLAG_PREDICTOR_CORRECTOR, FLAG_NORM_WATCHDOG = 32, 64
 
 EXPORTED = ["tddft_abi_version", "tddft_init", "tddft_set_potential", "tddft_propagate",
             "tddft_density_current", "tddft_get_orbitals", "tddft_set_orbitals", "tddft_energy",

@@ -331,6 +331,9 @@ const float* vpot<float>(tddft_ctx* c) {
   return c->Vf;
 }
 
+// tolerance of the norm watchdog (0: off)
+double norm_tol(const tddft_ctx* c) { return (c->cfg.flags & TDDFT_FLAG_NORM_WATCHDOG) ? 1e-3 : 0.0; }
+
 // observables of W with kappaJ / phAJ already set: obs, jnl, then finish
 template <typename T>
 tddft_status enqueue_observe(tddft_ctx* c, int bump) {
@@ -360,7 +363,7 @@ tddft_status enqueue_observe(tddft_ctx* c, int bump) {
   }
   LAUNCH(launch_finish(c->obs, c->g.tiles_x * c->g.tiles_y * c->g.zslabs, c->jnl, nl ? 1 : 0, c->kw_d, c->kappaJ,
                        c->cfg.n_orb, c->cfg.n_k, c->dV, c->volume, c->counter, bump, c->Jtab, c->scalars,
-                       c->nanflag, c->stream),
+                       c->nanflag, norm_tol(c), c->stream),
          "finish");
   return TDDFT_OK;
 }
@@ -432,7 +435,7 @@ template <typename T>
 tddft_status enqueue_fused_tail(tddft_ctx* c) {
   LAUNCH(launch_finish(c->obs, 1, c->jnl, c->nl.n_atoms > 0 ? 1 : 0, c->kw_d, c->kappaJ, c->cfg.n_orb,
                        c->cfg.n_k, c->dV, c->volume, c->counter, 1, c->Jtab, c->scalars, c->nanflag,
-                       c->stream),
+                       norm_tol(c), c->stream),
          "finish");
   return enqueue_density_potential<T>(c);
 }
@@ -675,7 +678,9 @@ tddft_status collect_propagate(tddft_ctx* c, int32_t nsteps, const double* A, do
   HIP_TRY(hipMemcpyAsync(&flag, c->nanflag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   for (int i = 0; i < 3; ++i) c->A_last[i] = A[3 * (size_t)nsteps + i];
-  if (flag) return fail(c, TDDFT_ENUMERIC, "NaN or Inf in the orbital norms or current");
+  if (flag & 1) return fail(c, TDDFT_ENUMERIC, "NaN or Inf in the orbital norms or current");
+  if (flag & 2)
+    return fail(c, TDDFT_ENUMERIC, "norm watchdog: an orbital norm left 1 by more than 1e-3 (unstable step?)");
   return TDDFT_OK;
 }
 

@@ -190,7 +190,7 @@ hipError_t launch_mgga_potential(const double* rho, const double* tau, const Mgg
 hipError_t launch_finish(const double* obs, int tiles, const double* jnl, int use_nl,
                          const double* kw, const double* kappaJ, int n_orb, int n_k, double dV,
                          double volume, int* counter, int bump, double* Jtab, double* scalars,
-                         int* nanflag, hipStream_t s);
+                         int* nanflag, double norm_tol, hipStream_t s);
 
 hipError_t launch_grid_sums(const double* rho, const double* rho0, const double* vh,
                             const double* exc, Geometry g, double* out, hipStream_t s);

@@ -411,12 +411,14 @@ hipError_t launch_xc_assemble(const double2* data, int n1, int n2, int n3, int M
 // One workgroup: I = -(1/Omega) sum_o f_o [p_o + kappaJ_k norm_o + jNL_o],
 // the orbital energy sum_o f_o [kin + kappaJ.p + 1/2 |kappaJ|^2 norm + vloc + E_NL],
 // and the occupied norm; f_o = 2 w_k. Thread t sums orbitals t, t+1024, ...
-// in order, then a fixed pairwise tree combines the threads.
+// in order, then a fixed pairwise tree combines the threads. nanflag gets
+// bit 0 for a non-finite norm or momentum, bit 1 (only when norm_tol > 0)
+// for a norm further than norm_tol from 1.
 __global__ __launch_bounds__(1024) void k_finish(const double* obs, int tiles, const double* jnl,
                                                  int use_nl, const double* kw, const double* kappaJ,
                                                  int n_orb, int n_k, double dV, double volume,
                                                  int* counter, int bump, double* Jtab,
-                                                 double* scalars, int* nanflag) {
+                                                 double* scalars, int* nanflag, double norm_tol) {
   __shared__ double red[1024][5];
   const int t = threadIdx.x;
   const int n_tot = n_orb * n_k;
@@ -443,7 +445,8 @@ __global__ __launch_bounds__(1024) void k_finish(const double* obs, int tiles, c
     en += f * (s[4] + kx * s[1] + ky * s[2] + kz * s[3] + 0.5 * (kx * kx + ky * ky + kz * kz) * s[0] +
                s[5] + enl);
     nr += f * s[0];
-    if (!isfinite(s[0]) || !isfinite(s[1]) || !isfinite(s[2]) || !isfinite(s[3])) bad = 1;
+    if (!isfinite(s[0]) || !isfinite(s[1]) || !isfinite(s[2]) || !isfinite(s[3])) bad |= 1;
+    else if (norm_tol > 0.0 && fabs(s[0] - 1.0) > norm_tol) bad |= 2;
   }
   red[t][0] = cx;
   red[t][1] = cy;
@@ -456,7 +459,7 @@ __global__ __launch_bounds__(1024) void k_finish(const double* obs, int tiles, c
       for (int i = 0; i < 5; ++i) red[t][i] += red[t + w][i];
     __syncthreads();
   }
-  if (bad) atomicOr(nanflag, 1);
+  if (bad) atomicOr(nanflag, bad);
   if (t == 0) {
     const double J[3] = {-red[0][0] / volume, -red[0][1] / volume, -red[0][2] / volume};
     for (int i = 0; i < 3; ++i) scalars[i] = J[i];
@@ -473,9 +476,9 @@ __global__ __launch_bounds__(1024) void k_finish(const double* obs, int tiles, c
 hipError_t launch_finish(const double* obs, int tiles, const double* jnl, int use_nl,
                          const double* kw, const double* kappaJ, int n_orb, int n_k, double dV,
                          double volume, int* counter, int bump, double* Jtab, double* scalars,
-                         int* nanflag, hipStream_t s) {
+                         int* nanflag, double norm_tol, hipStream_t s) {
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, obs, tiles, jnl, use_nl, kw, kappaJ, n_orb,
-                     n_k, dV, volume, counter, bump, Jtab, scalars, nanflag);
+                     n_k, dV, volume, counter, bump, Jtab, scalars, nanflag, norm_tol);
   return hipGetLastError();
 }
 

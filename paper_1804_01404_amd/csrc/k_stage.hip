@@ -303,9 +303,13 @@ hipError_t launch_nl_addback(const StageArgs<T>& a, const int* ents, int n_ents,
 template hipError_t launch_nl_addback<double>(const StageArgs<double>&, const int*, int, int, hipStream_t);
 template hipError_t launch_nl_addback<float>(const StageArgs<float>&, const int*, int, int, hipStream_t);
 
-// Per-orbital sums used by the current and the energy, all in FP64:
+// Per-orbital sums used by the current and the energy:
 // norm = sum |w|^2, p_mu = sum Im(conj(w) d_mu w), kin = sum Re(conj(w)(-1/2 Lap w)),
-// vloc = sum V_loc |w|^2 (the caller multiplies by h1 h2 h3).
+// vloc = sum V_loc |w|^2 (the caller multiplies by h1 h2 h3). The neighbour
+// differences and their weighted sums d_mu w and -1/2 Lap w are formed in the
+// orbital precision (exact differences of FP32 values up to one rounding, then
+// FP32 weighted sums for complex FP32); the products with w and the running
+// sums over the grid are FP64. complex128 is FP64 throughout.
 template <typename T, int BC>
 __global__ __launch_bounds__(1024) void k_observe(ObserveArgs<T> a) {
   using T2 = typename Vec2<T>::type;

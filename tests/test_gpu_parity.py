@@ -415,3 +415,79 @@ def test_excited_electrons_match_oracle(prec):
     floor = 1e-13 * full if prec == "c128" else 1e-6 * full
     assert abs(n0) < floor
     assert abs(n1 - ref) < (1e-10 if prec == "c128" else 1e-4) * abs(ref) + floor
+
+
+def test_streaming_mixed_path_after_1000_steps():
+    """The per-stage path in complex FP32 (its observe pass forms the
+    differences of the current and kinetic sums in FP32, the products and
+    running sums in FP64) against the per-stage complex128 path over 1000
+    steps: current series within 1e-5 of its maximum; and, from a ground
+    state with no field, the energy of the mixed run stays within 1e-5 of the
+    complex128 run's at every sample, with a drift below 1e-5 per 1000 steps."""
+    from paper_1804_01404_amd.binding import TDDFT
+
+    def run(s, prec, psi=None, every=0):
+        with TDDFT(s, precision=prec, flags=STREAMING) as t:
+            t.set_potential()
+            if psi is not None:
+                t.set_orbitals(psi)
+            if not every:
+                return t.propagate(s.A)
+            E = [t.energy()]
+            for i in range(0, s.A.shape[0] - 1, every):
+                t.propagate(s.A[i:i + every + 1])
+                E.append(t.energy())
+            return np.array(E)
+    s = synth.single_cell_config(1, nk=2, nsteps=1000)
+    announce("streaming mixed vs c128, 20^3 x 8 k, 1000 steps")
+    J64 = run(s, "c128")
+    J32 = run(s, "mixed")
+    err = max_rel_series(J32, J64)
+    announce(f"  current error {err:.3e}")
+    assert err < 1e-5
+    g = synth.single_cell_config(0, nsteps=1000, kick=0.0)
+    with TDDFT(g, precision="c128") as t:
+        t.set_potential()
+        t.ground_state(600, 0.035)
+        psi = t.orbitals()
+    announce("streaming energy drift from the ground state, 16^3, 1000 steps")
+    E64 = run(g, "c128", psi=psi, every=100)
+    E32 = run(g, "mixed", psi=psi, every=100)
+    tt = np.arange(E32.shape[0]) * 100
+    drift = abs(np.polyfit(tt, E32, 1)[0] * 1000 / E32[0])
+    gap = np.max(np.abs(E32 - E64)) / abs(E64[0])
+    announce(f"  mixed drift {drift:.3e} per 1000 steps, gap to c128 {gap:.3e}")
+    assert drift < 1e-5 and gap < 1e-5
+
+
+@pytest.mark.parametrize("flags", PATHS)
+def test_mixed_current_against_oracle(flags):
+    """The mixed path's current against the oracle directly (not through the
+    complex128 path), 40 steps of the 20^3 cell with 8 k-points: within 1e-5 of
+    the maximum of the series."""
+    s = synth.single_cell_config(1, nk=2, nsteps=40)
+    g = gpu_run(s, precision="mixed", flags=flags)
+    o = oracle_run(s)
+    err = max_rel_series(g["J"], o["J"])
+    announce(f"  current error against the oracle {err:.3e}")
+    assert err < 1e-5
+    assert rel_l2(g["rho"], o["rho"]) < 2e-6 * np.sqrt(40)
+
+
+@pytest.mark.parametrize("prec", ["c128", "mixed"])
+def test_projection_with_many_items(prec):
+    """A cell with 128 k-points x 8 orbitals (128 orbital groups) and 128
+    atoms with overlapping s+p spheres: 16384 (group, atom) projection items,
+    the size at which the projection runs one item per wavefront instead of
+    splitting each item over a workgroup; per-stage path, one step against the
+    oracle (orbitals, density and the current with its nonlocal part)."""
+    rng = np.random.default_rng(99)
+    k = rng.uniform(-0.4, 0.4, size=(128, 3))
+    # dt small enough for the stability bound with ~20-fold overlapping spheres
+    s = tiny_periodic(n=12, L=6.6, n_orb=8, kpts=k, n_atoms=128, nsteps=1, seed=909, real=False, dt=0.005)
+    g = gpu_run(s, precision=prec, flags=STREAMING)
+    o = oracle_run(s)
+    tol = 1e-10 if prec == "c128" else 5e-6
+    assert rel_l2(g["psi"], o["psi"]) < tol
+    assert rel_l2(g["rho"], o["rho"]) < tol
+    assert np.max(np.abs(g["J"] - o["J"])) < (1e-8 if prec == "c128" else 1e-5) * np.max(np.abs(o["J"]))
