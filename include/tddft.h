@@ -301,6 +301,23 @@ tddft_status tddft_oscillator_strength(int32_t n_t, const double *d, double dt, 
  * the current before the first step); W [n_t] (Ha per cell). */
 tddft_status tddft_work(int32_t n_t, const double *I, const double *A, double dt, double volume, double *W);
 
+/* For callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation as tddft_conductivity, same bits, with DEVICE arrays I [n_t],
+ * omega [n_w], sigma [n_w][2] and eps ([n_w][2] or NULL) owned by the caller,
+ * enqueued on `stream` (a hipStream_t, NULL for the default stream) without
+ * waiting for it. Allocates nothing: the chunk partials and the mean live in
+ * a fixed 8 MiB device array per GPU, held until the process ends, which
+ * every call on that GPU shares; calls that overlap on one GPU (other
+ * streams, other threads) race on it and must be serialised by the caller.
+ * Every slot is written before it is read, so no clearing is needed. Limit:
+ * 1 + min(64, ceil(n_t / 256)) * n_w <= 524288 (n_w <= 8191 for series of
+ * 16384 samples or more), else EINVAL. The device inputs are not checked for
+ * finiteness. Errors: EINVAL, EDEVICE; message in tddft_last_error(NULL). */
+tddft_status tddft_conductivity_noalloc(int32_t n_t, const double *I, double dt, double A0, int32_t n_w,
+                                        const double *omega, uint32_t flags, double *sigma, double *eps,
+                                        void *stream);
+
 /* ---- Batches of independent cells -------------------------------------
  * Many cells with their own grid, orbital and k-point counts, atoms and
  * field tables advance together: one hipGraph-captured batch step holds, per

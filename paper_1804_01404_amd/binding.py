@@ -49,7 +49,7 @@ EXPORTED = ["tddft_abi_version", "tddft_init", "tddft_set_potential", "tddft_pro
             "tddft_nn_adam_step", "tddft_nn_train", "tddft_nn_last_error", "tddft_nn_free",
             "tddft_ms_create", "tddft_ms_attach_surrogate", "tddft_ms_step", "tddft_ms_status",
             "tddft_ms_last_error", "tddft_ms_free", "tddft_excitation_energy", "tddft_conductivity",
-            "tddft_oscillator_strength", "tddft_work"]
+            "tddft_oscillator_strength", "tddft_work", "tddft_conductivity_noalloc"]
 KERNEL_STAGE, KERNEL_PROJECT, KERNEL_OBSERVE, KERNEL_DENSITY, KERNEL_FUSED = 0, 1, 2, 3, 4
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
