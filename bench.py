@@ -14,8 +14,13 @@ current reduction. value = orbital x k-point x grid-point steps per second
 (og-steps/s) of the mixed path (complex FP32 orbitals and stencil, FP64
 reductions, Poisson and projector products); the complex128 path is timed
 beside it. The JSON line also carries the roofline of the dominant kernel
-(a middle Horner stage, HIP events around back-to-back launches) and the
-CPU oracle timed on a bounded sample of the same workload.
+(the LDS-resident whole-step update k_fused, HIP events around back-to-back
+launches on the library's stream) and the CPU oracle timed on the host cores
+(one worker process per core) on a bounded sample of the same workload.
+Further lines run the other workloads at their stated shapes: the 96^3
+cluster with all 512 orbitals, the 64-cell uneven batch with 8-64 orbitals
+and 1-64 k-points, and the multiscale slab of 256 cells (16^3, 16 orbitals,
+64 k-points).
 """
 import argparse
 import json
@@ -29,8 +34,17 @@ sys.path.insert(0, ROOT)
 METRIC = "orbital·gridpoint Taylor steps/s (FP64 vs mixed/batched), % HBM peak"
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP64_MFMA_PEAK_TFLOPS = 78.6   # MI355X dense FP64 matrix
-FP32_VALU_PEAK_TFLOPS = 157.3  # MI355X FP32 vector (256 CU x 2.4 GHz x 256 flop/clk, packed issue)
+FP32_VALU_PACKED_TFLOPS = 157.3  # MI355X FP32 vector as published: 256 CU x 2.4 GHz x 256 flop/clk,
+                                 # which counts two packed FP32 FMAs per lane and clock
+# 256 CU x 4 SIMD x 16 lanes x 2 flop (one FMA per lane and clock) x 2.4 GHz: the FP32
+# vector rate of code built without packed FP32 instructions, as this library is
+FP32_VALU_PEAK_TFLOPS = 78.6
 FP64_VALU_PEAK_TFLOPS = 78.6   # MI355X FP64 vector
+
+
+def log(msg):
+    """Progress line on stderr (the JSON result is the only stdout line)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
 def time_path(system, precision, steps, warmup):
@@ -58,6 +72,7 @@ def time_path(system, precision, steps, warmup):
             kern["fused_ms"] = t.time_kernel(KERNEL_FUSED, 20)
         except TDDFTError:
             kern["fused_ms"] = None   # this shape takes the per-stage kernels
+        kern["report"] = t.report()
     return (t1 - t0) / steps * 1e3, dev_ms, kern, J
 
 
@@ -93,57 +108,141 @@ def stored_traffic(kernel_source, kernel_name, workload):
         return None
 
 
-def cpu_baseline(system, target_s=12.0):
-    """The oracle as it stands, on a bounded sample: the same cell, grid,
-    orbitals and projectors with a subset of the k-points, one BLAS thread.
-    The same sample then runs on the GPU (complex128 and mixed) and the
-    errors against the oracle's steps are reported beside the timing."""
-    import copy
-    import numpy as np
-    from threadpoolctl import threadpool_limits
-    from oracle import tdks
-    from paper_1804_01404_amd.binding import TDDFT
-    s = system
-    nk = 2
+# ---- the oracle on the host cores: one worker process per core, each owning a
+# block of k-points for the Taylor step, its density and its current; the
+# density and current are summed in block order in the parent, which then
+# forms the Hartree and LDA potential. Runs in a child process that never
+# touches the GPU.
 
-    def make(nk):
-        return tdks.TDKS(s.n, s.cell, s.boundary, s.kpts[:nk], np.full(nk, 1.0 / nk), s.psi0[:nk], s.dt,
-                         s.v_loc, s.projectors, hartree=s.hartree, xc=s.xc, gauge=s.gauge)
+def _oracle_worker(conn, ks):
+    from threadpoolctl import threadpool_limits
+    import numpy as np
+    from oracle import tdks
+    s = _POOL["system"]
+    grid = tdks.Grid(s.n, s.cell, s.boundary)
+    projs = [tdks.Projector(p.idx, p.x, p.beta, p.e_kb) for p in s.projectors]
+    psi = np.array(s.psi0[ks], dtype=np.complex128)
+    kpts, kw = s.kpts[ks], s.kw[ks]
     with threadpool_limits(limits=1):
         while True:
-            o = make(nk)
-            t0 = time.perf_counter()
-            o.step(s.A[0], s.A[1])
-            o.current()
-            one = time.perf_counter() - t0
-            if one * 3 >= target_s or nk >= s.n_k:
+            msg = conn.recv()
+            if msg is None:
                 break
-            nk = min(s.n_k, max(nk + 1, int(nk * target_s / (3 * one))))
-        steps = max(1, min(5, int(target_s / max(one, 1e-3))))
-        o = make(nk)
-        J_o = np.empty((steps, 3))
-        t0 = time.perf_counter()
-        for n in range(steps):
-            o.step(s.A[n], s.A[n + 1])
-            J_o[n] = o.current()
-        el = time.perf_counter() - t0
-    og = s.n_orb * nk * s.n_grid
+            V, A0, A1 = msg
+            shift = 0.5 * (A0 + A1) / tdks.C_LIGHT
+            for i, k in enumerate(kpts):
+                kap = k + shift
+                psi[i] = tdks.taylor_step(psi[i], s.dt, lambda X, kap=kap: tdks.apply_h(X, kap, V, projs, grid))
+            conn.send((tdks.density(psi, kw, grid), tdks.current(psi, kpts, kw, A1, projs, grid)))
+
+
+_POOL = {}
+
+
+def bench_sample(nk, nsteps):
+    """The bench cell restricted to its first nk k-points (equal weights)."""
+    import copy
+    import numpy as np
+    import synth
+    s = synth.single_cell_config(1, nsteps=nsteps)
+    if nk >= s.n_k:
+        return s
     sub = copy.copy(s)
     sub.kpts = s.kpts[:nk]
     sub.kw = np.full(nk, 1.0 / nk)
     sub.psi0 = s.psi0[:nk]
+    return sub
+
+
+def oracle_pool_run(steps, workers, nk):
+    """The bench cell's first nk k-points on `workers` processes: one untimed
+    step, then `steps` timed ones. Returns the density and current after the
+    last step and the timing."""
+    import multiprocessing as mp
+    import numpy as np
+    from oracle import tdks
+    s = bench_sample(nk, steps + 1)
+    _POOL["system"] = s
+    o = tdks.TDKS.from_system(s)          # the potential of the initial density
+    blocks = [b for b in np.array_split(np.arange(s.n_k), workers) if b.size]
+    ctx = mp.get_context("fork")
+    procs, conns = [], []
+    for b in blocks:
+        a, c = ctx.Pipe()
+        p = ctx.Process(target=_oracle_worker, args=(c, b))
+        p.start()
+        procs.append(p)
+        conns.append(a)
+    grid = o.grid
+    V = o.v_ks
+    J = np.zeros((steps + 1, 3))
+    t0 = None
+    for n in range(steps + 1):
+        if n == 1:
+            t0 = time.perf_counter()
+        for c in conns:
+            c.send((V, s.A[n], s.A[n + 1]))
+        parts = [c.recv() for c in conns]
+        rho = parts[0][0].copy()
+        cur = parts[0][1].copy()
+        for r, j in parts[1:]:
+            rho += r
+            cur += j
+        J[n] = cur
+        vh = tdks.hartree_periodic(rho, grid)
+        vxc, _ = tdks.lda_pz81(rho)
+        V = s.v_loc + vh + vxc
+    el = time.perf_counter() - t0
+    for c in conns:
+        c.send(None)
+    for p in procs:
+        p.join()
+    return {"rho": rho, "J": J, "seconds": el, "og": s.og, "steps": steps, "workers": len(blocks)}
+
+
+def cpu_baseline(steps=3, nk=128):
+    """The oracle as it stands on the host cores (one process per core, BLAS
+    threads pinned to 1 per worker), on a bounded sample of the bench cell:
+    its first nk of 512 k-points (all 16 orbitals, the whole grid), one
+    untimed step, then `steps` timed steps (Taylor + density + current +
+    Hartree + LDA). The same steps then run on the GPU (complex128 and mixed)
+    and their errors against the oracle are reported beside the timing."""
+    import subprocess
+    import numpy as np
+    from paper_1804_01404_amd.binding import TDDFT
+    host = os.cpu_count() or 1
+    try:
+        host = len(os.sched_getaffinity(0))
+    except AttributeError:
+        pass
+    workers = max(1, min(16, host))
+    out_npz = os.path.join(ROOT, "gpurun_out" if os.path.isdir(os.path.join(ROOT, "gpurun_out")) else ".",
+                           f".oracle_pool_{os.getpid()}.npz")
+    cmd = [sys.executable, os.path.abspath(__file__), "--oracle-pool-child", str(steps), str(workers), str(nk),
+           out_npz]
+    t_wall = time.perf_counter()
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    t_wall = time.perf_counter() - t_wall
+    if r.returncode != 0:
+        return {"error": r.stderr[-2000:]}
+    res = np.load(out_npz)
+    os.remove(out_npz)
+    og, el = float(res["og"]), float(res["seconds"])
     parity = {}
+    s = bench_sample(nk, steps + 1)
     for prec in ("c128", "mixed"):
-        with TDDFT(sub, precision=prec) as t:
+        with TDDFT(s, precision=prec) as t:
             t.set_potential()
-            J = t.propagate(s.A[:steps + 1])
+            J = t.propagate(s.A[:steps + 2])
             rho, _ = t.density_current()
-        parity[prec] = {"density_l2_error": float(np.linalg.norm(rho - o.rho) / np.linalg.norm(o.rho)),
-                        "current_error": float(np.max(np.abs(J - J_o)) / np.max(np.abs(J_o)))}
-    return {"value": og * steps / el, "unit": "og-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{nk} of {s.n_k} k-points x {s.n_orb} orbitals x {s.n_grid} points, "
-                      f"{steps} full steps (Taylor + density + current + Hartree + LDA), "
-                      f"{el:.1f} s, NumPy FP64 with one BLAS thread",
+        parity[prec] = {"density_l2_error": float(np.linalg.norm(rho - res["rho"]) / np.linalg.norm(res["rho"])),
+                        "current_error": float(np.max(np.abs(J - res["J"])) / np.max(np.abs(res["J"])))}
+    return {"value": og * steps / el, "unit": "og-steps/s", "cores": int(res["workers"]), "kind": "oracle",
+            "host_cpu_count": os.cpu_count(),
+            "sample": f"the bench cell's first {s.n_k} of 512 k-points x {s.n_orb} orbitals x {s.n_grid} points, "
+                      f"1 untimed + {steps} timed full steps (Taylor + density + current + Hartree + LDA) "
+                      f"in {el:.1f} s, NumPy FP64 on {int(res['workers'])} worker processes over k-point "
+                      f"blocks, one BLAS thread each; child process wall time {t_wall:.1f} s",
             "gpu_vs_oracle_on_sample": parity}
 
 
@@ -215,36 +314,69 @@ def bench_mgga(system, precision, lda_ms, steps=60, warmup=10):
             "fused_ms": kern["fused_ms"], "current_finite": bool(np.all(np.isfinite(J)))}
 
 
-def bench_cluster(steps=10, warmup=3, n_orb=64):
-    """The isolated-cluster shape (96^3 box, 256 atoms with s+p projectors,
-    length gauge) on the per-stage path, with n_orb of its 512 orbitals: step
-    rate and the middle Horner stage against the HBM roof."""
+def mfma_projection(system, project_ms, stage_mode=True):
+    """MFMA work of one projection launch (per-stage path): one 16x16x4 FP64
+    MFMA per four sphere entries, per atom and group of eight orbitals; in the
+    stage mode 4 of its 16 columns (the m = 0 moment of each projector) are
+    used, so the useful flops are a quarter of the issued ones."""
+    n_groups = (system.n_orb * system.n_k + 7) // 8
+    issued = sum(n_groups * -(-p.npts // 4) * 2 * 16 * 16 * 4 for p in system.projectors)
+    useful = issued / 4 if stage_mode else issued
+    t = project_ms * 1e-3
+    return {"issued_tflops": issued / t / 1e12, "useful_tflops": useful / t / 1e12,
+            "peak": FP64_MFMA_PEAK_TFLOPS, "frac_issued": issued / t / 1e12 / FP64_MFMA_PEAK_TFLOPS,
+            "frac_useful": useful / t / 1e12 / FP64_MFMA_PEAK_TFLOPS, "ms_per_launch": project_ms}
+
+
+def per_stage_figures(system, kern, esz):
+    """HBM fractions of the per-stage kernels from their algorithmic bytes:
+    a middle stage reads u_s and w and writes u_{s-1} (3 esz per og), the
+    observe pass reads w once (esz per og)."""
+    og = system.og
+    st = 3 * esz * og / (kern["stage_ms"] * 1e-3) / 1e9
+    ob = esz * og / (kern["observe_ms"] * 1e-3) / 1e9
+    return {"stage_ms": kern["stage_ms"], "stage_GBs": st, "stage_frac_hbm": st / HBM_PEAK_GBS,
+            "observe_ms": kern["observe_ms"], "observe_GBs": ob, "observe_frac_hbm": ob / HBM_PEAK_GBS,
+            "project_ms": kern["project_ms"], "tuner": kern["report"].get("stage"),
+            "tuner_source": kern["report"].get("source")}
+
+
+def bench_cluster(steps=5, warmup=2, n_orb=512):
+    """The isolated-cluster workload at its stated size: 96^3 box, 256 atoms
+    with s+p projectors, all 512 orbitals, length gauge, Gaussian-envelope
+    pulse; the orbital does not fit in LDS, so this is the per-stage path with
+    the tuned decomposition."""
     import numpy as np
     import synth
+    t0 = time.perf_counter()
     s = synth.single_cell_config(2, n_orb=n_orb, nsteps=steps + warmup)
+    t_gen = time.perf_counter() - t0
     ms, dev_ms, kern, J = time_path(s, "mixed", steps, warmup)
-    stage_bytes = 3 * 8 * s.og
-    return {"workload": f"cluster-96^3: 256 atoms, {n_orb} of 512 orbitals, Gamma, length gauge",
-            "og_per_step": s.og, "ms_per_step": ms, "value": s.og / (ms * 1e-3), "unit": "og-steps/s",
-            "stage_ms": kern["stage_ms"], "stage_GBs": stage_bytes / (kern["stage_ms"] * 1e-3) / 1e9,
-            "stage_frac_hbm": stage_bytes / (kern["stage_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
-            "observe_ms": kern["observe_ms"], "project_ms": kern["project_ms"],
-            "current_finite": bool(np.all(np.isfinite(J)))}
+    out = {"workload": f"cluster-96^3: 256 atoms, {n_orb} orbitals, Gamma, length gauge, dt 0.02",
+           "og_per_step": s.og, "ms_per_step": ms, "value": s.og / (ms * 1e-3), "unit": "og-steps/s",
+           "steps": steps, "warmup": warmup, "input_generation_s": t_gen,
+           "current_finite": bool(np.all(np.isfinite(J)))}
+    out.update(per_stage_figures(s, kern, 8))
+    out["mfma_projection"] = mfma_projection(s, kern["project_ms"])
+    return out
 
 
-def bench_batch(steps=30, warmup=8):
-    """The uneven-batch path on 64 seeded cells (grids 12..32, up to 32
-    orbitals and 8 k-points each: the 64-cell workload with the orbital and
-    k-point ranges cut so that the host can generate the initial orbitals in
-    seconds), mixed and complex128."""
+def bench_batch(steps=12, warmup=6):
+    """The uneven-batch workload at its stated ranges: 64 seeded periodic
+    cells, grids {12, 16, 20, 24, 32}^3 at h 0.55, 8-64 orbitals, 1-64
+    k-points, 2-16 atoms, each with its own cos^2 pulse; mixed and
+    complex128. The first steps of the mixed run include the tuner's
+    candidate steps (warm-up)."""
     import torch
     import synth
     from paper_1804_01404_amd.binding import TDDFTBatch
-    cells = synth.batch_cells(64, nsteps=warmup + steps, max_orb=32, max_k=8)
+    t0 = time.perf_counter()
+    cells = synth.batch_cells(64, nsteps=warmup + steps)
+    t_gen = time.perf_counter() - t0
     og = sum(c.og for c in cells)
     out = {"workload": "batch-64cells: 64 periodic cells, grids {12,16,20,24,32}^3 at h 0.55, "
-                       "8-32 orbitals, 1-8 k-points, 2-16 atoms, own cos^2 pulse each, dt 0.02",
-           "og_per_step": og}
+                       "8-64 orbitals, 1-64 k-points, 2-16 atoms, own cos^2 pulse each, dt 0.02",
+           "og_per_step": og, "input_generation_s": t_gen, "steps": steps, "warmup": warmup}
     for prec in ("mixed", "c128"):
         with TDDFTBatch(cells, precision=prec) as b:
             b.propagate([c.A[: warmup + 1] for c in cells])
@@ -255,6 +387,8 @@ def bench_batch(steps=30, warmup=8):
             el = time.perf_counter() - t0
             out[prec] = {"value": og * steps / el, "ms_per_step": el / steps * 1e3,
                          "device_ms_per_step": b.last_timing_ms()}
+            if prec == "mixed":
+                out["plan"] = b.report()
     out["speedup_mixed_over_c128"] = out["mixed"]["value"] / out["c128"]["value"]
     return out
 
@@ -316,7 +450,16 @@ def main():
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="also run a plain device copy of this many MB (a known-size "
                          "reference for the HBM byte counters of a profiler run)")
+    ap.add_argument("--oracle-pool-child", nargs=4, metavar=("STEPS", "WORKERS", "NK", "OUT"),
+                    help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.oracle_pool_child:
+        import numpy as np
+        steps, workers, nk = (int(v) for v in args.oracle_pool_child[:3])
+        out = args.oracle_pool_child[3]
+        res = oracle_pool_run(steps, workers, nk)
+        np.savez(out, rho=res["rho"], J=res["J"], seconds=res["seconds"], og=res["og"], workers=res["workers"])
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the multi-GPU sharding of the step is a design "
               "(orbital/k-point split, density all-reduce) and is not built; run with --gpus 1",
@@ -338,6 +481,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     total = args.steps + args.warmup
+    log("main line: diamond-20^3-k512")
     s = synth.single_cell_config(1, nsteps=total)
     og = s.og
     ms, dev_ms, kern, J = time_path(s, args.precision, args.steps, args.warmup)
@@ -350,10 +494,19 @@ def main():
         flops = og * step_flops_per_og(s)
         achieved = flops / (kern["fused_ms"] * 1e-3) / 1e12
         peak = FP32_VALU_PEAK_TFLOPS if args.precision == "mixed" else FP64_VALU_PEAK_TFLOPS
+        traffic = stored_traffic("k_fused.hip", "k_fused", "diamond20_k512") if args.precision == "mixed" else None
+        t_launch = kern["fused_ms"] * 1e-3
         roofline = {"bound": "alu", "kernel": "k_fused (whole step, LDS-resident)",
                     "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                    "traffic": stored_traffic("k_fused.hip", "k_fused", "diamond20_k512"),
+                    "traffic": traffic,
+                    "peak_note": "FP32 vector without packed instructions (256 CU x 4 SIMD x 16 lanes x "
+                                 "2 flop x 2.4 GHz); the library is built without packed FP32"
+                                 if args.precision == "mixed" else "FP64 vector",
+                    "published_fp32_peak_packed": FP32_VALU_PACKED_TFLOPS,
+                    "frac_of_published_packed": achieved / FP32_VALU_PACKED_TFLOPS,
                     "flops_per_launch": flops, "algorithmic_bytes_per_launch": 2 * esz * og,
+                    "hbm_frac_algorithmic": 2 * esz * og / t_launch / 1e9 / HBM_PEAK_GBS,
+                    "hbm_frac_counters": (traffic / t_launch / 1e9 / HBM_PEAK_GBS) if traffic else None,
                     "ms_per_launch": kern["fused_ms"]}
     else:
         # dominant kernel: a middle Horner stage, read u_s, read w, write u_{s-1}
@@ -364,11 +517,6 @@ def main():
                     "frac": achieved / HBM_PEAK_GBS,
                     "traffic": stored_traffic("k_stage.hip", "k_stage", "diamond20_k512"),
                     "bytes_per_launch": stage_bytes, "ms_per_launch": kern["stage_ms"]}
-    # issued MFMA work of one projection launch (per-stage path): one 16x16x4
-    # FP64 MFMA per four sphere entries, per atom and group of eight orbitals
-    n_groups = (s.n_orb * s.n_k + 7) // 8
-    mfma_flops = sum(n_groups * -(-p.npts // 4) * 2 * 16 * 16 * 4 for p in s.projectors)
-    mfma_tflops = mfma_flops / (kern["project_ms"] * 1e-3) / 1e12
 
     out = {
         "metric": METRIC,
@@ -393,28 +541,35 @@ def main():
         "device_ms_per_step": dev_ms,
         "flops_per_og_step": step_flops_per_og(s),
         "kernels_ms": kern,
-        "mfma_projection": {"issued_tflops": mfma_tflops, "peak": FP64_MFMA_PEAK_TFLOPS,
-                            "frac": mfma_tflops / FP64_MFMA_PEAK_TFLOPS},
+        "per_stage_path": per_stage_figures(s, kern, esz),
+        "mfma_projection": mfma_projection(s, kern["project_ms"]),
         "current_finite": bool(np.all(np.isfinite(J))),
     }
     if not args.no_twin:
+        log("complex128 twin")
         other = "c128" if args.precision == "mixed" else "mixed"
         ms2, dev2, kern2, _ = time_path(s, other, args.steps, args.warmup)
         out["twin"] = {"precision": other, "value": og / (ms2 * 1e-3), "ms_per_step": ms2,
                        "kernels_ms": kern2,
                        "stage_GBs": 3 * (16 if other == "c128" else 8) * og / (kern2["stage_ms"] * 1e-3) / 1e9}
     if not args.no_mgga:
+        log("Tran-Blaha line")
         out["mgga"] = bench_mgga(s, args.precision, ms)
     if not args.no_cluster:
+        log("cluster line (96^3, 512 orbitals)")
         out["cluster"] = bench_cluster()
     if not args.no_accuracy:
+        log("accuracy report")
         out["accuracy"] = accuracy_report()
     if not args.no_batch:
+        log("batch line (64 cells)")
         out["batched"] = bench_batch()
     if not args.no_multiscale:
+        log("multiscale line")
         out["multiscale"] = bench_multiscale()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(s)
+        log("cpu baseline (oracle on the host cores)")
+        out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
 
 

@@ -236,6 +236,19 @@ tddft_status tddft_excited_electrons(tddft_ctx *ctx, double *n_ex);
  * of the field there (tddft_work). */
 tddft_status tddft_excitation_energy(tddft_ctx *ctx, double *E_ex);
 
+/* JSON text (NUL-terminated in buf) of how the context runs its step:
+ * {"path": "fused"} for the LDS-resident step, else the per-stage
+ * kernel's decomposition chosen by the tuner at set_potential: "key" (device,
+ * grid, boundary, orbital count, precision), "source" ("tuned", "cache" or
+ * "default" under TDDFT_FLAG_NO_TUNE), "stage" (bc: 0 whole periodic plane,
+ * 1 periodic tiles, 2 isolated tiles; TX x TY tile, zs z slabs, xmap XCD
+ * renumbering, ms per middle stage) and the timed "candidates". The tuner
+ * times every decomposition that fits the grid (all compute identical bits;
+ * the observe pass keeps its own, so the current is unaffected) and keeps the
+ * fastest per key for the process, and in the JSON file named by the
+ * environment variable TDDFT_TUNE_CACHE when set. EINVAL if len is too small. */
+tddft_status tddft_report(tddft_ctx *ctx, char *buf, size_t len);
+
 /* Mean device time per step of the last propagate, from HIP events (ms). */
 tddft_status tddft_last_timing(tddft_ctx *ctx, double *ms_per_step);
 
@@ -327,7 +340,8 @@ tddft_status tddft_conductivity_noalloc(int32_t n_t, const double *I, double dt,
  * items from a device queue, largest cells first; other cells run the
  * per-stage kernels on forked streams inside the same graph. The persistent
  * grid of every group is chosen by timing candidates on the first steps
- * (every candidate computes identical bits), unless
+ * (every candidate computes identical bits), and every per-stage cell's
+ * decomposition by the tuner of tddft_report, unless
  * TDDFT_FLAG_NO_TUNE is set in cfgs[0].flags. Every cell behaves as its own
  * context would alone; the current of a cell is its own. */
 #define TDDFT_FLAG_NO_TUNE 0x10u

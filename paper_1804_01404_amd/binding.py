@@ -49,7 +49,7 @@ EXPORTED = ["tddft_abi_version", "tddft_init", "tddft_set_potential", "tddft_pro
             "tddft_nn_adam_step", "tddft_nn_train", "tddft_nn_last_error", "tddft_nn_free",
             "tddft_ms_create", "tddft_ms_attach_surrogate", "tddft_ms_step", "tddft_ms_status",
             "tddft_ms_last_error", "tddft_ms_free", "tddft_excitation_energy", "tddft_conductivity",
-            "tddft_oscillator_strength", "tddft_work", "tddft_conductivity_noalloc"]
+            "tddft_oscillator_strength", "tddft_work", "tddft_conductivity_noalloc", "tddft_report"]
 KERNEL_STAGE, KERNEL_PROJECT, KERNEL_OBSERVE, KERNEL_DENSITY, KERNEL_FUSED = 0, 1, 2, 3, 4
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -179,6 +179,8 @@ def load_library(path: str = LIB_PATH):
         getattr(lib, name).restype = C.c_int
     # spectra and work (no context)
     lib.tddft_excitation_energy.argtypes = [C.c_void_p, _dp]
+    lib.tddft_report.argtypes = [C.c_void_p, C.c_char_p, C.c_size_t]
+    lib.tddft_report.restype = C.c_int
     lib.tddft_conductivity.argtypes = [C.c_int32, _dp, C.c_double, C.c_double, C.c_int32, _dp, C.c_uint32,
                                        _dp, _dp]
     lib.tddft_oscillator_strength.argtypes = [C.c_int32, _dp, C.c_double, C.c_double, C.c_int32, _dp, _dp]
@@ -359,6 +361,13 @@ class TDDFT:
 
     def kick(self, F0: float, axis: int):
         self._check(self.lib.tddft_kick(self.h, float(F0), int(axis)))
+
+    def report(self) -> dict:
+        """How the step runs: the fused path, or the tuned per-stage decomposition."""
+        import json
+        buf = C.create_string_buffer(1 << 16)
+        self._check(self.lib.tddft_report(self.h, buf, len(buf)))
+        return json.loads(buf.value.decode())
 
     def last_timing_ms(self) -> float:
         ms = C.c_double()

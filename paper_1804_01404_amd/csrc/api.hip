@@ -13,7 +13,12 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -44,8 +49,12 @@ struct tddft_ctx {
   hipStream_t stream = nullptr;
   int device = 0;
 
-  Geometry g{};
+  Geometry g{};               // observe pass and shared sizes
   int bc = kPeriodicPlane;
+  Geometry gs{};              // decomposition of the per-stage kernel (tuned)
+  int sbc = kPeriodicPlane;
+  std::string tune_note;      // JSON of the tuner's choice and measurements
+  std::string tune_choice;    // the same without the candidate list
   size_t N = 0, n_orb_tot = 0;
   bool mixed = false;
   double dV = 0, volume = 0;
@@ -310,7 +319,7 @@ StageArgs<T> stage_args(tddft_ctx* c) {
   a.Eu = c->nl.n_atoms > 0 ? c->Eu : nullptr;
   a.phA = c->phA;
   a.nl = c->nl;
-  a.g = c->g;
+  a.g = c->gs;
   std::memcpy(a.lap, c->lap, sizeof(a.lap));
   std::memcpy(a.dh, c->dh, sizeof(a.dh));
   a.cdiag = c->cdiag;
@@ -471,7 +480,7 @@ tddft_status enqueue_taylor_stages(tddft_ctx* c, double dt, double tau_imag) {
     a.tau = dt / s;  // u_{s-1} = w + (x / s) h u_s
     a.tau_re = -tau_imag / s;
     const int mode = (s == 4) ? kFirst : (s == 1 ? kLast : kMid);
-    LAUNCH(launch_stage<T>(mode, c->bc, a, c->stream), "stage");
+    LAUNCH(launch_stage<T>(mode, c->sbc, a, c->stream), "stage");
     // the nonlocal term of the stage, added over each colour's sphere entries
     for (int cl = 0; cl < c->n_colors && c->nl.n_atoms > 0; ++cl) {
       const int e0 = c->color_ent_start[cl], ne = c->color_ent_start[cl + 1] - e0;
@@ -597,7 +606,7 @@ tddft_status launch_one(tddft_ctx* c, int which) {
     a.w = as2<T>(c->W);
     a.out = as2<T>(c->U1);
     a.tau = c->cfg.dt / 2;
-    LAUNCH(launch_stage<T>(kMid, c->bc, a, c->stream), "stage");
+    LAUNCH(launch_stage<T>(kMid, c->sbc, a, c->stream), "stage");
     for (int cl = 0; cl < c->n_colors && c->nl.n_atoms > 0; ++cl) {
       const int e0 = c->color_ent_start[cl], ne = c->color_ent_start[cl + 1] - e0;
       LAUNCH(launch_nl_addback<T>(a, c->color_ents + e0, ne, (int)c->n_orb_tot, c->stream), "nonlocal add-back");
@@ -637,6 +646,235 @@ tddft_status launch_one(tddft_ctx* c, int which) {
                                  c->rho_part, c->stream),
            "rho_partial");
   }
+  return TDDFT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Tuner of the per-stage kernel's decomposition: xy tile shape (or the whole
+// periodic plane), z slabs and the XCD renumbering. Every candidate computes
+// each output point with the same arithmetic in the same order, so the choice
+// changes no bit of the result; the observe pass keeps its own decomposition,
+// so the reductions of the current do not depend on it either. Each
+// candidate's middle stage is timed on the two stage buffers (scratch
+// between steps); the fastest is kept per (device, grid, boundary, orbital
+// count, precision) in a process-wide table, and in the JSON file named by the
+// environment variable TDDFT_TUNE_CACHE when it is set.
+
+struct StagePlan {
+  int bc, TX, TY, zs, xmap;
+  double ms;
+};
+
+std::mutex g_tune_mu;
+std::map<std::string, StagePlan> g_tune;
+bool g_tune_file_read = false;
+
+// the numbers that follow "name": after position pos (the file is our own)
+bool json_num(const std::string& t, size_t pos, size_t end, const char* name, double* v) {
+  const std::string pat = std::string("\"") + name + "\":";
+  const size_t i = t.find(pat, pos);
+  if (i == std::string::npos || i > end) return false;
+  char* stop = nullptr;
+  *v = std::strtod(t.c_str() + i + pat.size(), &stop);
+  return stop != t.c_str() + i + pat.size();
+}
+
+void tune_file_read_locked() {
+  if (g_tune_file_read) return;
+  g_tune_file_read = true;
+  const char* path = std::getenv("TDDFT_TUNE_CACHE");
+  if (!path || !*path) return;
+  std::ifstream f(path);
+  if (!f) return;
+  std::stringstream ss;
+  ss << f.rdbuf();
+  const std::string t = ss.str();
+  size_t pos = 0;
+  while ((pos = t.find("\"stage/", pos)) != std::string::npos) {
+    const size_t kend = t.find('"', pos + 1);
+    const size_t oend = t.find('}', kend);
+    if (kend == std::string::npos || oend == std::string::npos) break;
+    const std::string key = t.substr(pos + 1, kend - pos - 1);
+    double v[6];
+    const char* names[6] = {"bc", "TX", "TY", "zs", "xmap", "ms"};
+    bool ok = true;
+    for (int i = 0; i < 6 && ok; ++i) ok = json_num(t, kend, oend, names[i], &v[i]);
+    if (ok) g_tune[key] = StagePlan{(int)v[0], (int)v[1], (int)v[2], (int)v[3], (int)v[4], v[5]};
+    pos = oend;
+  }
+}
+
+void tune_file_write_locked() {
+  const char* path = std::getenv("TDDFT_TUNE_CACHE");
+  if (!path || !*path) return;
+  std::string tmp = std::string(path) + ".tmp";
+  std::ofstream f(tmp);
+  if (!f) return;
+  f << "{\n";
+  size_t i = 0;
+  for (const auto& kv : g_tune) {
+    const StagePlan& p = kv.second;
+    char line[512];
+    std::snprintf(line, sizeof line, "  \"%s\": {\"bc\": %d, \"TX\": %d, \"TY\": %d, \"zs\": %d, \"xmap\": %d, \"ms\": %.6f}%s\n",
+                  kv.first.c_str(), p.bc, p.TX, p.TY, p.zs, p.xmap, p.ms, ++i < g_tune.size() ? "," : "");
+    f << line;
+  }
+  f << "}\n";
+  f.close();
+  if (f) std::rename(tmp.c_str(), path);
+}
+
+std::string tune_key(const tddft_ctx* c) {
+  hipDeviceProp_t prop{};
+  std::string arch = "gpu";
+  if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) {
+    arch = prop.gcnArchName;
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch = arch.substr(0, colon);
+  }
+  char buf[160];
+  std::snprintf(buf, sizeof buf, "stage/%s/%dx%dx%d/%s/%zu/%s", arch.c_str(), c->g.n1, c->g.n2, c->g.n3,
+                c->g.periodic ? "periodic" : "isolated", c->n_orb_tot, c->mixed ? "c64" : "c128");
+  return buf;
+}
+
+// a decomposition for (bc, TX, TY, zs, xmap), or false if it does not fit
+bool make_stage_geometry(const tddft_ctx* c, const StagePlan& p, Geometry* out) {
+  Geometry g = c->g;
+  if (p.bc == kPeriodicPlane) {
+    if (!g.periodic || g.n1 * g.n2 > 1024 || p.TX != g.n1 || p.TY != g.n2) return false;
+  } else {
+    if (p.bc != (g.periodic ? kPeriodicTile : kIsolatedTile)) return false;
+    if (p.TX < 4 || p.TY < 4 || g.n1 % p.TX || g.n2 % p.TY || p.TX * p.TY > 1024) return false;
+  }
+  if (p.zs < 1 || p.zs > g.n3) return false;
+  const int zlen = (g.n3 + p.zs - 1) / p.zs;
+  if ((p.zs - 1) * zlen >= g.n3) return false;  // every slab non-empty
+  g.TX = p.TX;
+  g.TY = p.TY;
+  g.tiles_x = g.n1 / p.TX;
+  g.tiles_y = g.n2 / p.TY;
+  g.zslabs = p.zs;
+  g.xmap = p.xmap;
+  *out = g;
+  return true;
+}
+
+std::vector<StagePlan> stage_candidates(const tddft_ctx* c) {
+  const Geometry& g = c->g;
+  std::vector<StagePlan> out;
+  const int tbc = g.periodic ? kPeriodicTile : kIsolatedTile;
+  std::vector<std::pair<int, int>> tiles;
+  if (g.periodic && g.n1 * g.n2 <= 1024) tiles.push_back({-1, -1});  // the whole plane
+  for (int tx : {g.n1, 64, 48, 32, 24, 20, 16, 12, 10, 8})
+    for (int ty : {32, 24, 20, 16, 12, 10, 8, 6, 5, 4}) {
+      if (tx > g.n1 || ty > g.n2 || g.n1 % tx || g.n2 % ty || tx < 4 || ty < 4) continue;
+      if (tx * ty < 128 || tx * ty > 1024) continue;
+      if (std::find(tiles.begin(), tiles.end(), std::make_pair(tx, ty)) == tiles.end()) tiles.push_back({tx, ty});
+    }
+  for (const auto& t : tiles) {
+    const bool plane = t.first < 0;
+    const int tx = plane ? g.n1 : t.first, ty = plane ? g.n2 : t.second;
+    const long per_z = (long)c->n_orb_tot * (g.n1 / tx) * (g.n2 / ty);
+    for (int zs : {1, 2, 4}) {
+      if (zs > 1 && (per_z * zs > 8192 || g.n3 / zs < 8)) continue;  // slabs only for few workgroups
+      for (int xm : {0, 1}) {
+        if (plane && xm) continue;  // no halo shared between the workgroups of a plane
+        StagePlan p{plane ? kPeriodicPlane : tbc, tx, ty, zs, xm, 0.0};
+        Geometry tmp;
+        if (make_stage_geometry(c, p, &tmp)) out.push_back(p);
+      }
+    }
+  }
+  return out;
+}
+
+template <typename T>
+tddft_status time_stage(tddft_ctx* c, const StagePlan& p, int reps, double* ms) {
+  Geometry gs;
+  if (!make_stage_geometry(c, p, &gs)) return fail(c, TDDFT_EINVAL, "bad stage decomposition");
+  StageArgs<T> a = stage_args<T>(c);
+  a.g = gs;
+  a.V = vpot<T>(c);
+  a.in = as2<T>(c->U0);
+  a.w = as2<T>(c->W);
+  a.out = as2<T>(c->U1);
+  a.tau = c->cfg.dt / 2;
+  LAUNCH(launch_stage<T>(kMid, p.bc, a, c->stream), "stage (tuner warm-up)");
+  HIP_TRY(hipEventRecord(c->ev0, c->stream));
+  for (int r = 0; r < reps; ++r) LAUNCH(launch_stage<T>(kMid, p.bc, a, c->stream), "stage (tuner)");
+  HIP_TRY(hipEventRecord(c->ev1, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  float t = 0;
+  HIP_TRY(hipEventElapsedTime(&t, c->ev0, c->ev1));
+  *ms = t / reps;
+  return TDDFT_OK;
+}
+
+std::string plan_json(const StagePlan& p) {
+  char buf[160];
+  std::snprintf(buf, sizeof buf, "{\"bc\": %d, \"TX\": %d, \"TY\": %d, \"zs\": %d, \"xmap\": %d, \"ms\": %.5f}",
+                p.bc, p.TX, p.TY, p.zs, p.xmap, p.ms);
+  return buf;
+}
+
+// choose gs / sbc for the per-stage path (after the potential is set)
+tddft_status tune_stage(tddft_ctx* c) {
+  const std::string key = tune_key(c);
+  StagePlan best{c->bc, c->g.TX, c->g.TY, c->g.zslabs, c->g.xmap, 0.0};
+  std::string source = "default";
+  std::string cands = "[]";
+  if (!(c->cfg.flags & TDDFT_FLAG_NO_TUNE)) {
+    bool cached = false;
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      tune_file_read_locked();
+      auto it = g_tune.find(key);
+      Geometry tmp;
+      if (it != g_tune.end() && make_stage_geometry(c, it->second, &tmp)) {
+        best = it->second;
+        cached = true;
+      }
+    }
+    if (cached) {
+      source = "cache";
+    } else {
+      // coefficient tables of the current A, as for a real step
+      double Ab[6];
+      for (int i = 0; i < 3; ++i) Ab[i] = Ab[3 + i] = c->A_last[i];
+      HIP_TRY(hipMemcpyAsync(c->Aobs, Ab, sizeof(Ab), hipMemcpyHostToDevice, c->stream));
+      LAUNCH(launch_step_params(c->Aobs, c->counter, 0, c->kpt_d, c->cfg.n_k, c->ent_x, c->nl.n_ent, c->cfg.gauge,
+                                c->cfg.dt, c->kappa, c->kappaJ, c->efield, c->phA, c->phAJ, c->Alast, c->stream),
+             "step_params");
+      tddft_status st = enqueue_coef(c);
+      if (st != TDDFT_OK) return st;
+      const std::vector<StagePlan> cand = stage_candidates(c);
+      cands = "[";
+      best.ms = 1e300;
+      for (size_t i = 0; i < cand.size(); ++i) {
+        StagePlan p = cand[i];
+        st = c->mixed ? time_stage<float>(c, p, 3, &p.ms) : time_stage<double>(c, p, 3, &p.ms);
+        if (st != TDDFT_OK) return st;
+        cands += (i ? ", " : "") + plan_json(p);
+        if (p.ms < best.ms) best = p;
+      }
+      cands += "]";
+      source = "tuned";
+      if (cand.empty()) best = StagePlan{c->bc, c->g.TX, c->g.TY, c->g.zslabs, c->g.xmap, 0.0};
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      g_tune[key] = best;
+      tune_file_write_locked();
+    }
+  }
+  Geometry gs;
+  if (!make_stage_geometry(c, best, &gs)) {
+    gs = c->g;
+    best = StagePlan{c->bc, c->g.TX, c->g.TY, c->g.zslabs, c->g.xmap, 0.0};
+  }
+  c->gs = gs;
+  c->sbc = best.bc;
+  c->tune_choice = "{\"key\": \"" + key + "\", \"source\": \"" + source + "\", \"stage\": " + plan_json(best) + "}";
+  c->tune_note = c->tune_choice.substr(0, c->tune_choice.size() - 1) + ", \"candidates\": " + cands + "}";
   return TDDFT_OK;
 }
 
@@ -845,12 +1083,16 @@ tddft_status tddft_init(const tddft_config* cfg, const double* psi0, tddft_ctx**
   }
   g.tiles_x = g.n1 / g.TX;
   g.tiles_y = g.n2 / g.TY;
+  // tiles of one orbital on one XCD share their halo rows in its L2
+  g.xmap = c->bc == kPeriodicPlane ? 0 : 1;
   // per-stage kernels of cells with few orbitals: split z into slabs of at
   // least 8 planes until there are about a thousand workgroups
   g.zslabs = 1;
   while (g.zslabs < 8 && (long)c->n_orb_tot * g.tiles_x * g.tiles_y * g.zslabs < 1024 &&
          g.n3 / (2 * g.zslabs) >= 8)
     g.zslabs *= 2;
+  c->gs = g;  // the per-stage kernel starts from the same decomposition
+  c->sbc = c->bc;
   const double h[3] = {g.h1, g.h2, g.h3};
   c->cdiag = 0;
   for (int mu = 0; mu < 3; ++mu) {
@@ -1173,6 +1415,12 @@ tddft_status tddft_set_potential(tddft_ctx* c, const double* v_loc, int32_t n_at
   c->potential_set = true;
   st = potential_dispatch(c);
   if (st != TDDFT_OK) return st;
+  if (!c->fused) {
+    st = tune_stage(c);
+    if (st != TDDFT_OK) return st;
+  } else {
+    c->tune_note = "{\"path\": \"fused\"}";
+  }
   HIP_TRY(hipStreamSynchronize(c->stream));
   return TDDFT_OK;
 }
@@ -1452,6 +1700,13 @@ tddft_status tddft_excited_electrons(tddft_ctx* c, double* n_ex) {
   for (int k = 0; k < nk; ++k) total += c->kw[k] * 2.0 * ((double)n - S[k]);
   *n_ex = total / c->volume;
   return TDDFT_OK;
+}
+
+tddft_status tddft_report(tddft_ctx* c, char* buf, size_t len) {
+  if (!c || !buf || len == 0) return c ? fail(c, TDDFT_EINVAL, "null buffer") : TDDFT_EINVAL;
+  const std::string r = c->tune_note.empty() ? std::string("{}") : c->tune_note;
+  std::snprintf(buf, len, "%s", r.c_str());
+  return r.size() < len ? TDDFT_OK : fail(c, TDDFT_EINVAL, "report buffer too small");
 }
 
 tddft_status tddft_last_timing(tddft_ctx* c, double* ms) {
@@ -1847,7 +2102,21 @@ tddft_status tddft_batch_report(tddft_batch* b, char* buf, size_t len) {
       r += (first ? "" : ", ") + std::to_string(i);
       first = false;
     }
-  r += "]}";
+  // the per-stage decomposition chosen for each cell shape
+  r += "], \"per_stage_tiles\": {";
+  std::vector<std::string> seen;
+  for (const auto& lane : b->lanes)
+    for (int i : lane) {
+      const tddft_ctx* c = b->cells[i];
+      const size_t k0 = c->tune_choice.find("\"key\": \"");
+      if (k0 == std::string::npos) continue;
+      const size_t k1 = c->tune_choice.find('"', k0 + 8);
+      const std::string key = c->tune_choice.substr(k0 + 8, k1 - k0 - 8);
+      if (std::find(seen.begin(), seen.end(), key) != seen.end()) continue;
+      seen.push_back(key);
+      r += (seen.size() > 1 ? ", \"" : "\"") + key + "\": " + c->tune_choice;
+    }
+  r += "}}";
   std::snprintf(buf, len, "%s", r.c_str());
   return r.size() < len ? TDDFT_OK : TDDFT_EINVAL;
 }

@@ -47,7 +47,20 @@ struct Geometry {
   // there are too few (orbital, tile) workgroups to fill the chip
   int TX, TY, tiles_x, tiles_y;
   int zslabs;
+  // 1: renumber workgroups so that each XCD (each with its own L2) gets a
+  // contiguous range of (orbital, tile, slab) blocks; the result does not
+  // depend on it
+  int xmap;
 };
+
+// Workgroups are dealt to the eight XCDs in turn (XCD = id mod 8). With
+// q = n / 8, the first 8 q ids are renumbered so that XCD x runs the logical
+// blocks x q .. x q + q - 1 in order; the tail keeps its id (a bijection).
+__device__ __forceinline__ int xcd_block(int b, int n) {
+  const int q = n >> 3;
+  if (b >= 8 * q) return b;
+  return (b & 7) * q + (b >> 3);
+}
 
 template <typename T> struct Vec2;
 template <> struct Vec2<double> { using type = double2; };

@@ -48,8 +48,9 @@ __global__ __launch_bounds__(1024) void k_stage(StageArgs<T> a) {
   const size_t N = (size_t)plane * n3;
   const int ntiles = g.tiles_x * g.tiles_y;
   const int nz = g.zslabs;
-  const int o = blockIdx.x / (ntiles * nz);
-  const int rem = blockIdx.x - o * ntiles * nz;
+  const int bid = g.xmap ? xcd_block((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
+  const int o = bid / (ntiles * nz);
+  const int rem = bid - o * ntiles * nz;
   const int tile = rem / nz;
   const int slab = rem - tile * nz;
   // planes z0 .. z1 - 1 of the column (the whole column unless split)
@@ -324,8 +325,9 @@ __global__ __launch_bounds__(1024) void k_observe(ObserveArgs<T> a) {
   const size_t N = (size_t)plane * n3;
   const int ntiles = g.tiles_x * g.tiles_y;
   const int nz = g.zslabs;
-  const int o = blockIdx.x / (ntiles * nz);
-  const int rem = blockIdx.x - o * ntiles * nz;
+  const int bid = g.xmap ? xcd_block((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
+  const int o = bid / (ntiles * nz);
+  const int rem = bid - o * ntiles * nz;
   const int tile = rem / nz;
   const int slab = rem - tile * nz;
   // planes z0 .. z1 - 1 of the column (the whole column unless split)

@@ -19,9 +19,11 @@ sphere of radius ``r_c``.
 from __future__ import annotations
 
 import dataclasses
+import os
 from typing import List, Optional, Sequence
 
 import numpy as np
+import scipy.fft as sfft
 
 C_AU = 137.035999084  # speed of light in atomic units
 
@@ -231,7 +233,9 @@ def _orthonormalise(W: np.ndarray, dV: float) -> np.ndarray:
         S = dV * (W @ W.conj().T)
         S = 0.5 * (S + S.conj().T)
         L = np.linalg.cholesky(S)
-        W = sla.solve_triangular(L, W, lower=True)
+        # L^-1 W as a product with the small inverse (one threaded GEMM)
+        Linv = sla.solve_triangular(L, np.eye(L.shape[0], dtype=L.dtype), lower=True)
+        W = Linv @ W
     return W
 
 
@@ -244,10 +248,16 @@ def random_orbitals(n, cell, boundary, kpts, n_orb, rng, ecut: float = 4.0,
     the same filter on the box, times a sin^2 window vanishing at the walls.
     Gamma-only periodic and isolated sets are real-valued when ``real_gamma``.
     """
+    from concurrent.futures import ThreadPoolExecutor
+    from threadpoolctl import threadpool_limits
     h = [cell[i] / n[i] for i in range(3)]
     dV = h[0] * h[1] * h[2]
     gs = [2 * np.pi * np.fft.fftfreq(n[i], d=1.0 / n[i]) / cell[i] for i in range(3)]
     out = np.empty((kpts.shape[0], n_orb, n[2], n[1], n[0]), dtype=np.complex128)
+    ncpu = os.cpu_count() or 1
+    # the random coefficients are drawn k-point by k-point in order; the
+    # transforms and orthonormalisations of the k-points then run side by side
+    draws = []
     for ik, k in enumerate(kpts):
         ec = ecut
         while True:
@@ -258,15 +268,20 @@ def random_orbitals(n, cell, boundary, kpts, n_orb, rng, ecut: float = 4.0,
                 break
             ec *= 1.5
         real = real_gamma and (boundary == "isolated" or not np.any(k))
-        W = np.empty((n_orb, n[2], n[1], n[0]), dtype=np.complex128)
+        # coefficients drawn orbital by orbital (real parts, then imaginary
+        # parts), then one batched inverse FFT on all host cores
+        W = np.zeros((n_orb, n[2], n[1], n[0]), dtype=np.complex128)
+        m = int(mask.sum())
         for j in range(n_orb):
-            c = np.zeros((n[2], n[1], n[0]), dtype=np.complex128)
-            m = int(mask.sum())
-            c[mask] = rng.normal(size=m) + 1j * rng.normal(size=m)
-            f = np.fft.ifftn(c)
-            if real:
-                f = f.real.astype(np.complex128)
-            W[j] = f
+            W[j][mask] = rng.normal(size=m) + 1j * rng.normal(size=m)
+        draws.append([W, real])
+
+    def finish(ik, workers):
+        W, real = draws[ik]
+        draws[ik] = None
+        W = sfft.ifftn(W, axes=(1, 2, 3), overwrite_x=True, workers=workers)
+        if real:
+            W = W.real.astype(np.complex128)
         if boundary == "isolated":
             win = [np.sin(np.pi * (np.arange(N) + 1) / (N + 1)) ** 2 for N in n]
             W *= win[2][:, None, None] * win[1][None, :, None] * win[0][None, None, :]
@@ -274,6 +289,13 @@ def random_orbitals(n, cell, boundary, kpts, n_orb, rng, ecut: float = 4.0,
         if real:
             W = W.real.astype(np.complex128)
         out[ik] = W
+
+    if len(draws) > 1 and ncpu > 1:
+        with threadpool_limits(limits=1), ThreadPoolExecutor(max_workers=min(ncpu, len(draws))) as ex:
+            list(ex.map(lambda ik: finish(ik, 1), range(len(draws))))
+    else:
+        for ik in range(len(draws)):
+            finish(ik, ncpu)
     return out
 
 
