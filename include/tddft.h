@@ -416,6 +416,27 @@ tddft_status tddft_nn_adam_step(tddft_nn *nn);
  * loss. */
 tddft_status tddft_nn_train(tddft_nn *nn, int32_t n_traj, int32_t T, const double *A, const double *J,
                             int32_t epochs, int32_t batch, uint64_t seed, float *loss_per_epoch);
+/* Training options of tddft_nn_train_ex. */
+#define TDDFT_NN_COSINE_LR 0x1u      /* lr of epoch e: lr (1 + cos(pi e / epochs)) / 2 */
+#define TDDFT_NN_FREEZE_LINEAR 0x2u  /* keep b3 and ws fixed (their gradient is zeroed) */
+/* tddft_nn_train with options (flags 0 is tddft_nn_train). */
+tddft_status tddft_nn_train_ex(tddft_nn *nn, int32_t n_traj, int32_t T, const double *A, const double *J,
+                               int32_t epochs, int32_t batch, uint64_t seed, uint32_t flags,
+                               float *loss_per_epoch);
+/* Set the linear part of the network to the least-squares linear response:
+ * ws and b3 minimise sum (ws . x + b3 - y)^2 + lambda |(ws, b3)|^2 over every
+ * (trajectory, t) sample of the trajectories (A, J as in tddft_nn_train)
+ * whose largest |A| is within a_fit, with lambda = lambda_rel times the mean
+ * diagonal of the normal matrix; the normal equations are formed and solved
+ * (Cholesky) in FP64 on the device. w3 is set to 0, so the network equals the
+ * fit until trained further (the weak-field response is then carried by the
+ * skip and the hidden layers learn what is left); Adam's state is reset.
+ * Within a window the linear response of the cells to A is exact in the
+ * weak-field limit (Sec. 5 couples the cells through A alone). Errors:
+ * EINVAL (fewer than W + 1 samples within a_fit, bad arguments), ENUMERIC
+ * (normal matrix not positive definite), ENOMEM, EDEVICE. */
+tddft_status tddft_nn_fit_linear(tddft_nn *nn, int32_t n_traj, int32_t T, const double *A, const double *J,
+                                 double a_fit, double lambda_rel);
 const char *tddft_nn_last_error(const tddft_nn *nn);
 void tddft_nn_free(tddft_nn *nn);
 
@@ -464,6 +485,17 @@ tddft_status tddft_ms_step(tddft_ms *ms, int32_t n_macro, const double *inc, dou
 /* mode: 0 cells, 1 network; fallbacks taken; the last sentinel error; steps done. */
 tddft_status tddft_ms_status(tddft_ms *ms, int32_t *mode, int32_t *fallbacks, double *last_check,
                              int32_t *steps_done);
+/* Energy monitor (Sec. 5: the total energy is that of the electromagnetic
+ * field and of the electronic excitations; its conservation checks the run),
+ * per unit area of the slab (Ha / bohr^2), at the current step:
+ * em = (1/8 pi) [sum_j E_j^2 + sum_j B_{j+1/2}^2] dX with E = -(A^n - A^{n-1})/(c dt)
+ * and B = (A_{j+1} - A_j)/dX; work = the energy the field has given the medium
+ * since t = 0, W = sum_steps dt dX sum_medium (I^n + I^{n+1})/2 E^{n+1/2} (the
+ * work route to the excitation energy of Sec. 4.1; dE/dt = +I . E per volume).
+ * em + work changes only by the flux through the ends of the grid. Either
+ * pointer may be NULL. After a fallback the work is recomputed from the cells'
+ * currents. */
+tddft_status tddft_ms_energy(tddft_ms *ms, double *em, double *work);
 const char *tddft_ms_last_error(const tddft_ms *ms);
 void tddft_ms_free(tddft_ms *ms);
 

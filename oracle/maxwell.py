@@ -71,6 +71,18 @@ def em_energy(A_now, A_prev, dx, dt):
     return (np.sum(E * E) + np.sum(B * B)) * dx / (8.0 * math.pi)
 
 
+def medium_work(A_hist, I_hist, dx, dt):
+    """Work of the field on the medium per unit area after each step:
+    W_n = sum_{s<n} dt dX sum_m (I_m^s + I_m^{s+1})/2 E_m^{s+1/2}, with
+    E^{s+1/2} = -(A^{s+1} - A^s)/(c dt); A_hist, I_hist [(n + 1)][n_mat] at
+    the medium points from t_0 (I^0 = 0). Returns W [n + 1] (W_0 = 0)."""
+    A = np.asarray(A_hist, dtype=np.float64)
+    I = np.asarray(I_hist, dtype=np.float64)
+    E = -(A[1:] - A[:-1]) / (C_LIGHT * dt)
+    inc = dt * dx * np.sum(0.5 * (I[:-1] + I[1:]) * E, axis=1)
+    return np.concatenate([[0.0], np.cumsum(inc)])
+
+
 class Multiscale:
     """Coupled Maxwell + microscopic cells (Sec. 5). ``cells`` are objects with
     ``propagate(A_table) -> J`` (the oracle's TDKS); the material occupies the

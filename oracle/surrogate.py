@@ -111,3 +111,21 @@ def windows(A, J, W, a_scale=1.0, j_scale=1.0):
             X[i * T + t, W - seg.shape[0]:] = seg / a_scale
             Y[i * T + t] = J[i, t] / j_scale
     return X, Y
+
+
+def fit_linear(A, J, W, a_scale, j_scale, a_fit, lambda_rel=1e-10):
+    """Least-squares linear response for the skip weights and the output bias:
+    minimise sum (ws . x + b3 - y)^2 + lambda |(ws, b3)|^2 over every sample
+    (causal window x, scaled target y) of the trajectories whose largest |A|
+    is within a_fit, lambda = lambda_rel times the mean diagonal of the normal
+    matrix. Returns (ws, b3)."""
+    A = np.asarray(A, dtype=np.float64)
+    J = np.asarray(J, dtype=np.float64)
+    keep = np.max(np.abs(A), axis=1) <= a_fit
+    X, Y = windows(A[keep], J[keep], W, a_scale, j_scale)
+    Xb = np.hstack([X, np.ones((X.shape[0], 1))])
+    G = Xb.T @ Xb
+    G = G + lambda_rel * np.trace(G) / G.shape[0] * np.eye(G.shape[0])
+    sol = np.linalg.solve(G, Xb.T @ Y)
+    return sol[:-1], float(sol[-1])
+

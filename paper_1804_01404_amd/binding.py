@@ -49,7 +49,8 @@ EXPORTED = ["tddft_abi_version", "tddft_init", "tddft_set_potential", "tddft_pro
             "tddft_nn_adam_step", "tddft_nn_train", "tddft_nn_last_error", "tddft_nn_free",
             "tddft_ms_create", "tddft_ms_attach_surrogate", "tddft_ms_step", "tddft_ms_status",
             "tddft_ms_last_error", "tddft_ms_free", "tddft_excitation_energy", "tddft_conductivity",
-            "tddft_oscillator_strength", "tddft_work", "tddft_conductivity_noalloc", "tddft_report"]
+            "tddft_oscillator_strength", "tddft_work", "tddft_conductivity_noalloc", "tddft_report",
+            "tddft_nn_train_ex", "tddft_nn_fit_linear", "tddft_ms_energy"]
 KERNEL_STAGE, KERNEL_PROJECT, KERNEL_OBSERVE, KERNEL_DENSITY, KERNEL_FUSED = 0, 1, 2, 3, 4
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -158,6 +159,11 @@ def load_library(path: str = LIB_PATH):
     lib.tddft_nn_adam_step.argtypes = [C.c_void_p]
     lib.tddft_nn_train.argtypes = [C.c_void_p, C.c_int32, C.c_int32, _dp, _dp, C.c_int32, C.c_int32,
                                    C.c_uint64, _fp]
+    lib.tddft_nn_train_ex.argtypes = [C.c_void_p, C.c_int32, C.c_int32, _dp, _dp, C.c_int32, C.c_int32,
+                                      C.c_uint64, C.c_uint32, _fp]
+    lib.tddft_nn_train_ex.restype = C.c_int
+    lib.tddft_nn_fit_linear.argtypes = [C.c_void_p, C.c_int32, C.c_int32, _dp, _dp, C.c_double, C.c_double]
+    lib.tddft_nn_fit_linear.restype = C.c_int
     lib.tddft_nn_last_error.argtypes = [C.c_void_p]
     lib.tddft_nn_last_error.restype = C.c_char_p
     lib.tddft_nn_free.argtypes = [C.c_void_p]
@@ -169,6 +175,8 @@ def load_library(path: str = LIB_PATH):
     lib.tddft_ms_step.argtypes = [C.c_void_p, C.c_int32, _dp, _dp, _dp]
     lib.tddft_ms_status.argtypes = [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                     C.POINTER(C.c_double), C.POINTER(C.c_int32)]
+    lib.tddft_ms_energy.argtypes = [C.c_void_p, _dp, _dp]
+    lib.tddft_ms_energy.restype = C.c_int
     lib.tddft_ms_last_error.argtypes = [C.c_void_p]
     lib.tddft_ms_last_error.restype = C.c_char_p
     lib.tddft_ms_free.argtypes = [C.c_void_p]
@@ -337,11 +345,13 @@ class TDDFT:
         self._check(self.lib.tddft_dipole(self.h, _ptr(d)))
         return d
 
-    def ground_state(self, n_iter: int, tau: float) -> np.ndarray:
-        """Imaginary-time preparation of the initial state; energy per iteration."""
+    def ground_state(self, n_iter: int, tau: float, energies: bool = True) -> np.ndarray:
+        """Imaginary-time preparation of the initial state; energy per
+        iteration (or, with energies=False, none: no host round trip per
+        iteration)."""
         E = np.empty(max(int(n_iter), 1))
-        self._check(self.lib.tddft_ground_state(self.h, int(n_iter), float(tau), _ptr(E)))
-        return E[: int(n_iter)]
+        self._check(self.lib.tddft_ground_state(self.h, int(n_iter), float(tau), _ptr(E) if energies else None))
+        return E[: int(n_iter)] if energies else np.empty(0)
 
     def set_reference(self):
         """Keep the current orbitals as the reference of excited_electrons."""
@@ -400,6 +410,7 @@ class TDDFT:
 
 
 SPECTRUM_NO_MASK, SPECTRUM_SUBTRACT_MEAN = 1, 2
+NN_COSINE_LR, NN_FREEZE_LINEAR = 1, 2
 
 
 def _stateless_check(lib, st):
@@ -664,14 +675,24 @@ class Surrogate:
     def adam_step(self):
         self._check(self.lib.tddft_nn_adam_step(self.h))
 
-    def train(self, A, J, *, epochs, batch, seed=0):
+    def train(self, A, J, *, epochs, batch, seed=0, cosine=False, freeze_linear=False):
         A = np.ascontiguousarray(A, dtype=np.float64)
         J = np.ascontiguousarray(J, dtype=np.float64)
         assert A.shape == J.shape and A.ndim == 2
         losses = np.zeros(max(int(epochs), 1), dtype=np.float32)
-        self._check(self.lib.tddft_nn_train(self.h, A.shape[0], A.shape[1], _ptr(A), _ptr(J), int(epochs),
-                                            int(batch), int(seed), _fptr(losses)))
+        flags = (NN_COSINE_LR if cosine else 0) | (NN_FREEZE_LINEAR if freeze_linear else 0)
+        self._check(self.lib.tddft_nn_train_ex(self.h, A.shape[0], A.shape[1], _ptr(A), _ptr(J), int(epochs),
+                                               int(batch), int(seed), flags, _fptr(losses)))
         return losses[: int(epochs)]
+
+    def fit_linear(self, A, J, *, a_fit, lambda_rel=1e-10):
+        """Least-squares skip weights and output bias on the trajectories
+        whose largest |A| is within a_fit (device FP64); w3 := 0."""
+        A = np.ascontiguousarray(A, dtype=np.float64)
+        J = np.ascontiguousarray(J, dtype=np.float64)
+        assert A.shape == J.shape and A.ndim == 2
+        self._check(self.lib.tddft_nn_fit_linear(self.h, A.shape[0], A.shape[1], _ptr(A), _ptr(J), float(a_fit),
+                                                 float(lambda_rel)))
 
     def close(self):
         if getattr(self, "h", None):
@@ -733,6 +754,12 @@ class Multiscale:
             incp = _ptr(inc)
         self._check(self.lib.tddft_ms_step(self.h, int(n_macro), incp, _ptr(A), _ptr(I)))
         return A, I
+
+    def energy(self):
+        """(field energy, work on the medium) per unit area at the current step."""
+        em, w = C.c_double(), C.c_double()
+        self._check(self.lib.tddft_ms_energy(self.h, C.byref(em), C.byref(w)))
+        return em.value, w.value
 
     def status(self) -> dict:
         mode, fb, steps = C.c_int32(), C.c_int32(), C.c_int32()

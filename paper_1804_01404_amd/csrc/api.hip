@@ -95,6 +95,7 @@ struct tddft_ctx {
   double* coef = nullptr;  // [n_k][kCoef] in the stage precision (fused step)
   double2* phkA = nullptr;  // [n_k][S] combined projector phases of the step (fused step)
   double2* gram = nullptr;  // [2][n_k][n_orb][n_orb] overlap and its inverse factor (ground state)
+  int* chol_bad = nullptr;  // set by the device Cholesky when a pivot is not positive
   void* Wsave = nullptr;    // predictor-corrector: the orbitals at t_n
   void* Wref = nullptr;     // reference (ground-state) orbitals for the excited-pair count
   double* Sk = nullptr;     // [n_k] occupied weight kept in the reference space
@@ -922,57 +923,14 @@ tddft_status collect_propagate(tddft_ctx* c, int32_t nsteps, const double* A, do
   return TDDFT_OK;
 }
 
-// Cholesky S = L L^H of a Hermitian positive matrix, returns M = L^{-1}
-bool chol_inverse(const std::vector<double2>& S, int n, std::vector<double2>& M) {
-  std::vector<double> Lr(n * n, 0.0), Li(n * n, 0.0);
-  for (int j = 0; j < n; ++j) {
-    double d = S[j * n + j].x;
-    for (int k = 0; k < j; ++k) d -= Lr[j * n + k] * Lr[j * n + k] + Li[j * n + k] * Li[j * n + k];
-    if (!(d > 0.0)) return false;
-    const double ljj = std::sqrt(d);
-    Lr[j * n + j] = ljj;
-    for (int i = j + 1; i < n; ++i) {
-      double ar = S[i * n + j].x, ai = S[i * n + j].y;
-      for (int k = 0; k < j; ++k) {  // - L[i][k] conj(L[j][k])
-        ar -= Lr[i * n + k] * Lr[j * n + k] + Li[i * n + k] * Li[j * n + k];
-        ai -= Li[i * n + k] * Lr[j * n + k] - Lr[i * n + k] * Li[j * n + k];
-      }
-      Lr[i * n + j] = ar / ljj;
-      Li[i * n + j] = ai / ljj;
-    }
-  }
-  // forward substitution: L M = I, M lower
-  M.assign(n * n, make_double2(0.0, 0.0));
-  for (int c = 0; c < n; ++c) {
-    for (int i = c; i < n; ++i) {
-      double br = (i == c) ? 1.0 : 0.0, bi = 0.0;
-      for (int k = c; k < i; ++k) {
-        const double2 m = M[k * n + c];
-        br -= Lr[i * n + k] * m.x - Li[i * n + k] * m.y;
-        bi -= Lr[i * n + k] * m.y + Li[i * n + k] * m.x;
-      }
-      M[i * n + c] = make_double2(br / Lr[i * n + i], bi / Lr[i * n + i]);
-    }
-  }
-  return true;
-}
-
 template <typename T>
 tddft_status orthonormalise(tddft_ctx* c) {
   const int n = c->cfg.n_orb, nk = c->cfg.n_k, N = (int)c->N;
   double2* dS = c->gram;
   double2* dM = dS + (size_t)nk * n * n;
-  std::vector<double2> S((size_t)nk * n * n), M((size_t)nk * n * n), Mk;
   for (int pass = 0; pass < 2; ++pass) {
     LAUNCH(launch_gram<T>(as2<T>(c->W), n, nk, N, c->dV, dS, c->stream), "gram");
-    HIP_TRY(hipMemcpyAsync(S.data(), dS, S.size() * sizeof(double2), hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    for (int k = 0; k < nk; ++k) {
-      std::vector<double2> Sk(S.begin() + (size_t)k * n * n, S.begin() + (size_t)(k + 1) * n * n);
-      if (!chol_inverse(Sk, n, Mk)) return fail(c, TDDFT_ENUMERIC, "orbitals became linearly dependent");
-      std::copy(Mk.begin(), Mk.end(), M.begin() + (size_t)k * n * n);
-    }
-    HIP_TRY(hipMemcpyAsync(dM, M.data(), M.size() * sizeof(double2), hipMemcpyHostToDevice, c->stream));
+    LAUNCH(launch_chol_inverse(dS, dM, n, nk, c->chol_bad, c->stream), "cholesky inverse");
     LAUNCH(launch_apply_lower<T>(as2<T>(c->W), dM, n, nk, N, as2<T>(c->U0), c->stream), "apply L^-1");
     HIP_TRY(hipMemcpyAsync(c->W, c->U0, c->n_orb_tot * c->N * sizeof(typename Vec2<T>::type),
                            hipMemcpyDeviceToDevice, c->stream));
@@ -1621,7 +1579,9 @@ tddft_status tddft_ground_state(tddft_ctx* c, int32_t n_iter, double tau, double
   if (!c->gram) {
     tddft_status st = dalloc_t(c, (size_t)2 * c->cfg.n_k * n * n, &c->gram);
     if (st != TDDFT_OK) return st;
+    if ((st = dalloc_t(c, 1, &c->chol_bad)) != TDDFT_OK) return st;
   }
+  LAUNCH(launch_set_int(c->chol_bad, 0, c->stream), "flag reset");
   invalidate_graph(c);
   for (int i = 0; i < 3; ++i) c->A_last[i] = 0.0;
   double Ab[6] = {0, 0, 0, 0, 0, 0};
@@ -1641,7 +1601,10 @@ tddft_status tddft_ground_state(tddft_ctx* c, int32_t n_iter, double tau, double
     }
   }
   HIP_TRY(hipMemcpyAsync(c->rho0, c->rho, c->N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  int bad = 0;
+  HIP_TRY(hipMemcpyAsync(&bad, c->chol_bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
+  if (bad) return fail(c, TDDFT_ENUMERIC, "orbitals became linearly dependent");
   return TDDFT_OK;
 }
 

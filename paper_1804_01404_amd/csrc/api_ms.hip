@@ -76,12 +76,12 @@ tddft_status nn_reserve(tddft_nn* n, int B) {
   return TDDFT_OK;
 }
 
-tddft_status nn_adam_now(tddft_nn* n) {
+tddft_status nn_adam_now(tddft_nn* n, float lr = -1.0f) {
   n->t_adam += 1;
   const double c1 = 1.0 - std::pow((double)n->cfg.beta1, n->t_adam);
   const double c2 = 1.0 - std::pow((double)n->cfg.beta2, n->t_adam);
-  NHIP(nn_adam(n->theta, n->m, n->v, n->grad, n->np, n->cfg.lr, n->cfg.beta1, n->cfg.beta2, n->cfg.eps, (float)c1,
-               (float)c2, n->stream));
+  NHIP(nn_adam(n->theta, n->m, n->v, n->grad, n->np, lr > 0.0f ? lr : n->cfg.lr, n->cfg.beta1, n->cfg.beta2,
+               n->cfg.eps, (float)c1, (float)c2, n->stream));
   return TDDFT_OK;
 }
 
@@ -178,7 +178,71 @@ tddft_status tddft_nn_adam_step(tddft_nn* n) {
 
 tddft_status tddft_nn_train(tddft_nn* n, int32_t n_traj, int32_t T, const double* A, const double* J,
                             int32_t epochs, int32_t batch, uint64_t seed, float* loss_per_epoch) {
-  if (!n || !A || !J || n_traj < 1 || T < 1 || epochs < 0 || batch < 1)
+  return tddft_nn_train_ex(n, n_traj, T, A, J, epochs, batch, seed, 0u, loss_per_epoch);
+}
+
+tddft_status tddft_nn_fit_linear(tddft_nn* n, int32_t n_traj, int32_t T, const double* A, const double* J,
+                                 double a_fit, double lambda_rel) {
+  if (!n || !A || !J || n_traj < 1 || T < 1 || !(a_fit > 0.0) || !(lambda_rel >= 0.0) || !std::isfinite(lambda_rel))
+    return n ? nn_fail(n, TDDFT_EINVAL, "bad fit_linear arguments") : TDDFT_EINVAL;
+  const int W = n->sh.W, H = n->sh.H;
+  // trajectories whose largest |A| is within a_fit, scaled as the network sees them
+  std::vector<double> hA, hY;
+  int used = 0;
+  for (int k = 0; k < n_traj; ++k) {
+    double amax = 0.0;
+    for (int t = 0; t < T; ++t) {
+      const double a = A[(size_t)k * T + t], j = J[(size_t)k * T + t];
+      if (!std::isfinite(a) || !std::isfinite(j)) return nn_fail(n, TDDFT_EINVAL, "trajectories not finite");
+      amax = std::max(amax, std::fabs(a));
+    }
+    if (amax > a_fit) continue;
+    for (int t = 0; t < T; ++t) {
+      hA.push_back(A[(size_t)k * T + t] / n->cfg.a_scale);
+      hY.push_back(J[(size_t)k * T + t] / n->cfg.j_scale);
+    }
+    ++used;
+  }
+  if ((long)used * T < W + 1) return nn_fail(n, TDDFT_EINVAL, "too few samples within a_fit for the linear fit");
+  const int nn1 = W + 1;
+  double *dA = nullptr, *dY = nullptr, *dG = nullptr, *db = nullptr;
+  int* dok = nullptr;
+  auto cleanup = [&](tddft_status st) {
+    for (double* p : {dA, dY, dG, db})
+      if (p) (void)hipFree(p);
+    if (dok) (void)hipFree(dok);
+    return st;
+  };
+  if (nalloc(&dA, hA.size()) || nalloc(&dY, hY.size()) || nalloc(&dG, (size_t)nn1 * nn1) || nalloc(&db, nn1) ||
+      nalloc(&dok, 1))
+    return cleanup(nn_fail(n, TDDFT_ENOMEM, "device allocation failed (linear fit)"));
+#define FHIP(expr)                                                                                       do {                                                                                                     hipError_t e_ = (expr);                                                                                if (e_ != hipSuccess) return cleanup(nn_fail(n, TDDFT_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)));   } while (0)
+  FHIP(hipMemcpyAsync(dA, hA.data(), hA.size() * sizeof(double), hipMemcpyHostToDevice, n->stream));
+  FHIP(hipMemcpyAsync(dY, hY.data(), hY.size() * sizeof(double), hipMemcpyHostToDevice, n->stream));
+  // layout: ... w3 [H] at offset H W + H + H H + H, b3 right after, ws last
+  const long off_w3 = (long)H * W + H + (long)H * H + H;
+  float* w3 = n->theta + off_w3;
+  float* b3 = w3 + H;
+  float* ws = b3 + 1;
+  FHIP(nn_fit_linear(dA, dY, used, T, W, lambda_rel, dG, db, ws, b3, dok, n->stream));
+  // the hidden layers start from zero output weight: the network is the fit
+  FHIP(nn_zero(w3, H, n->stream));
+  FHIP(nn_zero(n->m, n->np, n->stream));
+  FHIP(nn_zero(n->v, n->np, n->stream));
+  int ok = 0;
+  FHIP(hipMemcpyAsync(&ok, dok, sizeof(int), hipMemcpyDeviceToHost, n->stream));
+  FHIP(hipStreamSynchronize(n->stream));
+#undef FHIP
+  n->t_adam = 0;
+  n->has_grad = false;
+  if (!ok) return cleanup(nn_fail(n, TDDFT_ENUMERIC, "linear fit: the normal equations are not positive definite"));
+  return cleanup(TDDFT_OK);
+}
+
+tddft_status tddft_nn_train_ex(tddft_nn* n, int32_t n_traj, int32_t T, const double* A, const double* J,
+                               int32_t epochs, int32_t batch, uint64_t seed, uint32_t flags, float* loss_per_epoch) {
+  if (!n || !A || !J || n_traj < 1 || T < 1 || epochs < 0 || batch < 1 ||
+      (flags & ~(uint32_t)(TDDFT_NN_COSINE_LR | TDDFT_NN_FREEZE_LINEAR)))
     return n ? nn_fail(n, TDDFT_EINVAL, "bad train arguments") : TDDFT_EINVAL;
   const long S = (long)n_traj * T;
   if (S > (1L << 30)) return nn_fail(n, TDDFT_EINVAL, "too many samples");
@@ -226,7 +290,12 @@ tddft_status tddft_nn_train(tddft_nn* n, int32_t n_traj, int32_t T, const double
       THIP(nn_forward(n->sh, n->theta, n->X, b, n->wk, n->stream));
       THIP(nn_backward(n->sh, n->theta, n->X, n->target, b, n->wk, n->grad, n->stream));
       THIP(nn_accumulate(n->wk.loss, dloss + ep, n->stream));
-      st = nn_adam_now(n);
+      if (flags & TDDFT_NN_FREEZE_LINEAR)  // b3 and ws are the last W + 1 parameters
+        THIP(nn_zero(n->grad + n->np - (n->sh.W + 1), n->sh.W + 1, n->stream));
+      const float lr = (flags & TDDFT_NN_COSINE_LR)
+                           ? (float)(0.5 * n->cfg.lr * (1.0 + std::cos(M_PI * (double)ep / (double)epochs)))
+                           : n->cfg.lr;
+      st = nn_adam_now(n, lr);
       if (st != TDDFT_OK) return cleanup(st);
       ++n_batches[ep];
     }
@@ -273,6 +342,8 @@ struct tddft_ms {
   hipStream_t stream = nullptr;
   double *A[3] = {nullptr, nullptr, nullptr};  // prev, now, new (rotating)
   double* I = nullptr;                          // [n_x]
+  double* Iold = nullptr;                       // [n_x] the current of the previous step
+  double* energy = nullptr;                     // [2]: work on the medium, field energy (per area)
   int steps = 0;
   int mode = 0;  // 0 cells, 1 network
   int fallbacks = 0;
@@ -412,6 +483,25 @@ tddft_status ms_fallback(tddft_ms* ms) {
   const size_t last = ms->steps > 0 ? (size_t)(ms->steps - 1) * nm : 0;
   for (int m = 0; m < nm; ++m) I[ms->cfg.x0 + m] = ms->steps > 0 ? Ic[last + m] : 0.0;
   MHIP(hipMemcpyAsync(ms->I, I.data(), I.size() * sizeof(double), hipMemcpyHostToDevice, ms->stream));
+  // the work on the medium, again from the cells' currents (I = 0 at t_0)
+  if (ms->steps > 0) {
+    std::vector<double> Ih((size_t)(ms->steps + 1) * nm, 0.0);
+    std::copy(Ic.begin(), Ic.end(), Ih.begin() + nm);
+    double *dA = nullptr, *dI = nullptr;
+    if (nalloc(&dA, h.size()) || nalloc(&dI, Ih.size())) {
+      if (dA) (void)hipFree(dA);
+      return ms_fail(ms, TDDFT_ENOMEM, "device allocation failed (work history)");
+    }
+    hipError_t e = hipMemcpyAsync(dA, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, ms->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(dI, Ih.data(), Ih.size() * sizeof(double), hipMemcpyHostToDevice, ms->stream);
+    if (e == hipSuccess)
+      e = launch_ms_work_history(dA, dI, ms->steps, nm, ms->cfg.dx, ms->cfg.dt, ms->energy, ms->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ms->stream);
+    (void)hipFree(dA);
+    (void)hipFree(dI);
+    if (e != hipSuccess) return ms_fail(ms, TDDFT_EDEVICE, std::string("work history: ") + hipGetErrorString(e));
+  }
   MHIP(hipStreamSynchronize(ms->stream));
   ms->hist = h;
   ms->mode = 0;
@@ -502,10 +592,11 @@ tddft_status tddft_ms_create(const tddft_ms_config* cfg, const tddft_config* cel
   if (hipStreamCreate(&ms->stream) != hipSuccess) return bad(TDDFT_EDEVICE);
   const size_t nx = cfg->n_x;
   if (nalloc(&ms->A[0], nx) || nalloc(&ms->A[1], nx) || nalloc(&ms->A[2], nx) || nalloc(&ms->I, nx) ||
-      nalloc(&ms->flag, 1))
+      nalloc(&ms->Iold, nx) || nalloc(&ms->energy, 2) || nalloc(&ms->flag, 1))
     return bad(TDDFT_ENOMEM);
-  for (double* p : {ms->A[0], ms->A[1], ms->A[2], ms->I})
+  for (double* p : {ms->A[0], ms->A[1], ms->A[2], ms->I, ms->Iold})
     if (hipMemsetAsync(p, 0, nx * sizeof(double), ms->stream) != hipSuccess) return bad(TDDFT_EDEVICE);
+  if (hipMemsetAsync(ms->energy, 0, 2 * sizeof(double), ms->stream) != hipSuccess) return bad(TDDFT_EDEVICE);
   if (hipMemsetAsync(ms->flag, 0, sizeof(int), ms->stream) != hipSuccess ||
       hipStreamSynchronize(ms->stream) != hipSuccess)
     return bad(TDDFT_EDEVICE);
@@ -559,6 +650,7 @@ tddft_status tddft_ms_step(tddft_ms* ms, int32_t n_macro, const double* inc, dou
     const double iv[4] = {inc ? inc[2 * n] : 0.0, inc ? inc[2 * n + 1] : 0.0, inc ? inc[2 * n + 2] : 0.0,
                           inc ? inc[2 * n + 3] : 0.0};
     MHIP(launch_fdtd_step(ms->A[1], ms->A[0], ms->I, ms->A[2], nx, S2, src, q, iv, ms->stream));
+    MHIP(hipMemcpyAsync(ms->Iold, ms->I, nx * sizeof(double), hipMemcpyDeviceToDevice, ms->stream));
     if (ms->mode == 0) {
       MHIP(hipMemcpyAsync(Anew.data(), ms->A[2], nx * sizeof(double), hipMemcpyDeviceToHost, ms->stream));
       MHIP(hipStreamSynchronize(ms->stream));
@@ -584,6 +676,7 @@ tddft_status tddft_ms_step(tddft_ms* ms, int32_t n_macro, const double* inc, dou
       MHIP(hipMemcpyAsync(ms->dIhist + (size_t)(ms->steps + 1) * nm, ms->I + g.x0, nm * sizeof(double),
                           hipMemcpyDeviceToDevice, ms->stream));
     }
+    MHIP(launch_ms_work_step(ms->A[2], ms->A[1], ms->Iold, ms->I, g.x0, nm, g.dx, g.dt, ms->energy, ms->stream));
     if (A_out) MHIP(hipMemcpyAsync(A_out + (size_t)n * nx, ms->A[2], nx * sizeof(double), hipMemcpyDeviceToHost, ms->stream));
     if (I_out) MHIP(hipMemcpyAsync(I_out + (size_t)n * nx, ms->I, nx * sizeof(double), hipMemcpyDeviceToHost, ms->stream));
     double* t = ms->A[0];
@@ -615,6 +708,17 @@ tddft_status tddft_ms_status(tddft_ms* ms, int32_t* mode, int32_t* fallbacks, do
   return TDDFT_OK;
 }
 
+tddft_status tddft_ms_energy(tddft_ms* ms, double* em, double* work) {
+  if (!ms) return TDDFT_EINVAL;
+  MHIP(launch_em_energy(ms->A[1], ms->A[0], ms->cfg.n_x, ms->cfg.dx, ms->cfg.dt, ms->energy + 1, ms->stream));
+  double v[2];
+  MHIP(hipMemcpyAsync(v, ms->energy, sizeof(v), hipMemcpyDeviceToHost, ms->stream));
+  MHIP(hipStreamSynchronize(ms->stream));
+  if (work) *work = v[0];
+  if (em) *em = v[1];
+  return TDDFT_OK;
+}
+
 const char* tddft_ms_last_error(const tddft_ms* ms) { return ms ? ms->err.c_str() : "null multiscale run"; }
 
 void tddft_ms_free(tddft_ms* ms) {
@@ -622,7 +726,7 @@ void tddft_ms_free(tddft_ms* ms) {
   if (ms->stream) (void)hipStreamSynchronize(ms->stream);
   if (ms->full) tddft_batch_free(ms->full);
   if (ms->sent) tddft_batch_free(ms->sent);
-  for (double* p : {ms->A[0], ms->A[1], ms->A[2], ms->I, ms->dhist, ms->dIhist})
+  for (double* p : {ms->A[0], ms->A[1], ms->A[2], ms->I, ms->Iold, ms->energy, ms->dhist, ms->dIhist})
     if (p) (void)hipFree(p);
   for (float* p : {ms->ring, ms->Xw, ms->wk.h1, ms->wk.h2, ms->wk.y})
     if (p) (void)hipFree(p);

@@ -225,6 +225,7 @@ hipError_t launch_overlap_weight(const typename Vec2<T>::type* ref, const typena
 template <typename T>
 hipError_t launch_apply_lower(const typename Vec2<T>::type* w, const double2* M, int n_orb, int n_k, int N,
                               typename Vec2<T>::type* out, hipStream_t s);
+hipError_t launch_chol_inverse(double2* S, double2* M, int n, int n_k, int* bad, hipStream_t s);
 hipError_t launch_real_part(const double2* src, double* dst, size_t n, hipStream_t s);
 hipError_t launch_fill(double* p, double v, size_t n, hipStream_t s);
 hipError_t launch_copy8(const void* src, void* dst, size_t bytes, hipStream_t s);
@@ -255,6 +256,12 @@ hipError_t launch_ring_windows(const float* ring, int n_mat, int W, int head, fl
 hipError_t launch_scatter_current(const float* y, int x0, int n_mat, int n, double j_scale, double* I,
                                   hipStream_t s);
 hipError_t launch_ms_gate(const double* A, int x0, int n_mat, double a_max, int* flag, hipStream_t s);
+hipError_t launch_em_energy(const double* A_now, const double* A_prev, int n, double dx, double dt, double* out,
+                            hipStream_t s);
+hipError_t launch_ms_work_step(const double* A_new, const double* A_now, const double* I_now, const double* I_new,
+                               int x0, int n_mat, double dx, double dt, double* W, hipStream_t s);
+hipError_t launch_ms_work_history(const double* A, const double* I, int steps, int n_mat, double dx, double dt,
+                                  double* W, hipStream_t s);
 
 // ---- current surrogate (k_nn.hip) ------------------------------------------
 struct NNShape {
@@ -271,5 +278,10 @@ hipError_t nn_adam(float* theta, float* m, float* v, const float* g, long n, flo
 hipError_t nn_gather(const float* seqA, const float* seqJ, int T, int W, const int* idx, int B, float* X,
                      float* target, hipStream_t s);
 hipError_t nn_accumulate(const float* src, float* dst, hipStream_t s);
+// least squares of the skip weights ws [W] and output bias b3 over trajectories
+// A, Y [n_traj][T] (scaled, FP64); G [(W+1)^2] and b [W+1] are work arrays
+hipError_t nn_fit_linear(const double* A, const double* Y, int n_traj, int T, int W, double lambda_rel, double* G,
+                         double* b, float* ws, float* b3, int* ok, hipStream_t s);
+hipError_t nn_zero(float* p, long n, hipStream_t s);
 
 }  // namespace td

@@ -102,4 +102,96 @@ hipError_t launch_scatter_current(const float* y, int x0, int n_mat, int n, doub
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Energy monitor of the coupled run (Sec. 5: the energy of the fields and of
+// the electronic excitations together). Per unit area of the slab:
+//   field: (1/8 pi) [sum_j E_j^2 + sum_links B^2] dX, E = -(A_now - A_prev)/(c dt)
+//   (backward difference at every point), B = (A_{j+1} - A_j)/dX;
+//   electrons: the work of the field, W += dt dX sum_m (I_m^n + I_m^{n+1})/2
+//   E_m^{n+1/2} over the medium points (the excitation energy per area by the
+//   work route of Sec. 4.1). One workgroup each, fixed-order sums.
+
+__device__ __forceinline__ double block_sum_1024(double v, double* red) {
+  const int t = threadIdx.x;
+  red[t] = v;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if (t < w) red[t] += red[t + w];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(1024) void k_em_energy(const double* __restrict__ A_now, const double* __restrict__ A_prev,
+                                                    int n, double dx, double dt, double* __restrict__ out) {
+  __shared__ double red[1024];
+  const int t = threadIdx.x;
+  double e2 = 0.0, b2 = 0.0;
+  for (int j = t; j < n; j += 1024) {
+    const double E = -(A_now[j] - A_prev[j]) / (kC * dt);
+    e2 += E * E;
+    if (j + 1 < n) {
+      const double B = (A_now[j + 1] - A_now[j]) / dx;
+      b2 += B * B;
+    }
+  }
+  const double se = block_sum_1024(e2, red);
+  const double sb = block_sum_1024(b2, red);
+  if (t == 0) *out = (se + sb) * dx / (8.0 * M_PI);
+}
+
+// one macroscopic step's work over the medium points x0 .. x0 + n_mat - 1
+__global__ __launch_bounds__(1024) void k_ms_work_step(const double* __restrict__ A_new, const double* __restrict__ A_now,
+                                                       const double* __restrict__ I_now, const double* __restrict__ I_new,
+                                                       int x0, int n_mat, double dx, double dt, double* __restrict__ W) {
+  __shared__ double red[1024];
+  double s = 0.0;
+  for (int m = threadIdx.x; m < n_mat; m += 1024) {
+    const int j = x0 + m;
+    const double E = -(A_new[j] - A_now[j]) / (kC * dt);
+    s += 0.5 * (I_now[j] + I_new[j]) * E;
+  }
+  const double tot = block_sum_1024(s, red);
+  if (threadIdx.x == 0) *W += dt * dx * tot;
+}
+
+// the work from t_0 to t_steps from the medium histories A, I [(steps + 1)][n_mat]
+__global__ __launch_bounds__(1024) void k_ms_work_history(const double* __restrict__ A, const double* __restrict__ I,
+                                                          int steps, int n_mat, double dx, double dt,
+                                                          double* __restrict__ W) {
+  __shared__ double red[1024];
+  double acc = 0.0;  // thread 0 keeps the running total
+  for (int s = 0; s < steps; ++s) {
+    double v = 0.0;
+    for (int m = threadIdx.x; m < n_mat; m += 1024) {
+      const size_t a = (size_t)s * n_mat + m, b = a + n_mat;
+      const double E = -(A[b] - A[a]) / (kC * dt);
+      v += 0.5 * (I[a] + I[b]) * E;
+    }
+    const double tot = block_sum_1024(v, red);
+    acc += dt * dx * tot;
+  }
+  if (threadIdx.x == 0) *W = acc;
+}
+
+hipError_t launch_em_energy(const double* A_now, const double* A_prev, int n, double dx, double dt, double* out,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_em_energy, dim3(1), dim3(1024), 0, s, A_now, A_prev, n, dx, dt, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_ms_work_step(const double* A_new, const double* A_now, const double* I_now, const double* I_new,
+                               int x0, int n_mat, double dx, double dt, double* W, hipStream_t s) {
+  hipLaunchKernelGGL(k_ms_work_step, dim3(1), dim3(1024), 0, s, A_new, A_now, I_now, I_new, x0, n_mat, dx, dt, W);
+  return hipGetLastError();
+}
+
+hipError_t launch_ms_work_history(const double* A, const double* I, int steps, int n_mat, double dx, double dt,
+                                  double* W, hipStream_t s) {
+  hipLaunchKernelGGL(k_ms_work_history, dim3(1), dim3(1024), 0, s, A, I, steps, n_mat, dx, dt, W);
+  return hipGetLastError();
+}
+
 }  // namespace td

@@ -151,6 +151,161 @@ static hipError_t gemm(const float* A, long sai, long sak, const float* B, long 
   return hipGetLastError();
 }
 
+__global__ void k_zero_f(float* __restrict__ p, long n) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0f;
+}
+
+// G[i][i] += lambda_rel * trace(G) / n (one workgroup, fixed-order sum)
+__global__ __launch_bounds__(1024) void k_lin_trace_scale(double* __restrict__ G, int n, double lambda_rel) {
+  __shared__ double red[1024];
+  const int t = threadIdx.x;
+  double s = 0.0;
+  for (int i = t; i < n; i += 1024) s += G[(size_t)i * n + i];
+  red[t] = s;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if (t < w) red[t] += red[t + w];
+    __syncthreads();
+  }
+  const double lam = lambda_rel * red[0] / n;
+  __syncthreads();
+  for (int i = t; i < n; i += 1024) G[(size_t)i * n + i] += lam;
+}
+
+// ---------------------------------------------------------------------------
+// Least-squares fit of the linear part (skip weights and output bias) over a
+// set of trajectories, FP64. With the regressors x = (window of A, 1), n = W + 1:
+//   G[i][j] = sum over samples of x_i x_j,  b[i] = sum x_i y,
+// then (G + lambda I) w = b by a Cholesky factorisation in one workgroup.
+// Window entry i of the sample at time t of a trajectory is A(t - W + 1 + i),
+// zero before t = 0; the sums run over trajectories and times in order.
+
+__device__ __forceinline__ double lin_x(const double* __restrict__ a, int T, int W, int t, int i) {
+  if (i == W) return 1.0;
+  const int tt = t - W + 1 + i;
+  return tt >= 0 ? a[tt] : 0.0;
+}
+
+// one thread per (i, j >= i) pair of G, and one per entry of b (j = n)
+__global__ void k_lin_gram(const double* __restrict__ A, const double* __restrict__ Y, int n_traj, int T, int W,
+                           double* __restrict__ G, double* __restrict__ b) {
+  const int n = W + 1;
+  const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long pairs = (long)n * (n + 1) / 2;
+  if (id >= pairs + n) return;
+  int i, j;
+  bool rhs = id >= pairs;
+  if (rhs) {
+    i = (int)(id - pairs);
+    j = -1;
+  } else {
+    // id -> (i, j) with 0 <= i <= j < n, row by row
+    long r = id;
+    i = 0;
+    while (r >= n - i) {
+      r -= n - i;
+      ++i;
+    }
+    j = i + (int)r;
+  }
+  double acc = 0.0;
+  for (int k = 0; k < n_traj; ++k) {
+    const double* a = A + (size_t)k * T;
+    const double* y = Y + (size_t)k * T;
+    for (int t = 0; t < T; ++t) {
+      const double xi = lin_x(a, T, W, t, i);
+      acc += xi * (rhs ? y[t] : lin_x(a, T, W, t, j));
+    }
+  }
+  if (rhs) {
+    b[i] = acc;
+  } else {
+    G[(size_t)i * n + j] = acc;
+    G[(size_t)j * n + i] = acc;
+  }
+}
+
+// Solve (G + lambda I) w = b in place (G n x n, row-major): right-looking
+// Cholesky G = L L^T (L in the lower triangle), then L z = b, L^T w = z.
+// One workgroup; *ok = 0 if a pivot is not positive.
+__global__ __launch_bounds__(1024) void k_lin_solve(double* __restrict__ G, double* __restrict__ b, int n,
+                                                    double lambda, float* __restrict__ ws, float* __restrict__ b3,
+                                                    int* __restrict__ ok) {
+  __shared__ double piv;
+  __shared__ int good;
+  const int t = threadIdx.x, nt = blockDim.x;
+  if (t == 0) good = 1;
+  for (int i = t; i < n; i += nt) G[(size_t)i * n + i] += lambda;
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    if (t == 0) {
+      const double d = G[(size_t)j * n + j];
+      if (!(d > 0.0)) good = 0;
+      piv = d > 0.0 ? sqrt(d) : 1.0;
+      G[(size_t)j * n + j] = piv;
+    }
+    __syncthreads();
+    for (int i = j + 1 + t; i < n; i += nt) G[(size_t)i * n + j] /= piv;
+    __syncthreads();
+    // trailing update of the lower triangle: G[i][k] -= L[i][j] L[k][j], j < k <= i
+    const int m = n - j - 1;
+    const long cnt = (long)m * (m + 1) / 2;
+    for (long q = t; q < cnt; q += nt) {
+      // q -> (ii, kk) with 0 <= kk <= ii < m
+      const int ii = (int)((sqrt(8.0 * (double)q + 1.0) - 1.0) * 0.5);
+      int i2 = ii;
+      long base = (long)i2 * (i2 + 1) / 2;
+      if (base > q) {
+        --i2;
+        base = (long)i2 * (i2 + 1) / 2;
+      } else if (base + i2 + 1 <= q) {
+        ++i2;
+        base = (long)i2 * (i2 + 1) / 2;
+      }
+      const int kk = (int)(q - base);
+      const int row = j + 1 + i2, col = j + 1 + kk;
+      G[(size_t)row * n + col] -= G[(size_t)row * n + j] * G[(size_t)col * n + j];
+    }
+    __syncthreads();
+  }
+  // forward substitution L z = b (z in b), then back substitution L^T w = z
+  for (int j = 0; j < n; ++j) {
+    if (t == 0) b[j] /= G[(size_t)j * n + j];
+    __syncthreads();
+    for (int i = j + 1 + t; i < n; i += nt) b[i] -= G[(size_t)i * n + j] * b[j];
+    __syncthreads();
+  }
+  for (int j = n - 1; j >= 0; --j) {
+    if (t == 0) b[j] /= G[(size_t)j * n + j];
+    __syncthreads();
+    for (int i = t; i < j; i += nt) b[i] -= G[(size_t)j * n + i] * b[j];
+    __syncthreads();
+  }
+  for (int i = t; i < n - 1; i += nt) ws[i] = (float)b[i];
+  if (t == 0) {
+    *b3 = (float)b[n - 1];
+    *ok = good;
+  }
+}
+
+hipError_t nn_fit_linear(const double* A, const double* Y, int n_traj, int T, int W, double lambda_rel, double* G,
+                         double* b, float* ws, float* b3, int* ok, hipStream_t s) {
+  const int n = W + 1;
+  const long work = (long)n * (n + 1) / 2 + n;
+  hipLaunchKernelGGL(k_lin_gram, dim3((unsigned)((work + 255) / 256)), dim3(256), 0, s, A, Y, n_traj, T, W, G, b);
+  // lambda relative to the mean diagonal of G, added by the solve kernel
+  // (which reads the diagonal first)
+  hipLaunchKernelGGL(k_lin_trace_scale, dim3(1), dim3(1024), 0, s, G, n, lambda_rel);
+  hipLaunchKernelGGL(k_lin_solve, dim3(1), dim3(1024), 0, s, G, b, n, 0.0, ws, b3, ok);
+  return hipGetLastError();
+}
+
+hipError_t nn_zero(float* p, long n, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_f, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
 hipError_t nn_forward(const NNShape& sh, const float* theta, const float* X, int B, NNWork& wk, hipStream_t s) {
   const int W = sh.W, H = sh.H;
   const float* W1 = theta;

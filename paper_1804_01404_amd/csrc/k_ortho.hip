@@ -1,7 +1,7 @@
 // Orthonormalisation of the orbitals of every k-point (Gram-Schmidt in
 // orbital order, as Cholesky-QR): S_k[i][j] = h^3 sum_r w_i(r) conj(w_j(r))
 // formed on the device in FP64 (fixed-order reductions), S_k = L L^H factored
-// on the host, and w <- L^{-1} w applied on the device. Used by the
+// and inverted on the device, and w <- L^{-1} w applied there too. Used by the
 // ground-state preparation that precedes the real-time run (Sec. 2.1).
 #include "internal.h"
 
@@ -44,6 +44,64 @@ __global__ __launch_bounds__(256) void k_gram(const typename Vec2<T>::type* w, i
     S[((size_t)k * n_orb + i) * n_orb + j] = make_double2(dV * red[0][0], dV * red[0][1]);
     S[((size_t)k * n_orb + j) * n_orb + i] = make_double2(dV * red[0][0], -dV * red[0][1]);
   }
+}
+
+// Per k-point (one workgroup each): the Cholesky factor S = L L^H of the
+// Hermitian positive overlap matrix (left-looking, column by column; L
+// overwrites the lower triangle of S) and its inverse M = L^{-1} (lower
+// triangular; the columns of M are independent, one thread each). A pivot
+// that is not positive sets *bad (the orbitals became linearly dependent).
+__global__ __launch_bounds__(256) void k_chol_inverse(double2* __restrict__ S, double2* __restrict__ M, int n,
+                                                      int* __restrict__ bad) {
+  __shared__ double piv;
+  const int k = blockIdx.x;
+  double2* L = S + (size_t)k * n * n;
+  double2* Mk = M + (size_t)k * n * n;
+  const int t = threadIdx.x, nt = blockDim.x;
+  for (int j = 0; j < n; ++j) {
+    // s_ij = S_ij - sum_{q<j} L_iq conj(L_jq), for i >= j
+    for (int i = j + t; i < n; i += nt) {
+      double sr = L[(size_t)i * n + j].x, si = L[(size_t)i * n + j].y;
+      for (int q = 0; q < j; ++q) {
+        const double2 a = L[(size_t)i * n + q], b = L[(size_t)j * n + q];
+        sr -= a.x * b.x + a.y * b.y;
+        si -= a.y * b.x - a.x * b.y;
+      }
+      L[(size_t)i * n + j] = make_double2(sr, si);
+    }
+    __syncthreads();
+    if (t == 0) {
+      const double d = L[(size_t)j * n + j].x;
+      if (!(d > 0.0)) atomicOr(bad, 1);
+      piv = d > 0.0 ? sqrt(d) : 1.0;
+      L[(size_t)j * n + j] = make_double2(piv, 0.0);
+    }
+    __syncthreads();
+    for (int i = j + 1 + t; i < n; i += nt) {
+      const double2 v = L[(size_t)i * n + j];
+      L[(size_t)i * n + j] = make_double2(v.x / piv, v.y / piv);
+    }
+    __syncthreads();
+  }
+  // M = L^{-1}: column c by forward substitution, M_ic = (delta_ic - sum_{q=c}^{i-1} L_iq M_qc) / L_ii
+  for (int c = t; c < n; c += nt) {
+    for (int i = 0; i < c; ++i) Mk[(size_t)i * n + c] = make_double2(0.0, 0.0);
+    for (int i = c; i < n; ++i) {
+      double br = (i == c) ? 1.0 : 0.0, bi = 0.0;
+      for (int q = c; q < i; ++q) {
+        const double2 l = L[(size_t)i * n + q], m = Mk[(size_t)q * n + c];
+        br -= l.x * m.x - l.y * m.y;
+        bi -= l.x * m.y + l.y * m.x;
+      }
+      const double d = L[(size_t)i * n + i].x;
+      Mk[(size_t)i * n + c] = make_double2(br / d, bi / d);
+    }
+  }
+}
+
+hipError_t launch_chol_inverse(double2* S, double2* M, int n, int n_k, int* bad, hipStream_t s) {
+  hipLaunchKernelGGL(k_chol_inverse, dim3((unsigned)n_k), dim3(256), 0, s, S, M, n, bad);
+  return hipGetLastError();
 }
 
 // out[k][i][p] = sum_{j <= i} M[k][i][j] w[k][j][p]

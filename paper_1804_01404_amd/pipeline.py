@@ -13,11 +13,31 @@ import numpy as np
 from .binding import Multiscale, Surrogate, TDDFT, TDDFTBatch
 
 
-def ground_state(system, *, n_iter=300, tau=0.02, precision="c128"):
-    """Orbitals and energies after n_iter imaginary-time iterations."""
+def ground_state(system, *, n_iter=300, tau=0.02, precision="c128", imag_time=None):
+    """Orbitals and the energies of the last two of n_iter imaginary-time
+    iterations of step tau. With imag_time, tau is the largest of 0.06, 0.05, 0.04, ... that the
+    library accepts for this cell (tau lambda_max <= 1.59) and n_iter covers
+    that much imaginary time."""
+    from .binding import EUNSTABLE, TDDFTError
+    def run(t, n, tau):
+        # energies of the last two iterations only (one host round trip each)
+        if n > 2:
+            t.ground_state(n - 2, tau, energies=False)
+        return t.ground_state(min(n, 2), tau)
     with TDDFT(system, precision=precision) as t:
         t.set_potential()
-        E = t.ground_state(n_iter, tau)
+        if imag_time is None:
+            E = run(t, n_iter, tau)
+        else:
+            for tau in (0.06, 0.05, 0.04, 0.033, 0.028, 0.024, 0.02, 0.016, 0.012, 0.008):
+                try:
+                    E = run(t, int(round(imag_time / tau)), tau)
+                    break
+                except TDDFTError as e:
+                    if e.status != EUNSTABLE:
+                        raise
+            else:
+                raise RuntimeError("no stable imaginary-time step")
         psi = t.orbitals()
     return psi, E
 
@@ -64,10 +84,19 @@ def _copy_with_orbitals(system, psi0):
     return c
 
 
-def train(A_macro, J_macro, params, *, window, hidden, a_scale, j_scale, epochs, batch, seed=0, lr=1e-3):
-    """A Surrogate trained on the trajectories; returns it and the losses."""
+def train(A_macro, J_macro, params, *, window, hidden, a_scale, j_scale, epochs, batch, seed=0, lr=1e-3,
+          a_fit=None, cosine=False):
+    """A Surrogate trained on the trajectories; returns it and the losses.
+
+    With a_fit, the skip weights and output bias are first set to the
+    least-squares linear response of the trajectories whose largest |A| is
+    within a_fit and kept fixed; Adam then trains the hidden layers on what
+    the linear response leaves (the nonlinear part)."""
     nn = Surrogate(window, hidden, params, a_scale=a_scale, j_scale=j_scale, lr=lr)
-    losses = nn.train(A_macro, J_macro, epochs=epochs, batch=batch, seed=seed)
+    if a_fit is not None:
+        nn.fit_linear(A_macro, J_macro, a_fit=a_fit)
+    losses = nn.train(A_macro, J_macro, epochs=epochs, batch=batch, seed=seed, cosine=cosine,
+                      freeze_linear=a_fit is not None)
     return nn, losses
 
 

@@ -65,3 +65,33 @@ def test_batch_second_propagate_reuses_graph():
     for i in range(len(cells)):
         assert np.array_equal(np.concatenate([J1[i], J2[i]]), J[i])
         assert np.array_equal(psi_a[i], psi_b[i])
+
+
+def test_mixed_batch_with_32_cubed_cells_matches_oracle():
+    """A complex FP32 batch whose cells include two 32^3 cells (per-stage
+    lanes with the tuned decomposition) beside 16^3 and 20^3 cells (persistent
+    fused groups), each with its own k-points, atoms and pulse, against the
+    oracle: orbitals and density within 2e-6 sqrt(n), current within 1e-4 of
+    its maximum (these cells start from random orbitals at random k-points
+    under weak pulses, so the current is a small difference of the momentum
+    and kappa-norm terms, each rounded at the FP32 level)."""
+    from paper_1804_01404_amd.binding import TDDFTBatch
+    n = 6
+    cells = synth.batch_cells(cells=[0, 1, 2, 3], nsteps=n, max_orb=8, max_k=2, grids=(32,), precision="mixed")
+    cells[1] = synth.batch_cells(cells=[1], nsteps=n, max_orb=8, max_k=2, grids=(16,), precision="mixed")[0]
+    cells[3] = synth.batch_cells(cells=[3], nsteps=n, max_orb=8, max_k=2, grids=(20,), precision="mixed")[0]
+    announce(f"mixed batch with 32^3 cells, grids {[c.n[0] for c in cells]}")
+    with TDDFTBatch(cells, precision="mixed") as b:
+        Js = b.propagate([c.A for c in cells])
+        psis = [b.orbitals(i) for i in range(len(cells))]
+        rhos = [b.density(i) for i in range(len(cells))]
+        rep = b.report()
+    assert sorted(rep["per_stage_cells"]) == [0, 2]
+    assert len(rep["per_stage_tiles"]) >= 1
+    for i, c in enumerate(cells):
+        o = oracle_run(c)
+        assert rel_l2(psis[i], o["psi"]) < 2e-6 * np.sqrt(n), i
+        assert rel_l2(rhos[i], o["rho"]) < 2e-6 * np.sqrt(n), i
+        err = max_rel_series(Js[i], o["J"])
+        announce(f"  cell {i} ({c.n[0]}^3) current error {err:.3e}")
+        assert err < 1e-4, i

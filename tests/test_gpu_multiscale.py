@@ -172,3 +172,85 @@ def test_sentinel_check_trips_on_an_untrained_network():
     assert st["fallbacks"] == 1 and st["mode"] == "cells"
     assert st["last_check"] > 1e-3
     assert np.all(np.isfinite(A)) and np.all(np.isfinite(I))
+
+
+def test_energy_monitor_matches_oracle():
+    """The field energy and the work on the medium (Sec. 5's energy monitor)
+    against the oracle's em_energy and medium_work on the oracle's own run of
+    the free-electron slab, after every few steps; and the monitor's sum stays
+    at the energy that has entered (no flux has left yet)."""
+    from paper_1804_01404_amd.binding import Multiscale
+    n_x, x0, n_mat, dx, n_sub = 24, 6, 10, 40.0, 3
+    dt = 0.6 * dx / C
+    s = _free_electron_system(dt / n_sub)
+    steps = 30
+    inc = synth.incident_table(steps, dt, dx, delay=0.0, E0=5e-3, omega=0.2, T=12.0)
+    announce("multiscale energy monitor vs oracle")
+    Ao, Io = _oracle_ms(s, n_x, x0, n_mat, dx, dt, n_sub, 2, steps, inc)
+    A_hist = np.vstack([np.zeros(n_mat), Ao[:, x0:x0 + n_mat]])
+    I_hist = np.vstack([np.zeros(n_mat), Io[:, x0:x0 + n_mat]])
+    W_o = maxwell.medium_work(A_hist, I_hist, dx, dt)
+    with Multiscale(s, s.psi0, n_x=n_x, x0=x0, n_mat=n_mat, dx=dx, dt=dt, n_sub=n_sub, axis=2,
+                    precision="c128") as ms:
+        done = 0
+        for chunk in (1, 4, 10, 15):
+            ms.step(chunk, inc[done:done + chunk + 1])
+            done += chunk
+            em, work = ms.energy()
+            A_prev = Ao[done - 2] if done >= 2 else np.zeros(n_x)
+            em_o = maxwell.em_energy(Ao[done - 1], A_prev, dx, dt)
+            assert abs(em - em_o) < 1e-10 * em_o, done
+            assert abs(work - W_o[done]) < 1e-9 * max(abs(W_o).max(), 1e-300), done
+    assert abs(W_o).max() > 0
+
+
+def test_linear_fit_matches_oracle():
+    """The device least-squares fit of the skip weights and bias against the
+    oracle's, on trajectories with a known linear part and a cubic term beyond
+    the fitted amplitude."""
+    from paper_1804_01404_amd.binding import Surrogate
+    import synth
+    rng = rng_for(6611)
+    W, H, T, n = 40, 8, 90, 24
+    A = np.cumsum(rng.normal(size=(n, T)), axis=1) * 0.05
+    A[:, 0] = 0.0
+    A[n // 2:] *= 30.0
+    k = rng.normal(size=W) * np.exp(-np.arange(W)[::-1] / 10.0)
+    J = np.zeros_like(A)
+    for i in range(n):
+        for t in range(T):
+            seg = A[i, max(0, t - W + 1):t + 1]
+            J[i, t] = np.dot(seg, k[W - seg.shape[0]:]) - 0.02
+    J[n // 2:] += 0.01 * A[n // 2:] ** 3
+    a_scale, j_scale = float(np.abs(A).max()), float(np.abs(J).max())
+    a_fit = float(np.abs(A[: n // 2]).max())
+    announce("surrogate linear fit vs oracle")
+    with Surrogate(W, H, synth.surrogate_init(W, H, 3), a_scale=a_scale, j_scale=j_scale) as nn:
+        nn.fit_linear(A, J, a_fit=a_fit, lambda_rel=1e-12)
+        p = nn.params()
+    ws_o, b3_o = surrogate.fit_linear(A, J, W, a_scale, j_scale, a_fit, lambda_rel=1e-12)
+    ws, b3, w3 = p[-W:], p[-W - 1], p[-W - 1 - H:-W - 1]
+    assert np.max(np.abs(ws - ws_o)) < 1e-5 * np.max(np.abs(ws_o))
+    assert abs(b3 - b3_o) < 1e-5 * max(abs(b3_o), 1e-6)
+    assert np.all(w3 == 0.0)
+
+
+def test_training_options_freeze_and_cosine():
+    """Frozen linear part: b3 and ws come out of training unchanged, the rest
+    moves; a cosine schedule over one epoch is the plain first epoch (its
+    learning rate at epoch 0 is the base rate)."""
+    rng = rng_for(6612)
+    A = np.cumsum(rng.normal(size=(6, 50)), axis=1) * 0.1
+    J = np.tanh(A) * 0.5
+    nn, th = _net(6613)
+    with nn:
+        nn.train(A, J, epochs=3, batch=32, seed=1, freeze_linear=True)
+        p = nn.params()
+    assert np.array_equal(p[-(W_ + 1):], th[-(W_ + 1):])
+    assert not np.array_equal(p[:-(W_ + 1)], th[:-(W_ + 1)])
+    nn1, _ = _net(6613)
+    nn2, _ = _net(6613)
+    with nn1, nn2:
+        nn1.train(A, J, epochs=1, batch=32, seed=2)
+        nn2.train(A, J, epochs=1, batch=32, seed=2, cosine=True)
+        assert np.array_equal(nn1.params(), nn2.params())
