@@ -462,7 +462,7 @@ def bench_multiscale_cfg5(n_macro=600, timed_cells=8, n_traj=64):
     cell = synth.multiscale_cell(dt=dt / n_sub)
     t0 = time.perf_counter()
     log("  cfg5 cell: ground state")
-    psi, E = pipeline.ground_state(cell, imag_time=2160.0)
+    psi, E = pipeline.ground_state(cell, imag_time=2880.0)
     t_gs = time.perf_counter() - t0
     log("  cfg5 cell: training trajectories")
     # field amplitudes within what the cell's step of 0.08 allows (|A| enters
@@ -472,7 +472,7 @@ def bench_multiscale_cfg5(n_macro=600, timed_cells=8, n_traj=64):
     A_tr = np.vstack([synth.random_field_tables(n_traj - n_traj // 4, n_macro, dt, 11, a_max=3.0), P])
     J_tr, t_gen = pipeline.trajectories(cell, psi, A_tr, n_sub=n_sub, axis=0)
     a_scale, j_scale = float(np.abs(A_tr).max()), float(np.abs(J_tr).max())
-    J0, _ = pipeline.trajectories(cell, psi, np.zeros((1, 64)), n_sub=n_sub, axis=0)
+    J0, _ = pipeline.trajectories(cell, psi, np.zeros((1, 32)), n_sub=n_sub, axis=0)
     t0 = time.perf_counter()
     log("  cfg5 cell: training")
     nn, losses = pipeline.train(A_tr, J_tr, synth.surrogate_init(W, 16, 2), window=W, hidden=16,

@@ -353,6 +353,7 @@ tddft_status enqueue_observe(tddft_ctx* c, int bump) {
   oa.g = c->g;
   std::memcpy(oa.dh, c->dh, sizeof(oa.dh));
   std::memcpy(oa.lap, c->lap, sizeof(oa.lap));
+  oa.set_weights();
   oa.cdiag = c->cdiag;
   oa.out = c->obs;
   LAUNCH(launch_observe<T>(c->bc, oa, c->stream), "observe");
@@ -633,6 +634,7 @@ tddft_status launch_one(tddft_ctx* c, int which) {
     oa.g = c->g;
     std::memcpy(oa.dh, c->dh, sizeof(oa.dh));
     std::memcpy(oa.lap, c->lap, sizeof(oa.lap));
+    oa.set_weights();
     oa.cdiag = c->cdiag;
     oa.out = c->obs;
     LAUNCH(launch_observe<T>(c->bc, oa, c->stream), "observe");
@@ -746,7 +748,8 @@ bool make_stage_geometry(const tddft_ctx* c, const StagePlan& p, Geometry* out) 
     if (!g.periodic || g.n1 * g.n2 > 1024 || p.TX != g.n1 || p.TY != g.n2) return false;
   } else {
     if (p.bc != (g.periodic ? kPeriodicTile : kIsolatedTile)) return false;
-    if (p.TX < 4 || p.TY < 4 || g.n1 % p.TX || g.n2 % p.TY || p.TX * p.TY > 1024) return false;
+    if (p.TX < 4 || p.TY < 4 || g.n1 % p.TX || g.n2 % p.TY || p.TX * p.TY > 1024 || !halo_fits(p.TX, p.TY))
+      return false;
   }
   if (p.zs < 1 || p.zs > g.n3) return false;
   const int zlen = (g.n3 + p.zs - 1) / p.zs;
@@ -1037,7 +1040,8 @@ tddft_status tddft_init(const tddft_config* cfg, const double* psi0, tddft_ctx**
     g.TX = tile_dim(g.n1, 32);
     g.TY = g.TX > 0 ? tile_dim(g.n2, std::max(4, 256 / g.TX)) : -1;
     if (g.TX > 0 && g.TY < 4) g.TY = tile_dim(g.n2, std::max(4, 1024 / g.TX));
-    if (g.TX < 4 || g.TY < 4 || g.TX * g.TY > 1024) return bad("no workgroup tiling for this grid");
+    if (g.TX < 4 || g.TY < 4 || g.TX * g.TY > 1024 || !halo_fits(g.TX, g.TY))
+      return bad("no workgroup tiling for this grid");
   }
   g.tiles_x = g.n1 / g.TX;
   g.tiles_y = g.n2 / g.TY;

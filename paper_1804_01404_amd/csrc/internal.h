@@ -18,6 +18,12 @@ constexpr int kHalf = 4;               // stencil half width (9 points per axis)
 constexpr int kMaxProj = 4;            // projectors per atom
 constexpr int kMoments = 4;            // beta, x beta, y beta, z beta
 constexpr int kCols = kMaxProj * kMoments;  // MFMA B-matrix columns (16)
+// halo points a thread of a tiled stage or observe workgroup stages per plane
+// at most: 8 (TX + TY) points over ceil64(TX TY) threads
+constexpr int kHaloSlots = 3;
+__host__ __device__ inline bool halo_fits(int TX, int TY) {
+  return 8 * (TX + TY) <= kHaloSlots * ((TX * TY + 63) / 64) * 64;
+}
 constexpr int kCoef = 16;  // per k-point: kappa_mu d_m / h_mu for x, y, z (3 x 4), diagonal, padding
 
 enum StageMode { kFirst = 0, kMid = 1, kLast = 2 };
@@ -98,6 +104,16 @@ struct ObserveArgs {
   double lap[3][5];
   double cdiag;
   double* out;             // [n_orb_tot][tiles][8]: norm, p_x, p_y, p_z, kin, vloc
+  // off-centre weights of lap and dh in the stage precision (kernel
+  // arguments, so they stay in scalar registers); set by set_weights
+  T cl[3][4], cd[3][4];
+  void set_weights() {
+    for (int mu = 0; mu < 3; ++mu)
+      for (int m = 0; m < 4; ++m) {
+        cl[mu][m] = (T)lap[mu][m + 1];
+        cd[mu][m] = (T)dh[mu][m];
+      }
+  }
 };
 
 template <typename T>

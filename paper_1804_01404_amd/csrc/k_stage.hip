@@ -16,6 +16,9 @@
 //
 // HBM traffic per orbital point and stage: read u_s once, read w once (not in
 // the first stage, where u_4 = w), write u_{s-1} once.
+#include <type_traits>
+#include <utility>
+
 #include "internal.h"
 
 namespace td {
@@ -28,14 +31,163 @@ __device__ __forceinline__ T2 zero2() {
   return z;
 }
 
-// planes of u, w and V in flight ahead of the current one: two for complex
-// FP32 on tiled grids, one otherwise (measured on 20^3 and 96^3 cells; a
-// deeper queue costs complex128 more in registers than it gains)
-template <typename T, int BC>
-constexpr int stage_prefetch() {
-  return (sizeof(T) == 4 && BC != kPeriodicPlane) ? 2 : 1;
+// v where c holds, else zero, selected per component: a select of the whole
+// vector value can be compiled as a select between addresses, one of them a
+// zero kept in private memory
+template <typename T2>
+__device__ __forceinline__ T2 keep_if(bool c, const T2& v) {
+  T2 r;
+  r.x = c ? v.x : 0;
+  r.y = c ? v.y : 0;
+  return r;
 }
 
+// p advanced by an unsigned 32-bit byte offset: with p uniform this is a
+// scalar base plus a 32-bit lane offset, which the load instruction adds
+// itself (no 64-bit address arithmetic per lane)
+template <class X>
+__device__ __forceinline__ X* at(X* p, unsigned bytes) {
+  using C = typename std::conditional<std::is_const<X>::value, const char, char>::type;
+  return reinterpret_cast<X*>(reinterpret_cast<C*>(p) + bytes);
+}
+
+__device__ __forceinline__ float fmat(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmat(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// Loads and stores of data used once (w, and u_{s-1} of a stage) marked
+// non-temporal, so that they do not push out of L2 the u lines that the
+// neighbouring tiles read as halo.
+typedef float f2v_t __attribute__((ext_vector_type(2)));
+typedef double d2v_t __attribute__((ext_vector_type(2)));
+template <class T2> struct NtVec;
+template <> struct NtVec<float2> { using V = f2v_t; };
+template <> struct NtVec<double2> { using V = d2v_t; };
+// Copies through the native vector type: a copy of the 16-byte complex128
+// struct into an array element is otherwise a memcpy that keeps the array in
+// private memory.
+template <class T2>
+__device__ __forceinline__ T2 load2(const T2* p) {
+  using V = typename NtVec<T2>::V;
+  const V v = *reinterpret_cast<const V*>(p);
+  T2 r;
+  r.x = v.x;
+  r.y = v.y;
+  return r;
+}
+template <class T2>
+__device__ __forceinline__ void store2(T2* p, const T2& a) {
+  using V = typename NtVec<T2>::V;
+  V v;
+  v.x = a.x;
+  v.y = a.y;
+  *reinterpret_cast<V*>(p) = v;
+}
+template <class T2>
+__device__ __forceinline__ T2 load_once(const T2* p) {
+  using V = typename NtVec<T2>::V;
+  const V v = __builtin_nontemporal_load(reinterpret_cast<const V*>(p));
+  T2 r;
+  r.x = v.x;
+  r.y = v.y;
+  return r;
+}
+template <class T2>
+__device__ __forceinline__ void store_once(T2* p, const T2& a) {
+  using V = typename NtVec<T2>::V;
+  V v;
+  v.x = a.x;
+  v.y = a.y;
+  __builtin_nontemporal_store(v, reinterpret_cast<V*>(p));
+}
+
+// The 4-point halo of a tiled workgroup's TX x TY tile (rows above and below,
+// columns left and right; the stencil needs no corners): 8 (TX + TY) points
+// per plane, dealt to the threads in turn, so a thread stages the same slots
+// on every plane. Every thread loads all kHaloSlots slots on every plane (a
+// fixed count of loads per plane lets the compiler wait for exactly the
+// plane it needs); slots past the last point repeat it and are not staged
+// (a per-lane test, so that the slot loop keeps constant indices).
+struct HaloSlots {
+  int lds[kHaloSlots];       // place in the staged plane
+  unsigned off[kHaloSlots];  // in-plane offset of the source point (wrapped or clamped)
+  bool own[kHaloSlots];      // a real slot of this thread (not a repeat of the last one)
+  bool in[kHaloSlots];       // false outside an isolated grid: staged as zero
+  bool stage[kHaloSlots];    // own and in: staged from the plane's load
+};
+
+__device__ __forceinline__ HaloSlots halo_slots(int tid, int B, int TX, int TY, int LW, int x0, int y0, int n1,
+                                                int n2, bool periodic) {
+  HaloSlots h;
+  const int S = 8 * (TX + TY);
+#pragma unroll
+  for (int i = 0; i < kHaloSlots; ++i) {
+    h.own[i] = tid + i * B < S;
+    const int s = min(tid + i * B, S - 1);
+    int lx, ly, x, y;
+    if (s < 8 * TX) {  // four rows below, then four above: TX consecutive points each
+      const int side = s / (4 * TX), j = (s / TX) % 4, c = s % TX;
+      lx = c + 4;
+      ly = side ? TY + 4 + j : j;
+      x = x0 + c;
+      y = side ? y0 + TY + j : y0 - 4 + j;
+    } else {  // four columns left, then four right, by row
+      const int r = s - 8 * TX;
+      const int side = r / (4 * TY), row = (r / 4) % TY, j = r % 4;
+      lx = side ? TX + 4 + j : j;
+      ly = row + 4;
+      x = side ? x0 + TX + j : x0 - 4 + j;
+      y = y0 + row;
+    }
+    bool in = true;
+    if (periodic) {
+      x = (x + n1) % n1;
+      y = (y + n2) % n2;
+    } else {
+      in = x >= 0 && x < n1 && y >= 0 && y < n2;
+      x = min(max(x, 0), n1 - 1);
+      y = min(max(y, 0), n2 - 1);
+    }
+    h.lds[i] = ly * LW + lx;
+    h.off[i] = (unsigned)(y * n1 + x);
+    h.in[i] = in;
+    h.stage[i] = h.own[i] & in;
+  }
+  return h;
+}
+
+// The z loop in rounds of PF planes, plane z + S of a round using prefetch
+// slot S (a compile-time index, so every slot stays in its own registers), then
+// the last planes of an incomplete round. Every full round issues the same
+// loads, which keeps the compiler's wait counts exact.
+template <class F, int... S>
+__device__ __forceinline__ void round_steps(F& f, int z, std::integer_sequence<int, S...>) {
+  (f(z + S, std::integral_constant<int, S>{}), ...);
+}
+template <class F, int... S>
+__device__ __forceinline__ void tail_steps(F& f, int z, int z1, std::integer_sequence<int, S...>) {
+  ((z + S < z1 ? (f(z + S, std::integral_constant<int, S>{}), 0) : 0), ...);
+}
+template <int PF, class F>
+__device__ __forceinline__ void run_planes(int z0, int z1, F& f) {
+  int z = z0;
+  for (; z + PF <= z1; z += PF) round_steps(f, z, std::make_integer_sequence<int, PF>{});
+  if (z < z1) tail_steps(f, z, z1, std::make_integer_sequence<int, PF - 1>{});
+}
+
+// planes of u, w, V and the halo in flight ahead of the current one: two for
+// complex FP32, one for complex128 (whose queue holds twice the registers)
+template <typename T, int BC>
+constexpr int stage_prefetch() {
+  return sizeof(T) == 4 ? 2 : 1;
+}
+
+// Loads in the z loop are issued unconditionally at in-bounds plane indices
+// (wrapped, or clamped past the ends of an isolated grid and of the slab) and
+// zero is selected only where a value is consumed, planes later. A load
+// under a branch, or a select right after it, makes the compiler wait for it
+// on the spot (and a branch around a load whose alternative is a constant can
+// become a flat load, which the LDS wait before the barrier also waits for):
+// either undoes the prefetch.
 template <typename T, int MODE, int BC>
 __global__ __launch_bounds__(1024) void k_stage(StageArgs<T> a) {
   using T2 = typename Vec2<T>::type;
@@ -62,8 +214,8 @@ __global__ __launch_bounds__(1024) void k_stage(StageArgs<T> a) {
   const int tid = threadIdx.x;
   const int tx = tid % TX, ty = tid / TX;
   const bool active = ty < TY;
-  const int gx = (tile % g.tiles_x) * TX + tx;
-  const int gy = (tile / g.tiles_x) * TY + ty;
+  const int x0 = (tile % g.tiles_x) * TX, y0 = (tile / g.tiles_x) * TY;
+  const int gx = x0 + tx, gy = y0 + ty;
 
   const int LW = (BC == kPeriodicPlane) ? n1 : TX + 8;
   const int LH = (BC == kPeriodicPlane) ? n2 : TY + 8;
@@ -72,47 +224,42 @@ __global__ __launch_bounds__(1024) void k_stage(StageArgs<T> a) {
   const int ly = (BC == kPeriodicPlane) ? ty : ty + 4;
   const int lc = ly * LW + lx;
 
+  // LDS places of the x/y neighbours: a table of wrapped places for a whole
+  // periodic plane, lc +- m and lc +- m LW (uniform multiples, no vector
+  // registers) for a tile with its halo
   int oxp[4], oxm[4], oyp[4], oym[4];
+  if (BC == kPeriodicPlane) {
 #pragma unroll
-  for (int m = 1; m <= 4; ++m) {
-    if (BC == kPeriodicPlane) {
+    for (int m = 1; m <= 4; ++m) {
       oxp[m - 1] = ly * LW + (tx + m) % n1;
       oxm[m - 1] = ly * LW + (tx - m + n1) % n1;
       oyp[m - 1] = ((ty + m) % n2) * LW + lx;
       oym[m - 1] = ((ty - m + n2) % n2) * LW + lx;
-    } else {
-      oxp[m - 1] = lc + m;
-      oxm[m - 1] = lc - m;
-      oyp[m - 1] = lc + m * LW;
-      oym[m - 1] = lc - m * LW;
     }
   }
+  auto XP = [&](int m) { return BC == kPeriodicPlane ? oxp[m] : lc + (m + 1); };
+  auto XM = [&](int m) { return BC == kPeriodicPlane ? oxm[m] : lc - (m + 1); };
+  auto YP = [&](int m) { return BC == kPeriodicPlane ? oyp[m] : lc + (m + 1) * LW; };
+  auto YM = [&](int m) { return BC == kPeriodicPlane ? oym[m] : lc - (m + 1) * LW; };
 
   const size_t base = (size_t)o * N;
-  const int col = gy * n1 + gx;
+  // idle threads of the last wave read column 0 and store nothing; every
+  // global access is a uniform plane pointer plus this unsigned lane offset
+  const unsigned col = active ? (unsigned)(gy * n1 + gx) : 0u;
+  const unsigned colb = col * (unsigned)sizeof(T2), colv = col * (unsigned)sizeof(T);
   const T2* __restrict__ src = a.in + base;
   const T2 z2 = zero2<T2>();
   const bool periodic = (BC != kIsolatedTile);
-
-  auto load_col = [&](int z) -> T2 {
-    if (!active) return z2;
-    if (!periodic && (z < 0 || z >= n3)) return z2;
-    int zz = z;
+  // plane index of the column load for plane z: wrapped, or clamped (the
+  // value is replaced by zero where it is used)
+  auto zidx = [&](int z) -> int {
     if (periodic) {
-      zz = z % n3;
-      if (zz < 0) zz += n3;
+      int zz = z % n3;
+      return zz < 0 ? zz + n3 : zz;
     }
-    return src[(size_t)zz * plane + col];
+    return min(max(z, 0), n3 - 1);
   };
-  auto load_xy = [&](int x, int y, int z) -> T2 {
-    if (periodic) {
-      x = (x % n1 + n1) % n1;
-      y = (y % n2 + n2) % n2;
-    } else if (x < 0 || x >= n1 || y < 0 || y >= n2) {
-      return z2;
-    }
-    return src[(size_t)z * plane + y * n1 + x];
-  };
+  auto zin = [&](int z) -> bool { return periodic || (z >= 0 && z < n3); };
 
   // per-step, per-k coefficients (uniform across the workgroup): the k-point's
   // table row is read with scalar loads and the weights come as stage-precision
@@ -128,115 +275,113 @@ __global__ __launch_bounds__(1024) void k_stage(StageArgs<T> a) {
     by[m] = ck[4 + m];
     bz[m] = ck[8 + m];
   }
-  const T diag_t = ck[12];
   const T tau = (T)a.tau;
   const T tau_re = (T)a.tau_re;
-  T ext = 0, ez = 0;
+  // diagonal without V: kinetic |kappa|^2 / 2 and, in the length gauge, the
+  // field's in-plane part E_x x + E_y y (the z part is added per plane)
+  T dgx = ck[12], ez = 0;
   if (a.efield) {
     const double xr = (gx - 0.5 * (n1 - 1)) * g.h1;
     const double yr = (gy - 0.5 * (n2 - 1)) * g.h2;
-    ext = (T)(a.efield[0] * xr + a.efield[1] * yr);
+    dgx += (T)(a.efield[0] * xr + a.efield[1] * yr);
     ez = (T)(a.efield[2] * g.h3);
   }
   const T zc = (T)(0.5 * (n3 - 1));
 
-  // u, w and V are fetched PF planes ahead of their use, so that a plane's
-  // loads have that many barrier-separated iterations to arrive
+  HaloSlots hs{};
+  if (BC != kPeriodicPlane) {
+    hs = halo_slots(tid, (int)blockDim.x, TX, TY, LW, x0, y0, n1, n2, periodic);
+#pragma unroll
+    for (int i = 0; i < kHaloSlots; ++i) hs.off[i] *= (unsigned)sizeof(T2);  // bytes
+    // halo points outside an isolated grid are zero on every plane: staged
+    // once in both buffers and never written again
+#pragma unroll
+    for (int i = 0; i < kHaloSlots; ++i)
+      if (hs.own[i] && !hs.in[i]) lds[hs.lds[i]] = lds[lsz + hs.lds[i]] = z2;
+  }
+
   constexpr int PF = stage_prefetch<T, BC>();
   T2 q[9];
 #pragma unroll
-  for (int i = 0; i < 8; ++i) q[i] = load_col(z0 + i - 4);
-  T2 nxt[PF];
-#pragma unroll
-  for (int d = 0; d < PF; ++d) nxt[d] = load_col(z0 + 4 + d);
-  T2 wr[PF];
+  for (int i = 0; i < 8; ++i) {
+    const T2 v = load2(at(src + (size_t)zidx(z0 + i - 4) * plane, colb));
+    q[i] = keep_if(zin(z0 + i - 4), v);
+  }
+  // slot d holds the column of plane z + 4 and w, V and the halo of plane z
+  // for the planes z = z0 + d (mod PF); the loop is unrolled by PF so that a
+  // slot's registers keep their loads until they are used (a register
+  // rotation would move, and so wait for, values still in flight)
+  T2 nxt[PF], wr[PF], hv[PF][kHaloSlots];
   T vr[PF];
+  auto fetch = [&](int d, int zp) __attribute__((always_inline)) {  // plane zp into slot d (clamped past the end)
+    const size_t pd = (size_t)min(zp, n3 - 1) * plane;
+    const T2* __restrict__ sp = src + pd;
+    nxt[d] = load2(at(src + (size_t)zidx(zp + 4) * plane, colb));
+    if (MODE != kFirst) wr[d] = load_once(at(a.w + base + pd, colb));
+    vr[d] = *at(a.V + pd, colv);
+#pragma unroll
+    for (int i = 0; i < kHaloSlots; ++i)
+      if (BC != kPeriodicPlane) hv[d][i] = load2(at(sp, hs.off[i]));
+  };
+  // slots issued in order (the first plane's wait counts on it)
 #pragma unroll
   for (int d = 0; d < PF; ++d) {
     wr[d] = z2;
-    vr[d] = 0;
-    if (active && z0 + d < z1) {
-      if (MODE != kFirst) wr[d] = a.w[base + (size_t)(z0 + d) * plane + col];
-      vr[d] = a.V[(size_t)(z0 + d) * plane + col];
-    }
+    fetch(d, z0 + d);
+    __builtin_amdgcn_sched_barrier(0);
   }
 
-  // tile-edge threads also stage the x/y halo of their tile (4 points out,
-  // wrapped or zero), one plane ahead like the column values
-  const bool hxm = BC != kPeriodicPlane && active && tx < 4;
-  const bool hxp = BC != kPeriodicPlane && active && tx >= TX - 4;
-  const bool hym = BC != kPeriodicPlane && active && ty < 4;
-  const bool hyp = BC != kPeriodicPlane && active && ty >= TY - 4;
-  T2 hal[4] = {z2, z2, z2, z2};
-  auto load_halo = [&](int z) {
-    if (hxm) hal[0] = load_xy(gx - 4, gy, z);
-    if (hxp) hal[1] = load_xy(gx + 4, gy, z);
-    if (hym) hal[2] = load_xy(gx, gy - 4, z);
-    if (hyp) hal[3] = load_xy(gx, gy + 4, z);
-  };
-  if (BC != kPeriodicPlane) load_halo(z0);
-
-  for (int z = z0; z < z1; ++z) {
-    q[8] = nxt[0];
-    const size_t pz = (size_t)z * plane + col;
-    T2 wv = (MODE == kFirst) ? q[4] : wr[0];
-    const T vv = vr[0];
-#pragma unroll
-    for (int d = 0; d + 1 < PF; ++d) {
-      nxt[d] = nxt[d + 1];
-      wr[d] = wr[d + 1];
-      vr[d] = vr[d + 1];
-    }
-    if (z + PF < z1) {
-      nxt[PF - 1] = load_col(z + 4 + PF);
-      if (active) {
-        if (MODE != kFirst) wr[PF - 1] = a.w[base + pz + (size_t)PF * plane];
-        vr[PF - 1] = a.V[pz + (size_t)PF * plane];
-      }
-    }
-
+  auto plane_step = [&](int z, auto slot) __attribute__((always_inline)) {
+    constexpr int d = decltype(slot)::value;
+    q[8] = keep_if(zin(z + 4), nxt[d]);
+    const T2 wv = (MODE == kFirst) ? q[4] : wr[d];
+    const T vv = vr[d];
     T2* buf = lds + (z & 1) * lsz;
-    if (active) {
-      buf[lc] = q[4];
-      if (BC != kPeriodicPlane) {
-        // this plane's halo values, loaded one plane ahead
-        if (hxm) buf[lc - 4] = hal[0];
-        if (hxp) buf[lc + 4] = hal[1];
-        if (hym) buf[lc - 4 * LW] = hal[2];
-        if (hyp) buf[lc + 4 * LW] = hal[3];
-        if (z + 1 < z1) load_halo(z + 1);
-      }
-    }
+    if (active) buf[lc] = q[4];
+#pragma unroll
+    for (int i = 0; i < kHaloSlots; ++i)
+      if (BC != kPeriodicPlane && hs.stage[i]) store2(buf + hs.lds[i], hv[d][i]);
+    fetch(d, z + PF);
     __syncthreads();
 
     if (active) {
       const T2 u = q[4];
-      T dg = diag_t + vv;
-      if (a.efield) dg += ext + ez * ((T)z - zc);
+      T dg = dgx + vv;
+      if (a.efield) dg = fmat(ez, (T)z - zc, dg);
+      // h u as fused multiply-adds into two accumulators (real, imaginary)
       T hr = dg * u.x;
       T hi = dg * u.y;
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
-        T2 p = buf[oxp[m]], n = buf[oxm[m]];
-        hr += cx[m] * (p.x + n.x) + bx[m] * (p.y - n.y);
-        hi += cx[m] * (p.y + n.y) - bx[m] * (p.x - n.x);
-        p = buf[oyp[m]];
-        n = buf[oym[m]];
-        hr += cy[m] * (p.x + n.x) + by[m] * (p.y - n.y);
-        hi += cy[m] * (p.y + n.y) - by[m] * (p.x - n.x);
+        T2 p = buf[XP(m)], n = buf[XM(m)];
+        hr = fmat(cx[m], p.x + n.x, hr);
+        hr = fmat(bx[m], p.y - n.y, hr);
+        hi = fmat(cx[m], p.y + n.y, hi);
+        hi = fmat(-bx[m], p.x - n.x, hi);
+        p = buf[YP(m)];
+        n = buf[YM(m)];
+        hr = fmat(cy[m], p.x + n.x, hr);
+        hr = fmat(by[m], p.y - n.y, hr);
+        hi = fmat(cy[m], p.y + n.y, hi);
+        hi = fmat(-by[m], p.x - n.x, hi);
         p = q[5 + m];
         n = q[3 - m];
-        hr += cz[m] * (p.x + n.x) + bz[m] * (p.y - n.y);
-        hi += cz[m] * (p.y + n.y) - bz[m] * (p.x - n.x);
+        hr = fmat(cz[m], p.x + n.x, hr);
+        hr = fmat(bz[m], p.y - n.y, hr);
+        hi = fmat(cz[m], p.y + n.y, hi);
+        hi = fmat(-bz[m], p.x - n.x, hi);
       }
+      // u_{s-1} = w + (tau_re - i tau) h u_s
       T2 res;
-      res.x = wv.x + tau * hi + tau_re * hr;
-      res.y = wv.y - tau * hr + tau_re * hi;
-      a.out[base + pz] = res;
+      res.x = fmat(tau, hi, fmat(tau_re, hr, wv.x));
+      res.y = fmat(-tau, hr, fmat(tau_re, hi, wv.y));
+      store_once(at(a.out + base + (size_t)z * plane, colb), res);
     }
 #pragma unroll
     for (int i = 0; i < 8; ++i) q[i] = q[i + 1];
-  }
+  };
+
+  run_planes<PF>(z0, z1, plane_step);
 }
 
 // Nonlocal term of a stage, added to u_{s-1} after the local part:
@@ -338,98 +483,101 @@ __global__ __launch_bounds__(1024) void k_observe(ObserveArgs<T> a) {
   const int tid = threadIdx.x;
   const int tx = tid % TX, ty = tid / TX;
   const bool active = ty < TY;
-  const int gx = (tile % g.tiles_x) * TX + tx;
-  const int gy = (tile / g.tiles_x) * TY + ty;
+  const int x0 = (tile % g.tiles_x) * TX, y0 = (tile / g.tiles_x) * TY;
+  const int gx = x0 + tx, gy = y0 + ty;
   const int LW = (BC == kPeriodicPlane) ? n1 : TX + 8;
   const int LH = (BC == kPeriodicPlane) ? n2 : TY + 8;
   const int lsz = LW * LH;
   const int lx = (BC == kPeriodicPlane) ? tx : tx + 4;
   const int ly = (BC == kPeriodicPlane) ? ty : ty + 4;
   const int lc = ly * LW + lx;
+  // LDS places of the x/y neighbours: a table of wrapped places for a whole
+  // periodic plane, lc +- m and lc +- m LW (uniform multiples, no vector
+  // registers) for a tile with its halo
   int oxp[4], oxm[4], oyp[4], oym[4];
+  if (BC == kPeriodicPlane) {
 #pragma unroll
-  for (int m = 1; m <= 4; ++m) {
-    if (BC == kPeriodicPlane) {
+    for (int m = 1; m <= 4; ++m) {
       oxp[m - 1] = ly * LW + (tx + m) % n1;
       oxm[m - 1] = ly * LW + (tx - m + n1) % n1;
       oyp[m - 1] = ((ty + m) % n2) * LW + lx;
       oym[m - 1] = ((ty - m + n2) % n2) * LW + lx;
-    } else {
-      oxp[m - 1] = lc + m;
-      oxm[m - 1] = lc - m;
-      oyp[m - 1] = lc + m * LW;
-      oym[m - 1] = lc - m * LW;
     }
   }
+  auto XP = [&](int m) { return BC == kPeriodicPlane ? oxp[m] : lc + (m + 1); };
+  auto XM = [&](int m) { return BC == kPeriodicPlane ? oxm[m] : lc - (m + 1); };
+  auto YP = [&](int m) { return BC == kPeriodicPlane ? oyp[m] : lc + (m + 1) * LW; };
+  auto YM = [&](int m) { return BC == kPeriodicPlane ? oym[m] : lc - (m + 1) * LW; };
   const size_t base = (size_t)o * N;
-  const int col = gy * n1 + gx;
+  const unsigned col = active ? (unsigned)(gy * n1 + gx) : 0u;
+  const unsigned colb = col * (unsigned)sizeof(T2), cold = col * (unsigned)sizeof(double);
   const T2* __restrict__ src = a.w + base;
   const bool periodic = (BC != kIsolatedTile);
   // differences and weighted sums in the stage precision, products and the
   // running sums in FP64 (the same arithmetic as before for complex128)
   const T2 zt = zero2<T2>();
-  auto load_col = [&](int z) -> T2 {
-    if (!active) return zt;
-    if (!periodic && (z < 0 || z >= n3)) return zt;
-    int zz = z;
+  // branch-free prefetch as in k_stage: loads at wrapped or clamped plane
+  // indices, zero selected where a value is used
+  auto zidx = [&](int z) -> int {
     if (periodic) {
-      zz = z % n3;
-      if (zz < 0) zz += n3;
+      int zz = z % n3;
+      return zz < 0 ? zz + n3 : zz;
     }
-    return src[(size_t)zz * plane + col];
+    return min(max(z, 0), n3 - 1);
   };
-  auto load_xy = [&](int x, int y, int z) -> T2 {
-    if (periodic) {
-      x = (x % n1 + n1) % n1;
-      y = (y % n2 + n2) % n2;
-    } else if (x < 0 || x >= n1 || y < 0 || y >= n2) {
-      return zt;
-    }
-    return src[(size_t)z * plane + y * n1 + x];
-  };
-  // weights: the FP64 kernel arguments themselves for complex128, a copy in
-  // FP32 registers for complex FP32
-  T cl[3][4], cd[3][4];
-  if constexpr (sizeof(T) == 4) {
-#pragma unroll
-    for (int mu = 0; mu < 3; ++mu)
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        cl[mu][m] = (T)a.lap[mu][m + 1];
-        cd[mu][m] = (T)a.dh[mu][m];
-      }
-  }
-  auto CL = [&](int mu, int m) -> T {
-    if constexpr (sizeof(T) == 8) return a.lap[mu][m + 1];
-    else return cl[mu][m];
-  };
-  auto CD = [&](int mu, int m) -> T {
-    if constexpr (sizeof(T) == 8) return a.dh[mu][m];
-    else return cd[mu][m];
-  };
+  auto zin = [&](int z) -> bool { return periodic || (z >= 0 && z < n3); };
+  // weights in the stage precision, from the kernel arguments (the FP64
+  // values themselves for complex128)
+  auto CL = [&](int mu, int m) -> T { return a.cl[mu][m]; };
+  auto CD = [&](int mu, int m) -> T { return a.cd[mu][m]; };
   const T cdiag = (T)a.cdiag;
 
+  HaloSlots hs{};
+  if (BC != kPeriodicPlane) {
+    hs = halo_slots(tid, (int)blockDim.x, TX, TY, LW, x0, y0, n1, n2, periodic);
+#pragma unroll
+    for (int i = 0; i < kHaloSlots; ++i) hs.off[i] *= (unsigned)sizeof(T2);  // bytes
+#pragma unroll
+    for (int i = 0; i < kHaloSlots; ++i)
+      if (hs.own[i] && !hs.in[i]) lds[hs.lds[i]] = lds[lsz + hs.lds[i]] = zt;
+  }
+
+  constexpr int PF = stage_prefetch<T, BC>();
   double s_norm = 0, s_px = 0, s_py = 0, s_pz = 0, s_kin = 0, s_v = 0;
   T2 q[9];
 #pragma unroll
-  for (int i = 0; i < 8; ++i) q[i] = load_col(z0 + i - 4);
-  T2 nxt = load_col(z0 + 4);  // the column one plane ahead, and V_loc
-  double vl_nxt = active ? a.Vloc[(size_t)z0 * plane + col] : 0.0;
-  for (int z = z0; z < z1; ++z) {
-    q[8] = nxt;
-    if (z + 1 < z1) nxt = load_col(z + 5);
-    const double vl = vl_nxt;
-    if (active && z + 1 < z1) vl_nxt = a.Vloc[(size_t)(z + 1) * plane + col];
+  for (int i = 0; i < 8; ++i) {
+    const T2 v = load2(at(src + (size_t)zidx(z0 + i - 4) * plane, colb));
+    q[i] = keep_if(zin(z0 + i - 4), v);
+  }
+  // slots as in k_stage: column of plane z + 4, V_loc and the halo of plane z
+  T2 nxt[PF], hv[PF][kHaloSlots];
+  double vl[PF];
+  auto fetch = [&](int d, int zp) __attribute__((always_inline)) {
+    const size_t pd = (size_t)min(zp, n3 - 1) * plane;
+    const T2* __restrict__ sp = src + pd;
+    nxt[d] = load2(at(src + (size_t)zidx(zp + 4) * plane, colb));
+    vl[d] = *at(a.Vloc + pd, cold);
+#pragma unroll
+    for (int i = 0; i < kHaloSlots; ++i)
+      if (BC != kPeriodicPlane) hv[d][i] = load2(at(sp, hs.off[i]));
+  };
+#pragma unroll
+  for (int d = 0; d < PF; ++d) {
+    fetch(d, z0 + d);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+
+  auto plane_step = [&](int z, auto slot) __attribute__((always_inline)) {
+    constexpr int d = decltype(slot)::value;
+    q[8] = keep_if(zin(z + 4), nxt[d]);
+    const double vz = vl[d];
     T2* buf = lds + (z & 1) * lsz;
-    if (active) {
-      buf[lc] = q[4];
-      if (BC != kPeriodicPlane) {
-        if (tx < 4) buf[lc - 4] = load_xy(gx - 4, gy, z);
-        if (tx >= TX - 4) buf[lc + 4] = load_xy(gx + 4, gy, z);
-        if (ty < 4) buf[lc - 4 * LW] = load_xy(gx, gy - 4, z);
-        if (ty >= TY - 4) buf[lc + 4 * LW] = load_xy(gx, gy + 4, z);
-      }
-    }
+    if (active) buf[lc] = q[4];
+#pragma unroll
+    for (int i = 0; i < kHaloSlots; ++i)
+      if (BC != kPeriodicPlane && hs.stage[i]) store2(buf + hs.lds[i], hv[d][i]);
+    fetch(d, z + PF);
     __syncthreads();
     if (active) {
       const T2 u = q[4];
@@ -437,36 +585,38 @@ __global__ __launch_bounds__(1024) void k_observe(ObserveArgs<T> a) {
       T dxr = 0, dxi = 0, dyr = 0, dyi = 0, dzr = 0, dzi = 0;
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
-        T2 p = buf[oxp[m]], n = buf[oxm[m]];
-        lr += CL(0, m) * (p.x + n.x);
-        li += CL(0, m) * (p.y + n.y);
-        dxr += CD(0, m) * (p.x - n.x);
-        dxi += CD(0, m) * (p.y - n.y);
-        p = buf[oyp[m]];
-        n = buf[oym[m]];
-        lr += CL(1, m) * (p.x + n.x);
-        li += CL(1, m) * (p.y + n.y);
-        dyr += CD(1, m) * (p.x - n.x);
-        dyi += CD(1, m) * (p.y - n.y);
+        T2 p = buf[XP(m)], n = buf[XM(m)];
+        lr = fmat(CL(0, m), p.x + n.x, lr);
+        li = fmat(CL(0, m), p.y + n.y, li);
+        dxr = fmat(CD(0, m), p.x - n.x, dxr);
+        dxi = fmat(CD(0, m), p.y - n.y, dxi);
+        p = buf[YP(m)];
+        n = buf[YM(m)];
+        lr = fmat(CL(1, m), p.x + n.x, lr);
+        li = fmat(CL(1, m), p.y + n.y, li);
+        dyr = fmat(CD(1, m), p.x - n.x, dyr);
+        dyi = fmat(CD(1, m), p.y - n.y, dyi);
         p = q[5 + m];
         n = q[3 - m];
-        lr += CL(2, m) * (p.x + n.x);
-        li += CL(2, m) * (p.y + n.y);
-        dzr += CD(2, m) * (p.x - n.x);
-        dzi += CD(2, m) * (p.y - n.y);
+        lr = fmat(CL(2, m), p.x + n.x, lr);
+        li = fmat(CL(2, m), p.y + n.y, li);
+        dzr = fmat(CD(2, m), p.x - n.x, dzr);
+        dzi = fmat(CD(2, m), p.y - n.y, dzi);
       }
       const double ux = (double)u.x, uy = (double)u.y;
-      const double nn = ux * ux + uy * uy;
+      const double nn = fmat(ux, ux, uy * uy);
       s_norm += nn;
-      s_px += ux * (double)dxi - uy * (double)dxr;
-      s_py += ux * (double)dyi - uy * (double)dyr;
-      s_pz += ux * (double)dzi - uy * (double)dzr;
-      s_kin += ux * (double)lr + uy * (double)li;
-      s_v += vl * nn;
+      s_px = fmat(ux, (double)dxi, fmat(-uy, (double)dxr, s_px));
+      s_py = fmat(ux, (double)dyi, fmat(-uy, (double)dyr, s_py));
+      s_pz = fmat(ux, (double)dzi, fmat(-uy, (double)dzr, s_pz));
+      s_kin = fmat(ux, (double)lr, fmat(uy, (double)li, s_kin));
+      s_v = fmat(vz, nn, s_v);
     }
 #pragma unroll
     for (int i = 0; i < 8; ++i) q[i] = q[i + 1];
-  }
+  };
+
+  run_planes<PF>(z0, z1, plane_step);
   double v[6] = {s_norm, s_px, s_py, s_pz, s_kin, s_v};
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
