@@ -314,18 +314,24 @@ def bench_mgga(system, precision, lda_ms, steps=60, warmup=10):
             "fused_ms": kern["fused_ms"], "current_finite": bool(np.all(np.isfinite(J)))}
 
 
-def mfma_projection(system, project_ms, stage_mode=True):
-    """MFMA work of one projection launch (per-stage path): one 16x16x4 FP64
-    MFMA per four sphere entries, per atom and group of eight orbitals; in the
-    stage mode 4 of its 16 columns (the m = 0 moment of each projector) are
-    used, so the useful flops are a quarter of the issued ones."""
-    n_groups = (system.n_orb * system.n_k + 7) // 8
-    issued = sum(n_groups * -(-p.npts // 4) * 2 * 16 * 16 * 4 for p in system.projectors)
-    useful = issued / 4 if stage_mode else issued
+def mfma_projection(system, project_ms, esz):
+    """MFMA work of one stage-mode projection launch (per-stage path): one
+    four-block 4x4x4 FP64 MFMA (512 flops) per four sphere entries, per atom
+    and group of eight orbitals; every product is used except the padding of
+    the last orbital group and of the last four entries of a sphere. The
+    launch is bound by the sphere gathers (one orbital value per entry and
+    orbital, esz bytes), reported as gather_GBs."""
+    n_tot = system.n_orb * system.n_k
+    n_groups = (n_tot + 7) // 8
+    issued = sum(n_groups * -(-p.npts // 4) * 512 for p in system.projectors)
+    useful = sum(n_tot * 2 * kmax * p.npts * 2 for p in system.projectors for kmax in (4,))
+    gathered = sum(n_tot * p.npts * esz for p in system.projectors)
     t = project_ms * 1e-3
-    return {"issued_tflops": issued / t / 1e12, "useful_tflops": useful / t / 1e12,
-            "peak": FP64_MFMA_PEAK_TFLOPS, "frac_issued": issued / t / 1e12 / FP64_MFMA_PEAK_TFLOPS,
-            "frac_useful": useful / t / 1e12 / FP64_MFMA_PEAK_TFLOPS, "ms_per_launch": project_ms}
+    return {"instruction": "v_mfma_f64_4x4x4f64", "issued_tflops": issued / t / 1e12,
+            "useful_tflops": useful / t / 1e12, "peak": FP64_MFMA_PEAK_TFLOPS,
+            "frac_issued": issued / t / 1e12 / FP64_MFMA_PEAK_TFLOPS,
+            "frac_useful": useful / t / 1e12 / FP64_MFMA_PEAK_TFLOPS,
+            "gather_GBs": gathered / t / 1e9, "ms_per_launch": project_ms}
 
 
 def per_stage_figures(system, kern, esz):
@@ -357,7 +363,7 @@ def bench_cluster(steps=5, warmup=2, n_orb=512):
            "steps": steps, "warmup": warmup, "input_generation_s": t_gen,
            "current_finite": bool(np.all(np.isfinite(J)))}
     out.update(per_stage_figures(s, kern, 8))
-    out["mfma_projection"] = mfma_projection(s, kern["project_ms"])
+    out["mfma_projection"] = mfma_projection(s, kern["project_ms"], 8)
     return out
 
 
@@ -618,7 +624,7 @@ def main():
         "flops_per_og_step": step_flops_per_og(s),
         "kernels_ms": kern,
         "per_stage_path": per_stage_figures(s, kern, esz),
-        "mfma_projection": mfma_projection(s, kern["project_ms"]),
+        "mfma_projection": mfma_projection(s, kern["project_ms"], esz),
         "current_finite": bool(np.all(np.isfinite(J))),
     }
     if not args.no_twin:

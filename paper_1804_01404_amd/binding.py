@@ -472,6 +472,22 @@ def mfma_layout_check(A: np.ndarray, B: np.ndarray) -> np.ndarray:
     return D
 
 
+def mfma44_layout_check(A: np.ndarray, B: np.ndarray) -> np.ndarray:
+    """Run one v_mfma_f64_4x4x4f64 (four blocks) with the lane layout the
+    stage projection assumes; A, B [4][4][4]; returns D [4][4][4] for
+    comparison with A[b] @ B[b]."""
+    lib = load_library()
+    fn = lib.tddft_test_mfma44_layout
+    fn.argtypes = [_dp, _dp, _dp]
+    fn.restype = C.c_int
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    B = np.ascontiguousarray(B, dtype=np.float64)
+    D = np.zeros((4, 4, 4))
+    if fn(_ptr(A), _ptr(B), _ptr(D)) != 0:
+        raise RuntimeError("mfma layout check failed to run")
+    return D
+
+
 def _config_for(system, precision, flags):
     s = system
     cfg = Config()

@@ -21,6 +21,25 @@
 
 namespace td {
 
+// Global-memory views of the argument pointers. The persistent kernel reads
+// its arguments from a device array, and a pointer loaded from memory is a
+// generic (flat) pointer to the compiler; flat accesses also count on the LDS
+// counter, so every LDS wait would wait for them. Accesses through these
+// views are plain global (or scalar) loads and stores.
+// (The host pass of this single-source file also parses the device templates;
+// the address space exists only in the device pass.)
+#if defined(__HIP_DEVICE_COMPILE__)
+template <class X>
+using gp = __attribute__((address_space(1))) X*;
+#else
+template <class X>
+using gp = X*;
+#endif
+template <class X>
+__device__ __forceinline__ gp<X> G(X* p) {
+  return (gp<X>)p;
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -125,9 +144,9 @@ __device__ __forceinline__ typename Vec2<T>::type lds_xy(const typename Vec2<T>:
 
 // h u_s (local part) and the Horner update for the planes Z0 .. Z0 + ZN - 1
 template <typename T, int N, int ZN, int Z0, bool PERIODIC>
-__device__ __forceinline__ void stencil_part(const typename Vec2<T>::type* u, const T* __restrict__ V,
+__device__ __forceinline__ void stencil_part(const typename Vec2<T>::type* u, gp<const T> V,
                                              const Coef<T>& cf, const Nbr& nb, const bool (&ok)[16],
-                                             const typename Vec2<T>::type* __restrict__ wg,
+                                             gp<const typename Vec2<T>::type> wg,
                                              typename Vec2<T>::type (&un)[ZN], T tau, bool length) {
   using T2 = typename Vec2<T>::type;
   constexpr int plane = N * N;
@@ -213,6 +232,14 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, const int o, u
   constexpr int HALF = ((plane + 63) / 64) * 64;  // threads per column half (whole waves)
   const int n_atoms = a.nl.n_atoms;
   const int S = a.nl.n_ent;
+  const gp<const int> atom_start = G(a.nl.atom_start);
+  const gp<const int> ent_idx = G(a.nl.ent_idx);
+  const gp<const double> atom_E = G(a.nl.atom_E);
+  const gp<const double> ent_beta = G(a.ent_beta);
+  const gp<const double> ent_x = G(a.ent_x);
+  const gp<const int> color_start = G(a.color_start);
+  const gp<const int> color_atoms = G(a.color_atoms);
+  const gp<const double2> phAJ = G(a.phAJ);
   T2* u = reinterpret_cast<T2*>(smem_raw);
   constexpr size_t ubytes = ((size_t)NP * sizeof(T2) + 15) & ~(size_t)15;
   double2* eu = reinterpret_cast<double2*>(smem_raw + ubytes);               // [n_atoms][4]
@@ -243,7 +270,7 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, const int o, u
   }
   nb.c = active ? ctid : 0;
 
-  T2* __restrict__ wg = a.w + (size_t)o * NP;
+  const gp<T2> wg = G(a.w) + (size_t)o * NP;
   T2 un[ZN];
   const int z0 = half * ZN;
 #pragma unroll
@@ -257,7 +284,7 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, const int o, u
   Coef<T> cf;
   {
     // wave-uniform: the k-point table is read with scalar loads
-    const T* __restrict__ ck = a.coef + (size_t)k * kCoef;
+    const gp<const T> ck = G(a.coef) + (size_t)k * kCoef;
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
       cf.cx[m] = a.lapc[0][m];
@@ -271,30 +298,31 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, const int o, u
     cf.ext = cf.ez = 0;
     if (!PERIODIC && a.efield) {
       // E . r with r from the box centre; the z part is added per plane
-      cf.ext = (T)(a.efield[0] * (tx - 0.5 * (N - 1)) * a.g.h1 + a.efield[1] * (ty - 0.5 * (N - 1)) * a.g.h2 -
-                   a.efield[2] * a.g.h3 * 0.5 * (N - 1));
-      cf.ez = (T)(a.efield[2] * a.g.h3);
+      const gp<const double> ef = G(a.efield);
+      cf.ext = (T)(ef[0] * (tx - 0.5 * (N - 1)) * a.g.h1 + ef[1] * (ty - 0.5 * (N - 1)) * a.g.h2 -
+                   ef[2] * a.g.h3 * 0.5 * (N - 1));
+      cf.ez = (T)(ef[2] * a.g.h3);
     }
   }
   const bool length = !PERIODIC && a.efield != nullptr;
-  const double2* __restrict__ phk = a.nl.phk + (size_t)k * S;
-  const double2* __restrict__ phkA = a.phkA + (size_t)k * S;  // exp(i kappa . x_e) of this step
+  const gp<const double2> phk = G(a.nl.phk) + (size_t)k * S;
+  const gp<const double2> phkA = G(a.phkA) + (size_t)k * S;  // exp(i kappa . x_e) of this step
   __syncthreads();
 
   // ---- projections of u_s: one wavefront per atom, FP64
   auto project = [&]() {
     for (int at = wave; at < n_atoms; at += nwaves) {
-      const int e0 = a.nl.atom_start[at], e1 = a.nl.atom_start[at + 1];
+      const int e0 = atom_start[at], e1 = atom_start[at + 1];
       double acc[2 * kMaxProj] = {0, 0, 0, 0, 0, 0, 0, 0};
       for (int e = e0 + lane; e < e1; e += 64) {
-        const T2 v = u[a.nl.ent_idx[e]];
+        const T2 v = u[ent_idx[e]];
         const double2 ph = phkA[e];
         const double pr = ph.x, pim = ph.y;
         const double gr = pr * (double)v.x - pim * (double)v.y;
         const double gi = pr * (double)v.y + pim * (double)v.x;
 #pragma unroll
         for (int p = 0; p < kMaxProj; ++p) {
-          const double b = a.ent_beta[(size_t)e * kMaxProj + p];
+          const double b = ent_beta[(size_t)e * kMaxProj + p];
           acc[2 * p] += b * gr;
           acc[2 * p + 1] += b * gi;
         }
@@ -304,7 +332,7 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, const int o, u
       const double im = __shfl_down(tot, 8, 64);
       if ((lane & 15) == 0) {
         const int p = lane >> 4;
-        const double E = a.nl.atom_E[at * kMaxProj + p] * a.dV;
+        const double E = atom_E[at * kMaxProj + p] * a.dV;
         eu[at * kMaxProj + p] = make_double2(E * tot, E * im);
       }
     }
@@ -325,9 +353,9 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, const int o, u
       const Nbr sb = opaque(nb);
       if (active) {
         if (ZS == 1 || half == 0)
-          stencil_part<T, N, ZN, 0, PERIODIC>(u, a.V, cf, sb, ok, wg, un, tau, length);
+          stencil_part<T, N, ZN, 0, PERIODIC>(u, G(a.V), cf, sb, ok, wg, un, tau, length);
         else
-          stencil_part<T, N, ZN, (ZS == 2 ? ZN : 0), PERIODIC>(u, a.V, cf, sb, ok, wg, un, tau, length);
+          stencil_part<T, N, ZN, (ZS == 2 ? ZN : 0), PERIODIC>(u, G(a.V), cf, sb, ok, wg, un, tau, length);
       }
     }
     __syncthreads();
@@ -343,19 +371,19 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, const int o, u
       const double taud = a.dt / s;
       if (one_colour) {
         for (int at = wave; at < n_atoms; at += nwaves) {
-          const int e0 = a.nl.atom_start[at], e1 = a.nl.atom_start[at + 1];
+          const int e0 = atom_start[at], e1 = atom_start[at + 1];
           {
             double2 E4[kMaxProj];
 #pragma unroll
             for (int p = 0; p < kMaxProj; ++p) E4[p] = eu[at * kMaxProj + p];
             for (int e = e0 + lane; e < e1; e += 64) {
-              const int idx = a.nl.ent_idx[e];
+              const int idx = ent_idx[e];
               const double2 ph = phkA[e];
               const double pr = ph.x, pim = ph.y;
               double sr = 0.0, si = 0.0;
 #pragma unroll
               for (int p = 0; p < kMaxProj; ++p) {
-                const double b = a.ent_beta[(size_t)e * kMaxProj + p];
+                const double b = ent_beta[(size_t)e * kMaxProj + p];
                 sr += b * E4[p].x;
                 si += b * E4[p].y;
               }
@@ -370,14 +398,14 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, const int o, u
           if (s > 1) {
             double acc[2 * kMaxProj] = {0, 0, 0, 0, 0, 0, 0, 0};
             for (int e = e0 + lane; e < e1; e += 64) {
-              const T2 v = u[a.nl.ent_idx[e]];
+              const T2 v = u[ent_idx[e]];
               const double2 ph = phkA[e];
               const double pr = ph.x, pim = ph.y;
               const double gr = pr * (double)v.x - pim * (double)v.y;
               const double gi = pr * (double)v.y + pim * (double)v.x;
 #pragma unroll
               for (int p = 0; p < kMaxProj; ++p) {
-                const double b = a.ent_beta[(size_t)e * kMaxProj + p];
+                const double b = ent_beta[(size_t)e * kMaxProj + p];
                 acc[2 * p] += b * gr;
                 acc[2 * p + 1] += b * gi;
               }
@@ -386,7 +414,7 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, const int o, u
             const double im = __shfl_down(tot, 8, 64);
             if ((lane & 15) == 0) {
               const int p = lane >> 4;
-              const double E = a.nl.atom_E[at * kMaxProj + p] * a.dV;
+              const double E = atom_E[at * kMaxProj + p] * a.dV;
               eu[at * kMaxProj + p] = make_double2(E * tot, E * im);
             }
           }
@@ -394,20 +422,20 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, const int o, u
         __syncthreads();
       } else {
         for (int cl = 0; cl < a.n_colors; ++cl) {
-          for (int ii = a.color_start[cl] + wave; ii < a.color_start[cl + 1]; ii += nwaves) {
-            const int at = a.color_atoms[ii];
-            const int e0 = a.nl.atom_start[at], e1 = a.nl.atom_start[at + 1];
+          for (int ii = color_start[cl] + wave; ii < color_start[cl + 1]; ii += nwaves) {
+            const int at = color_atoms[ii];
+            const int e0 = atom_start[at], e1 = atom_start[at + 1];
             double2 E4[kMaxProj];
 #pragma unroll
             for (int p = 0; p < kMaxProj; ++p) E4[p] = eu[at * kMaxProj + p];
             for (int e = e0 + lane; e < e1; e += 64) {
-              const int idx = a.nl.ent_idx[e];
+              const int idx = ent_idx[e];
               const double2 ph = phkA[e];
               const double pr = ph.x, pim = ph.y;
               double sr = 0.0, si = 0.0;
 #pragma unroll
               for (int p = 0; p < kMaxProj; ++p) {
-                const double b = a.ent_beta[(size_t)e * kMaxProj + p];
+                const double b = ent_beta[(size_t)e * kMaxProj + p];
                 sr += b * E4[p].x;
                 si += b * E4[p].y;
               }
@@ -448,7 +476,7 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, const int o, u
     double acc = 0;
     if (tid < 4)
       for (int wv = 0; wv < nwaves; ++wv) acc += red[wv * 8 + tid];
-    a.obs[(size_t)o * 8 + tid] = acc;  // slots 4, 5 (kinetic, local) stay 0 here
+    G(a.obs)[(size_t)o * 8 + tid] = acc;  // slots 4, 5 (kinetic, local) stay 0 here
   }
   __syncthreads();
 
@@ -457,11 +485,11 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, const int o, u
   // moments per gather of the sphere values
   if (n_atoms > 0) {
     for (int at = wave; at < n_atoms; at += nwaves) {
-      const int e0 = a.nl.atom_start[at], e1 = a.nl.atom_start[at + 1];
+      const int e0 = atom_start[at], e1 = atom_start[at + 1];
       // lane 32 mm + 8 p holds the real part of the pass's moment mm of
       // projector p and receives the imaginary part from 4 lanes up
       const int pl = (lane >> 3) & 3, mml = lane >> 5;
-      const double E = a.nl.atom_E[at * kMaxProj + pl];
+      const double E = atom_E[at * kMaxProj + pl];
       double ur = 0.0, ui = 0.0;
 #pragma unroll 1
       for (int pass = 0; pass < 2; ++pass) {
@@ -470,16 +498,16 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, const int o, u
 #pragma unroll
         for (int i = 0; i < 16; ++i) acc[i] = 0.0;
         for (int e = e0 + lane; e < e1; e += 64) {
-          const T2 v = u[a.nl.ent_idx[e]];
-          const double2 p1 = phk[e], p2 = a.phAJ[e];
+          const T2 v = u[ent_idx[e]];
+          const double2 p1 = phk[e], p2 = phAJ[e];
           const double pr = p1.x * p2.x - p1.y * p2.y, pim = p1.x * p2.y + p1.y * p2.x;
           const double gr = pr * (double)v.x - pim * (double)v.y;
           const double gi = pr * (double)v.y + pim * (double)v.x;
-          const double m0 = pass == 0 ? 1.0 : a.ent_x[3 * (size_t)e + 1];
-          const double m1 = a.ent_x[3 * (size_t)e + 2 * pass];
+          const double m0 = pass == 0 ? 1.0 : ent_x[3 * (size_t)e + 1];
+          const double m1 = ent_x[3 * (size_t)e + 2 * pass];
 #pragma unroll
           for (int p = 0; p < kMaxProj; ++p) {
-            const double b = a.ent_beta[(size_t)e * kMaxProj + p];
+            const double b = ent_beta[(size_t)e * kMaxProj + p];
             const double br = b * gr, bi = b * gi;
             acc[2 * p] += m0 * br;
             acc[2 * p + 1] += m0 * bi;
@@ -506,7 +534,7 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, const int o, u
   if (tid < 4) {  // atoms summed in index order, whatever wavefront formed them
     double acc = 0;
     for (int at = 0; at < n_atoms; ++at) acc += ja[at * 4 + tid];
-    a.jnl[(size_t)o * 4 + tid] = acc;
+    G(a.jnl)[(size_t)o * 4 + tid] = acc;
   }
 }
 

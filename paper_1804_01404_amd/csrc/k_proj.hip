@@ -16,7 +16,14 @@
 //   A: lane l holds A[l % 16][l / 16];  B: lane l holds B[l / 16][l % 16];
 //   D: register r of lane l holds D[l / 16 + 4 r][l % 16], r = 0..3.
 //
-// Stage mode writes E_p u_p (m = 0) for the add-back of the next stage.
+// Stage mode needs only m = 0, so it runs on the four-block FP64 MFMA
+// v_mfma_f64_4x4x4f64 instead (k_project_eu): block b holds orbitals 2b and
+// 2b + 1 of the group (rows: real and imaginary part of each), its four
+// columns are the four projectors, and every product it forms is used.
+// Lane layout of v_mfma_f64_4x4x4f64 (checked by a GPU unit test), with
+// b = (l >> 2) & 3:
+//   A: lane l holds A_b[l & 3][l >> 4];  B: lane l holds B_b[l >> 4][l & 3];
+//   D: lane l holds D_b[l >> 4][l & 3].
 // Moment mode writes, per orbital and atom, the nonlocal current
 // sum_p 2 E_p Im(conj(v_p) u_p) (v = moments 1..3) and the nonlocal energy
 // sum_p E_p |u_p|^2 into a partial table [orbital][atom][4]; k_moment_reduce
@@ -138,6 +145,76 @@ __global__ __launch_bounds__(256) void k_project(ProjArgs<T> a) {
   }
 }
 
+// Stage mode: E_p u_p of every (orbital, atom, projector) on the four-block
+// MFMA. One wavefront per (group of eight orbitals, atom); SPLIT as in
+// k_project.
+template <typename T, int SPLIT>
+__global__ __launch_bounds__(256) void k_project_eu(ProjArgs<T> a) {
+  using T2 = typename Vec2<T>::type;
+  __shared__ double dpart[SPLIT > 1 ? SPLIT : 1][64];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int n_groups = (a.n_orb_tot + 7) / 8;
+  const int n_atoms = a.nl.n_atoms;
+  const int item = SPLIT > 1 ? (int)blockIdx.x : (int)blockIdx.x * 4 + wave;
+  const int sub = SPLIT > 1 ? wave : 0;
+  if (item >= n_groups * n_atoms) return;  // uniform over the wavefront (the workgroup when split)
+  const int grp = item / n_atoms;
+  const int at = item - grp * n_atoms;
+  const int blk = (lane >> 2) & 3;
+  // A operand: row i = lane & 3 of block blk is orbital 2 blk + (i >> 1),
+  // real (i even) or imaginary part; column k = lane >> 4 is entry eb + k
+  const int i_a = lane & 3, k_op = lane >> 4;
+  const int o_a = grp * 8 + 2 * blk + (i_a >> 1);
+  const int part = i_a & 1;
+  const bool row_ok = o_a < a.n_orb_tot;
+  const int k_a = row_ok ? o_a / a.n_orb : 0;
+  const T2* __restrict__ urow = a.u + (size_t)(row_ok ? o_a : 0) * a.N;
+  const double2* __restrict__ phk = a.nl.phk + (size_t)k_a * a.nl.n_ent;
+  // B operand: column j = lane & 3 is projector j (its m = 0 column), row k_op
+  const int j_b = lane & 3;
+
+  const int e0 = a.nl.atom_start[at], e1 = a.nl.atom_start[at + 1];
+  double acc = 0.0;
+  for (int eb = e0 + 4 * sub; eb < e1; eb += 4 * SPLIT) {
+    const int e = eb + k_op;
+    double av = 0.0, bv = 0.0;
+    if (e < e1) {
+      bv = a.nl.ent_B[(size_t)e * kCols + 4 * j_b];
+      if (row_ok) {
+        const int idx = a.nl.ent_idx[e];
+        const T2 uv = urow[idx];
+        const double2 p1 = phk[e];
+        const double2 p2 = a.phA[e];
+        const double pr = p1.x * p2.x - p1.y * p2.y;
+        const double pim = p1.x * p2.y + p1.y * p2.x;
+        const double ur = (double)uv.x, ui = (double)uv.y;
+        av = part ? (pr * ui + pim * ur) : (pr * ur - pim * ui);
+      }
+    }
+    acc = __builtin_amdgcn_mfma_f64_4x4x4f64(av, bv, acc, 0, 0, 0);
+  }
+  if (SPLIT > 1) {
+    dpart[wave][lane] = acc;
+    __syncthreads();
+    if (wave != 0) return;
+    double v = dpart[0][lane];
+#pragma unroll
+    for (int w = 1; w < SPLIT; ++w) v += dpart[w][lane];
+    acc = v;
+  }
+  // acc = D_blk[i][j], i = lane >> 4: orbital 2 blk + (i >> 1), real part for
+  // even i; lane ^ 16 holds the other part of the same orbital and projector
+  const double mine = a.dV * acc;
+  const double other = __shfl_xor(mine, 16, 64);
+  const int i_d = lane >> 4;
+  const int o = grp * 8 + 2 * blk + (i_d >> 1);
+  if ((i_d & 1) == 0 && o < a.n_orb_tot) {
+    const double E = a.nl.atom_E[at * kMaxProj + j_b];
+    a.Eu[((size_t)o * n_atoms + at) * kMaxProj + j_b] = make_double2(E * mine, E * other);
+  }
+}
+
 // jnl[o][slot] = sum over atoms, in order, of the moment-mode partials
 __global__ void k_moment_reduce(const double* __restrict__ part, int n_atoms, int n_orb_tot,
                                 double* __restrict__ jnl) {
@@ -161,6 +238,13 @@ hipError_t launch_project(const ProjArgs<T>& a, hipStream_t s) {
   // serial chain is a quarter as long (the 96^3 cluster, 8 orbital groups x
   // 256 atoms: 0.075 -> 0.048 ms per projection; the 20^3 cell with 512
   // k-points on the per-stage path, 1024 groups x 8 atoms: 0.172 -> 0.140 ms)
+  if (!a.moments) {
+    if (total < 16384)
+      hipLaunchKernelGGL((k_project_eu<T, 4>), dim3((unsigned)total), dim3(256), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_project_eu<T, 1>), dim3((unsigned)((total + 3) / 4)), dim3(256), 0, s, a);
+    return hipGetLastError();
+  }
   if (total < 16384)
     hipLaunchKernelGGL((k_project<T, 4>), dim3((unsigned)total), dim3(256), 0, s, a);
   else
@@ -187,7 +271,35 @@ __global__ void k_mfma_layout(const double* A, const double* B, double* D) {
   for (int r = 0; r < 4; ++r) D[(l / 16 + 4 * r) * 16 + l % 16] = acc[r];
 }
 
+// D_b = A_b B_b for the four 4 x 4 blocks of v_mfma_f64_4x4x4f64, A, B, D
+// given as [4 blocks][4][4] row-major; used only by a test entry point.
+__global__ void k_mfma44_layout(const double* A, const double* B, double* D) {
+  const int l = threadIdx.x;
+  const int b = (l >> 2) & 3;
+  const double av = A[b * 16 + (l & 3) * 4 + (l >> 4)];
+  const double bv = B[b * 16 + (l >> 4) * 4 + (l & 3)];
+  const double d = __builtin_amdgcn_mfma_f64_4x4x4f64(av, bv, 0.0, 0, 0, 0);
+  D[b * 16 + (l >> 4) * 4 + (l & 3)] = d;
+}
+
 }  // namespace td
+
+extern "C" int tddft_test_mfma44_layout(const double* A, const double* B, double* D) {
+  double *dA, *dB, *dD;
+  if (hipMalloc(&dA, 64 * sizeof(double)) != hipSuccess) return 1;
+  if (hipMalloc(&dB, 64 * sizeof(double)) != hipSuccess) return 1;
+  if (hipMalloc(&dD, 64 * sizeof(double)) != hipSuccess) return 1;
+  hipError_t e = hipMemcpy(dA, A, 64 * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(dB, B, 64 * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(td::k_mfma44_layout, dim3(1), dim3(64), 0, 0, dA, dB, dD);
+    e = hipMemcpy(D, dD, 64 * sizeof(double), hipMemcpyDeviceToHost);
+  }
+  hipFree(dA);
+  hipFree(dB);
+  hipFree(dD);
+  return e == hipSuccess ? 0 : 2;
+}
 
 extern "C" int tddft_test_mfma_layout(const double* A, const double* B, double* D) {
   double *dA, *dB, *dD;

@@ -39,6 +39,16 @@ def test_mfma_lane_layout():
     assert np.max(np.abs(D - A @ B)) < 1e-14
 
 
+def test_mfma44_lane_layout():
+    from paper_1804_01404_amd.binding import mfma44_layout_check
+    rng = np.random.default_rng(2)
+    A = rng.normal(size=(4, 4, 4))
+    B = rng.normal(size=(4, 4, 4))
+    announce("mfma_f64_4x4x4 (4 blocks) layout")
+    D = mfma44_layout_check(A, B)
+    assert np.max(np.abs(D - A @ B)) < 1e-14
+
+
 @pytest.mark.parametrize("flags", PATHS)
 @pytest.mark.parametrize("prec", ["c128", "mixed"])
 def test_plane_waves_closed_form(prec, flags):
