@@ -437,7 +437,10 @@ FusedArgs<T> fused_args(tddft_ctx* c) {
   f.coef = reinterpret_cast<T*>(c->coef);
   f.phkA = c->phkA;
   for (int mu = 0; mu < 3; ++mu)
-    for (int m = 0; m < 4; ++m) f.lapc[mu][m] = (T)c->lap[mu][m + 1];
+    for (int m = 0; m < 4; ++m) {
+      f.lapc[mu][m] = (T)c->lap[mu][m + 1];
+      f.dhc[mu][m] = (T)c->dh[mu][m];
+    }
   return f;
 }
 

@@ -156,6 +156,7 @@ struct FusedArgs {
   T* coef;                 // [n_k][kCoef] stencil coefficients of the step, stage precision
   double2* phkA;           // [n_k][S] exp(i kappa . x_e) at the step midpoint (set with coef)
   T lapc[3][4];            // off-centre Laplacian weights -1/2 c_m / h_mu^2, stage precision
+  T dhc[3][4];             // first-derivative weights d_m / h_mu, stage precision
 };
 
 // Becke-Johnson / Tran-Blaha exchange (k_mgga.hip): grid and the plain

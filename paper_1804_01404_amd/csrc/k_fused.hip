@@ -186,10 +186,11 @@ __device__ __forceinline__ void stencil_part(const typename Vec2<T>::type* u, gp
   }
 }
 
-// norm and momentum sums of w_new for the planes Z0 .. Z0 + ZN - 1, products
-// and sums in FP64 from the stage-precision values
+// norm and momentum sums of w_new for the planes Z0 .. Z0 + ZN - 1: the
+// weighted neighbour sums in the stage precision, their products with w and
+// the running sums in FP64 (as in the streaming observables kernel)
 template <typename T, int N, int ZN, int Z0, bool PERIODIC>
-__device__ __forceinline__ void observe_part(const typename Vec2<T>::type* u, const double (&dh)[3][4],
+__device__ __forceinline__ void observe_part(const typename Vec2<T>::type* u, const T (&dw)[3][4],
                                              const Nbr& nb, const bool (&ok)[16], double (&sv)[4]) {
   // Summed over the whole grid, Im(conj(w) D w) with the antisymmetric
   // difference D = sum_m d_m (S_m - S_-m) equals 2 sum_m d_m Im(conj(w) S_m w)
@@ -203,7 +204,7 @@ __device__ __forceinline__ void observe_part(const typename Vec2<T>::type* u, co
     const T2* pl = u + z * plane;
     const T2 cv = pl[nb.c];
     const double cr = (double)cv.x, ci = (double)cv.y;
-    double px = 0, py = 0, pz = 0;
+    T sxr = 0, sxi = 0, syr = 0, syi = 0, szr = 0, szi = 0;
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
       const T2 p = lds_xy<T, PERIODIC>(pl, nb.xp[m], ok[m]);
@@ -212,14 +213,17 @@ __device__ __forceinline__ void observe_part(const typename Vec2<T>::type* u, co
       T2 r;
       r.x = r.y = 0;
       if (PERIODIC || zp < N) r = u[(zp % N) * plane + nb.c];
-      px += dh[0][m] * (cr * (double)p.y - ci * (double)p.x);
-      py += dh[1][m] * (cr * (double)q.y - ci * (double)q.x);
-      pz += dh[2][m] * (cr * (double)r.y - ci * (double)r.x);
+      sxr += dw[0][m] * p.x;
+      sxi += dw[0][m] * p.y;
+      syr += dw[1][m] * q.x;
+      syi += dw[1][m] * q.y;
+      szr += dw[2][m] * r.x;
+      szi += dw[2][m] * r.y;
     }
     sv[0] += cr * cr + ci * ci;
-    sv[1] += 2.0 * px;
-    sv[2] += 2.0 * py;
-    sv[3] += 2.0 * pz;
+    sv[1] += 2.0 * (cr * (double)sxi - ci * (double)sxr);
+    sv[2] += 2.0 * (cr * (double)syi - ci * (double)syr);
+    sv[3] += 2.0 * (cr * (double)szi - ci * (double)szr);
   }
 }
 
@@ -462,7 +466,7 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, const int o, u
       for (int zz = 0; zz < ZN; ++zz) wg[(z0 + zz) * plane + fb.c] = u[(z0 + zz) * plane + fb.c];
       // whole columns, by the threads of the first column half: the summation
       // order is the same for either column split
-      if (half == 0) observe_part<T, N, N, 0, PERIODIC>(u, a.dh, fb, ok, sv);
+      if (half == 0) observe_part<T, N, N, 0, PERIODIC>(u, a.dhc, fb, ok, sv);
     }
   }
 #pragma unroll
