@@ -200,12 +200,12 @@ def oracle_pool_run(steps, workers, nk):
     return {"rho": rho, "J": J, "seconds": el, "og": s.og, "steps": steps, "workers": len(blocks)}
 
 
-def cpu_baseline(steps=3, nk=128):
+def cpu_baseline(steps=6, nk=512):
     """The oracle as it stands on the host cores (one process per core, BLAS
     threads pinned to 1 per worker), on a bounded sample of the bench cell:
-    its first nk of 512 k-points (all 16 orbitals, the whole grid), one
-    untimed step, then `steps` timed steps (Taylor + density + current +
-    Hartree + LDA). The same steps then run on the GPU (complex128 and mixed)
+    its first nk of 512 k-points (all of them by default; all 16 orbitals, the
+    whole grid), one untimed step, then `steps` timed steps (Taylor + density
+    + current + Hartree + LDA), about 10 s of work on 16 cores. The same steps then run on the GPU (complex128 and mixed)
     and their errors against the oracle are reported beside the timing."""
     import subprocess
     import numpy as np

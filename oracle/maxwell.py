@@ -97,10 +97,6 @@ class Multiscale:
         self.A_prev = np.zeros(n_x)
         self.I = np.zeros(n_x)
 
-    def set_field(self, A_now, A_prev):
-        self.A_now = np.array(A_now, dtype=np.float64)
-        self.A_prev = np.array(A_prev, dtype=np.float64)
-
     def step(self, n_macro, inc=None):
         """Advance n_macro macroscopic steps. ``inc`` [n_macro + 1][2] is the
         incident A at X_0 and X_1 for t_n .. t_{n + n_macro} (or None: no
