@@ -85,6 +85,7 @@ struct tddft_ctx {
   int* color_ents = nullptr;         // [S] entry ids grouped by colour
   bool fused = false;          // whole step per orbital in LDS
   double2* Eu = nullptr;
+  double2* Eu2 = nullptr;      // second E_p u_p buffer: stages alternate when the add-back rides in the projection
   double* jnl = nullptr;
   double nl_bound = 0;
   double vabs = 0;
@@ -463,9 +464,17 @@ tddft_status enqueue_taylor_stages(tddft_ctx* c, double dt, double tau_imag) {
   a.V = vpot<T>(c);
   void* bufs_in[4] = {c->W, c->U0, c->U1, c->U0};
   void* bufs_out[4] = {c->U0, c->U1, c->U0, c->W};
+  // With disjoint spheres (one colour) the nonlocal term of stages 4, 3 and 2
+  // is added by the next stage's projection, at the sphere points it gathers
+  // anyway (same arithmetic, so the same bits as the add-back kernel); E_p u_p
+  // then alternates between two buffers. The last stage keeps the add-back
+  // kernel: its output goes to the observables.
+  const bool nl = c->nl.n_atoms > 0;
+  const bool ride = nl && c->n_colors == 1;
+  double2* eu_buf[2] = {c->Eu, ride ? c->Eu2 : c->Eu};
   for (int i = 0; i < 4; ++i) {
     const int s = 4 - i;
-    if (c->nl.n_atoms > 0) {
+    if (nl) {
       ProjArgs<T> pa{};
       pa.u = as2<T>(bufs_in[i]);
       pa.phA = c->phA;
@@ -475,8 +484,15 @@ tddft_status enqueue_taylor_stages(tddft_ctx* c, double dt, double tau_imag) {
       pa.n_orb_tot = (int)c->n_orb_tot;
       pa.dV = c->dV;
       pa.moments = 0;
-      pa.Eu = c->Eu;
+      pa.Eu = eu_buf[i & 1];
       pa.jnl = c->jnl;
+      if (ride && i > 0) {
+        // u_s came from stage s + 1, whose projections are in the other buffer
+        pa.Eu_prev = eu_buf[(i - 1) & 1];
+        pa.ent_beta = c->ent_beta;
+        pa.tau = dt / (s + 1);
+        pa.tau_re = -tau_imag / (s + 1);
+      }
       LAUNCH(launch_project<T>(pa, c->stream), "project");
     }
     a.in = as2<T>(bufs_in[i]);
@@ -484,10 +500,12 @@ tddft_status enqueue_taylor_stages(tddft_ctx* c, double dt, double tau_imag) {
     a.out = as2<T>(bufs_out[i]);
     a.tau = dt / s;  // u_{s-1} = w + (x / s) h u_s
     a.tau_re = -tau_imag / s;
+    a.Eu = nl ? eu_buf[i & 1] : nullptr;
     const int mode = (s == 4) ? kFirst : (s == 1 ? kLast : kMid);
     LAUNCH(launch_stage<T>(mode, c->sbc, a, c->stream), "stage");
     // the nonlocal term of the stage, added over each colour's sphere entries
-    for (int cl = 0; cl < c->n_colors && c->nl.n_atoms > 0; ++cl) {
+    if (ride && s > 1) continue;
+    for (int cl = 0; cl < c->n_colors && nl; ++cl) {
       const int e0 = c->color_ent_start[cl], ne = c->color_ent_start[cl + 1] - e0;
       LAUNCH(launch_nl_addback<T>(a, c->color_ents + e0, ne, (int)c->n_orb_tot, c->stream), "nonlocal add-back");
     }
@@ -1274,7 +1292,7 @@ tddft_status tddft_set_potential(tddft_ctx* c, const double* v_loc, int32_t n_at
   tddft_status st;
   int *d_atom_start, *d_ent_idx, *d_ent_atom, *d_pt_ptr, *d_pt_ent;
   double *d_ent_B, *d_atom_E, *d_ent_x, *d_ent_beta;
-  double2 *d_phk, *d_phA, *d_phAJ, *d_Eu;
+  double2 *d_phk, *d_phA, *d_phAJ, *d_Eu, *d_Eu2;
   double* d_jnl;
   const int nA = std::max(n_atoms, 1);
   const int Sx = std::max(S, 1);
@@ -1287,7 +1305,8 @@ tddft_status tddft_set_potential(tddft_ctx* c, const double* v_loc, int32_t n_at
       (st = dalloc_t(c, (size_t)Sx, &c->color_ents)) ||
       (st = dalloc_t(c, phk.size(), &d_phk)) || (st = dalloc_t(c, Sx, &d_phA)) ||
       (st = dalloc_t(c, Sx, &d_phAJ)) ||
-      (st = dalloc_t(c, c->n_orb_tot * nA * kMaxProj, &d_Eu)) || (st = dalloc_t(c, c->n_orb_tot * 4, &d_jnl)))
+      (st = dalloc_t(c, c->n_orb_tot * nA * kMaxProj, &d_Eu)) ||
+      (st = dalloc_t(c, c->n_orb_tot * nA * kMaxProj, &d_Eu2)) || (st = dalloc_t(c, c->n_orb_tot * 4, &d_jnl)))
     return st;
   auto up = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
     if (bytes == 0) return hipSuccess;
@@ -1330,6 +1349,7 @@ tddft_status tddft_set_potential(tddft_ctx* c, const double* v_loc, int32_t n_at
   c->phA = d_phA;
   c->phAJ = d_phAJ;
   c->Eu = d_Eu;
+  c->Eu2 = d_Eu2;
   c->jnl = d_jnl;
   // ---- Hartree kernel in Fourier space
   if (c->cfg.hartree) {

@@ -128,6 +128,13 @@ struct ProjArgs {
   int moments;             // 0: stage projections -> Eu; 1: all 16 columns -> proj
   double2* Eu;             // [n_orb_tot][n_atoms][4]
   double* jnl;             // moments: [n_orb_tot][4]: nonlocal current (3) and energy
+  // stage mode with disjoint spheres: the nonlocal term of the stage that
+  // produced u, tau (-i tau + tau_re) sum_p beta_p exp(-i kappa.x) Eu_prev_p,
+  // is first added to u at the sphere points (in place) and the sum projected;
+  // Eu_prev = nullptr: u is complete
+  const double2* Eu_prev;  // [n_orb_tot][n_atoms][4]
+  const double* ent_beta;  // [S][4] beta_p
+  double tau, tau_re;
 };
 
 template <typename T>

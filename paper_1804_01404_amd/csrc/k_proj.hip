@@ -169,10 +169,18 @@ __global__ __launch_bounds__(256) void k_project_eu(ProjArgs<T> a) {
   const int part = i_a & 1;
   const bool row_ok = o_a < a.n_orb_tot;
   const int k_a = row_ok ? o_a / a.n_orb : 0;
-  const T2* __restrict__ urow = a.u + (size_t)(row_ok ? o_a : 0) * a.N;
+  T2* __restrict__ urow = const_cast<T2*>(a.u) + (size_t)(row_ok ? o_a : 0) * a.N;
   const double2* __restrict__ phk = a.nl.phk + (size_t)k_a * a.nl.n_ent;
   // B operand: column j = lane & 3 is projector j (its m = 0 column), row k_op
   const int j_b = lane & 3;
+  // the previous stage's E_p u_p of this lane's orbital and the wavefront's atom
+  const bool addback = a.Eu_prev != nullptr;
+  double2 ep[kMaxProj];
+#pragma unroll
+  for (int p = 0; p < kMaxProj; ++p) {
+    ep[p] = make_double2(0.0, 0.0);
+    if (addback && row_ok) ep[p] = a.Eu_prev[((size_t)o_a * n_atoms + at) * kMaxProj + p];
+  }
 
   const int e0 = a.nl.atom_start[at], e1 = a.nl.atom_start[at + 1];
   double acc = 0.0;
@@ -183,11 +191,28 @@ __global__ __launch_bounds__(256) void k_project_eu(ProjArgs<T> a) {
       bv = a.nl.ent_B[(size_t)e * kCols + 4 * j_b];
       if (row_ok) {
         const int idx = a.nl.ent_idx[e];
-        const T2 uv = urow[idx];
+        T2 uv = urow[idx];
         const double2 p1 = phk[e];
         const double2 p2 = a.phA[e];
         const double pr = p1.x * p2.x - p1.y * p2.y;
         const double pim = p1.x * p2.y + p1.y * p2.x;
+        if (addback) {
+          // the previous stage's nonlocal term at this point, with the same
+          // arithmetic as k_nl_addback (FP64 sum, one rounding to the stage
+          // precision); with disjoint spheres this (orbital, point) belongs to
+          // this wavefront alone, and the lane holding the real part writes it
+          double sr = 0.0, si = 0.0;
+#pragma unroll
+          for (int p = 0; p < kMaxProj; ++p) {
+            const double b = a.ent_beta[(size_t)e * kMaxProj + p];
+            sr += b * ep[p].x;
+            si += b * ep[p].y;
+          }
+          const double hr = pr * sr + pim * si, hi = pr * si - pim * sr;
+          uv.x += (T)(a.tau * hi + a.tau_re * hr);
+          uv.y += (T)(-a.tau * hr + a.tau_re * hi);
+          if (part == 0) urow[idx] = uv;
+        }
         const double ur = (double)uv.x, ui = (double)uv.y;
         av = part ? (pr * ui + pim * ur) : (pr * ur - pim * ui);
       }
