@@ -594,28 +594,59 @@ tddft_status upload_orbitals(tddft_ctx* c, const double* psi) {
   return TDDFT_OK;
 }
 
-// kinetic + potential + nonlocal upper bound of |lambda(h)| for the stability check
-double spectral_bound(const tddft_ctx* c, double amax, double vmin, double vmax) {
+// Upper bound of |lambda(h)| for the stability checks. The kinetic part
+// (1/2)(-i grad + kappa)^2, kappa = k + A/c, is a sum over the axes of commuting
+// one-axis operators whose symbol is f_i(theta) = K2(theta)/(2 h_i^2) +
+// kappa_i K1(theta)/h_i + kappa_i^2/2, with K2(theta) = -c0 - 2 sum c_m cos(m theta)
+// >= 0 and K1(theta) = 2 sum d_m sin(m theta) the symbols of the eighth-order
+// second and first differences that discretise the kinetic term of Eq.
+// TDKS_solid. On a periodic grid the one-axis eigenvalues are values of f_i,
+// with zero boundaries they lie between its extremes (Hermitian Toeplitz), so |lambda_kin| <= sum_i max_theta |f_i| <=
+// sum_i [max_theta (K2/(2 h_i^2) + |kappa_i| |K1|/h_i) + kappa_i^2/2]. The
+// maximum is taken over the Bloch vectors of the context and, per axis, the
+// largest |A_i| of the table (amax); it is sampled on a grid of theta and raised
+// by the Lipschitz constant times half the grid spacing, so it stays an upper
+// bound. The potential and the nonlocal term add |V|_max and the nonlocal norm
+// bound.
+const double kNoField[3] = {0.0, 0.0, 0.0};
+
+double spectral_bound(const tddft_ctx* c, const double amax[3], double vmin, double vmax) {
+  constexpr int kTheta = 4096;
+  static const std::vector<double> k2tab = [] {
+    std::vector<double> t(kTheta + 1);
+    for (int j = 0; j <= kTheta; ++j) {
+      const double th = M_PI * j / kTheta;
+      double v = -kFdC[0];
+      for (int m = 1; m <= 4; ++m) v -= 2.0 * kFdC[m] * std::cos(m * th);
+      t[j] = v;
+    }
+    return t;
+  }();
+  static const std::vector<double> k1tab = [] {
+    std::vector<double> t(kTheta + 1);
+    for (int j = 0; j <= kTheta; ++j) {
+      const double th = M_PI * j / kTheta;
+      double v = 0.0;
+      for (int m = 1; m <= 4; ++m) v += 2.0 * kFdD[m - 1] * std::sin(m * th);
+      t[j] = std::fabs(v);
+    }
+    return t;
+  }();
+  double lip2 = 0.0, lip1 = 0.0;  // Lipschitz constants of K2 and |K1| in theta
+  for (int m = 1; m <= 4; ++m) {
+    lip2 += 2.0 * m * std::fabs(kFdC[m]);
+    lip1 += 2.0 * m * std::fabs(kFdD[m - 1]);
+  }
   const double h[3] = {c->g.h1, c->g.h2, c->g.h3};
-  double k2pi = 0.0;  // K2(pi) = -c0 - 2 sum c_m cos(m pi)
-  k2pi = -kFdC[0];
-  for (int m = 1; m <= 4; ++m) k2pi -= 2.0 * kFdC[m] * ((m % 2) ? -1.0 : 1.0);
-  double k1max = 0.0;  // max over theta of |K1(theta)| = |2 sum d_m sin(m theta)|
-  for (int i = 0; i <= 2000; ++i) {
-    const double th = M_PI * i / 2000.0;
-    double v = 0.0;
-    for (int m = 1; m <= 4; ++m) v += 2.0 * kFdD[m - 1] * std::sin(m * th);
-    k1max = std::max(k1max, std::fabs(v));
-  }
-  double kmax[3] = {0, 0, 0};
-  for (int k = 0; k < c->cfg.n_k; ++k)
-    for (int i = 0; i < 3; ++i) kmax[i] = std::max(kmax[i], std::fabs(c->kpt[3 * k + i]) + amax / kC);
-  double lam = 0.0, kk = 0.0;
+  double lam = 0.0;
   for (int i = 0; i < 3; ++i) {
-    lam += 0.5 * k2pi / (h[i] * h[i]) + kmax[i] * k1max / h[i];
-    kk += kmax[i] * kmax[i];
+    double kap = 0.0;
+    for (int k = 0; k < c->cfg.n_k; ++k) kap = std::max(kap, std::fabs(c->kpt[3 * k + i]) + amax[i] / kC);
+    const double a2 = 0.5 / (h[i] * h[i]), a1 = kap / h[i];
+    double g = 0.0;
+    for (int j = 0; j <= kTheta; ++j) g = std::max(g, a2 * k2tab[j] + a1 * k1tab[j]);
+    lam += g + (a2 * lip2 + a1 * lip1) * (0.5 * M_PI / kTheta) + 0.5 * kap * kap;
   }
-  lam += 0.5 * kk;
   const double vabs = std::max(std::fabs(vmin), std::fabs(vmax));
   return lam + vabs + c->nl_bound;
 }
@@ -908,16 +939,21 @@ tddft_status prepare_propagate(tddft_ctx* c, int32_t nsteps, const double* A) {
   if (c->poisoned) return fail(c, TDDFT_ESTATE, "context poisoned: " + c->err);
   if (!c->potential_set) return fail(c, TDDFT_ESTATE, "propagate before set_potential");
   if (nsteps < 1 || !A) return fail(c, TDDFT_EINVAL, "bad propagate arguments");
-  double amax = 0;
+  double amax[3] = {0.0, 0.0, 0.0};
   for (size_t i = 0; i < 3 * (size_t)(nsteps + 1); ++i) {
     if (!std::isfinite(A[i])) return fail(c, TDDFT_EINVAL, "A table not finite");
-    amax = std::max(amax, std::fabs(A[i]));
+    amax[i % 3] = std::max(amax[i % 3], std::fabs(A[i]));
   }
   if (c->cfg.gauge == TDDFT_VELOCITY && !(c->cfg.flags & TDDFT_FLAG_ALLOW_UNSTABLE)) {
     // the potential part was checked in set_potential; recheck the kinetic part with |A|
     const double lam = spectral_bound(c, amax, -c->vabs, c->vabs);
-    if (std::fabs(c->cfg.dt) * lam > 2.0 * std::sqrt(2.0))
-      return fail(c, TDDFT_EUNSTABLE, "unstable for this A table: |dt| lambda_max > 2 sqrt 2");
+    if (std::fabs(c->cfg.dt) * lam > 2.0 * std::sqrt(2.0)) {
+      char buf[200];
+      std::snprintf(buf, sizeof buf,
+                    "unstable for this A table: |dt| * lambda_max = %.4g > 2 sqrt 2 (lambda_max <= %.6g Ha)",
+                    std::fabs(c->cfg.dt) * lam, lam);
+      return fail(c, TDDFT_EUNSTABLE, buf);
+    }
   }
   if (nsteps > c->cap_steps) {
     invalidate_graph(c);
@@ -1279,10 +1315,10 @@ tddft_status tddft_set_potential(tddft_ctx* c, const double* v_loc, int32_t n_at
     }
   // stability: |lambda| dt <= 2 sqrt 2 for the truncated fourth-order Taylor step
   c->vabs = std::max(std::fabs(vmin), std::fabs(vmax));
-  const double lam = spectral_bound(c, 0.0, vmin, vmax);
+  const double lam = spectral_bound(c, kNoField, vmin, vmax);
   if (std::fabs(c->cfg.dt) * lam > 2.0 * std::sqrt(2.0) && !(c->cfg.flags & TDDFT_FLAG_ALLOW_UNSTABLE)) {
     char buf[200];
-    std::snprintf(buf, sizeof buf, "unstable: |dt| * lambda_max = %.4g > 2 sqrt 2 (lambda_max <= %.4g Ha)",
+    std::snprintf(buf, sizeof buf, "unstable: |dt| * lambda_max = %.4g > 2 sqrt 2 (lambda_max <= %.6g Ha)",
                   std::fabs(c->cfg.dt) * lam, lam);
     return fail(c, TDDFT_EUNSTABLE, buf);
   }
@@ -1596,7 +1632,7 @@ tddft_status tddft_ground_state(tddft_ctx* c, int32_t n_iter, double tau, double
   if (c->poisoned) return fail(c, TDDFT_ESTATE, "context poisoned: " + c->err);
   if (!c->potential_set) return fail(c, TDDFT_ESTATE, "ground_state before set_potential");
   if (n_iter < 0 || !(tau > 0.0) || !std::isfinite(tau)) return fail(c, TDDFT_EINVAL, "bad ground-state arguments");
-  const double lam = spectral_bound(c, 0.0, -c->vabs, c->vabs);
+  const double lam = spectral_bound(c, kNoField, -c->vabs, c->vabs);
   // P4(-x) = 1 - x + x^2/2 - x^3/6 + x^4/24 decreases monotonically only up to
   // x = 1.596 (where P4'(-x) = 0); beyond it high modes are damped less than
   // lower ones and the iteration can settle on the wrong subspace

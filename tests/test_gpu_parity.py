@@ -286,6 +286,60 @@ def test_error_paths():
         assert e.value.status == EINVAL
 
 
+def _lambda_true(s, A, kpts):
+    """Largest |eigenvalue| of the discrete Hamiltonian at the given Bloch
+    vectors and uniform A, from the oracle's h applied to every grid delta
+    (dense, so small grids only)."""
+    o = tdks.TDKS.from_system(s)
+    g = o.grid
+    N = int(np.prod(g.shape))
+    eye = np.eye(N, dtype=np.complex128).reshape((N,) + tuple(g.shape))
+    lam = 0.0
+    for k in kpts:
+        H = tdks.apply_h(eye, np.asarray(k) + np.asarray(A) / C, o.v_ks, o.projs, g).reshape(N, N)
+        lam = max(lam, float(np.max(np.abs(np.linalg.eigvalsh(0.5 * (H + H.conj().T))))))
+    return lam
+
+
+def _reported_bound(err):
+    import re
+    m = re.search(r"lambda_max <= ([0-9.eE+-]+) Ha", str(err))
+    assert m, str(err)
+    return float(m.group(1))
+
+
+def test_stability_bound_covers_the_spectrum():
+    """The library's |lambda|max bound (per-axis symbol maxima with the
+    table's largest |A_i|) is at least the spectral radius of the discrete
+    Hamiltonian, with and without a strong field, and within a factor 2 of
+    it (the bound adds |V|max and the nonlocal norm bound to the kinetic
+    symbol's maximum)."""
+    from paper_1804_01404_amd.binding import EUNSTABLE, TDDFT, TDDFTError
+    s = synth.multiscale_cell(nk=2, n=12, n_orb=4, dt=1.0, precision="c128")
+    kx = [k for k in np.asarray(s.kpts) if k[0] > 0][:2]
+    announce("stability bound: 12^3 diamond, 8 k-points")
+    with TDDFT(s, precision="c128") as t:
+        with pytest.raises(TDDFTError) as e:
+            t.set_potential()
+        assert e.value.status == EUNSTABLE
+    lam0 = _reported_bound(e.value)
+    true0 = _lambda_true(s, [0.0, 0.0, 0.0], kx)
+    assert true0 <= lam0 <= 2.0 * true0
+    s.dt = 0.999 * 2.0 * np.sqrt(2.0) / lam0
+    A = np.zeros((3, 3))
+    A[:, 0] = 200.0
+    with TDDFT(s, precision="c128") as t:
+        t.set_potential()
+        with pytest.raises(TDDFTError) as e:
+            t.propagate(A)
+        assert e.value.status == EUNSTABLE
+        lam_a = _reported_bound(e.value)
+        J = t.propagate(np.zeros((3, 3)))                # the field-free table still runs
+        assert np.all(np.isfinite(J))
+    true_a = _lambda_true(s, [200.0, 0.0, 0.0], kx)
+    assert true_a <= lam_a <= 2.0 * true_a
+
+
 @pytest.mark.parametrize("flags", PATHS)
 def test_full_size_diamond20_k512_sampled(flags):
     """The full 20^3 x 512 k-point workload, one step: sampled k-points are
