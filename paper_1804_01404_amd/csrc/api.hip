@@ -357,6 +357,7 @@ tddft_status enqueue_observe(tddft_ctx* c, int bump) {
   oa.set_weights();
   oa.cdiag = c->cdiag;
   oa.out = c->obs;
+  oa.energy = bump ? 0 : 1;  // a step records the current; the energy is read on demand
   LAUNCH(launch_observe<T>(c->bc, oa, c->stream), "observe");
   const bool nl = c->nl.n_atoms > 0;
   if (nl) {
@@ -689,6 +690,7 @@ tddft_status launch_one(tddft_ctx* c, int which) {
     oa.set_weights();
     oa.cdiag = c->cdiag;
     oa.out = c->obs;
+    oa.energy = 0;  // the variant each step runs
     LAUNCH(launch_observe<T>(c->bc, oa, c->stream), "observe");
   } else if (which == TDDFT_KERNEL_FUSED) {
     LAUNCH(launch_fused<T>(fused_args<T>(c), c->stream), "fused step");

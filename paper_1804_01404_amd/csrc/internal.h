@@ -104,6 +104,7 @@ struct ObserveArgs {
   double lap[3][5];
   double cdiag;
   double* out;             // [n_orb_tot][tiles][8]: norm, p_x, p_y, p_z, kin, vloc
+  int energy;              // 0: norm and p only (kin, vloc written as 0), as each step needs
   // off-centre weights of lap and dh in the stage precision (kernel
   // arguments, so they stay in scalar registers); set by set_weights
   T cl[3][4], cd[3][4];

@@ -451,12 +451,14 @@ template hipError_t launch_nl_addback<float>(const StageArgs<float>&, const int*
 
 // Per-orbital sums used by the current and the energy:
 // norm = sum |w|^2, p_mu = sum Im(conj(w) d_mu w), kin = sum Re(conj(w)(-1/2 Lap w)),
-// vloc = sum V_loc |w|^2 (the caller multiplies by h1 h2 h3). The neighbour
+// vloc = sum V_loc |w|^2 (the caller multiplies by h1 h2 h3); with EN false
+// only norm and p (what each step's current needs), kin and vloc written as
+// 0. The neighbour
 // differences and their weighted sums d_mu w and -1/2 Lap w are formed in the
 // orbital precision (exact differences of FP32 values up to one rounding, then
 // FP32 weighted sums for complex FP32); the products with w and the running
 // sums over the grid are FP64. complex128 is FP64 throughout.
-template <typename T, int BC>
+template <typename T, int BC, bool EN>
 __global__ __launch_bounds__(1024) void k_observe(ObserveArgs<T> a) {
   using T2 = typename Vec2<T>::type;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -557,7 +559,7 @@ __global__ __launch_bounds__(1024) void k_observe(ObserveArgs<T> a) {
     const size_t pd = (size_t)min(zp, n3 - 1) * plane;
     const T2* __restrict__ sp = src + pd;
     nxt[d] = load2(at(src + (size_t)zidx(zp + 4) * plane, colb));
-    vl[d] = *at(a.Vloc + pd, cold);
+    if (EN) vl[d] = *at(a.Vloc + pd, cold);
 #pragma unroll
     for (int i = 0; i < kHaloSlots; ++i)
       if (BC != kPeriodicPlane) hv[d][i] = load2(at(sp, hs.off[i]));
@@ -571,7 +573,7 @@ __global__ __launch_bounds__(1024) void k_observe(ObserveArgs<T> a) {
   auto plane_step = [&](int z, auto slot) __attribute__((always_inline)) {
     constexpr int d = decltype(slot)::value;
     q[8] = keep_if(zin(z + 4), nxt[d]);
-    const double vz = vl[d];
+    const double vz = EN ? vl[d] : 0.0;
     T2* buf = lds + (z & 1) * lsz;
     if (active) buf[lc] = q[4];
 #pragma unroll
@@ -586,20 +588,26 @@ __global__ __launch_bounds__(1024) void k_observe(ObserveArgs<T> a) {
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
         T2 p = buf[XP(m)], n = buf[XM(m)];
-        lr = fmat(CL(0, m), p.x + n.x, lr);
-        li = fmat(CL(0, m), p.y + n.y, li);
+        if (EN) {
+          lr = fmat(CL(0, m), p.x + n.x, lr);
+          li = fmat(CL(0, m), p.y + n.y, li);
+        }
         dxr = fmat(CD(0, m), p.x - n.x, dxr);
         dxi = fmat(CD(0, m), p.y - n.y, dxi);
         p = buf[YP(m)];
         n = buf[YM(m)];
-        lr = fmat(CL(1, m), p.x + n.x, lr);
-        li = fmat(CL(1, m), p.y + n.y, li);
+        if (EN) {
+          lr = fmat(CL(1, m), p.x + n.x, lr);
+          li = fmat(CL(1, m), p.y + n.y, li);
+        }
         dyr = fmat(CD(1, m), p.x - n.x, dyr);
         dyi = fmat(CD(1, m), p.y - n.y, dyi);
         p = q[5 + m];
         n = q[3 - m];
-        lr = fmat(CL(2, m), p.x + n.x, lr);
-        li = fmat(CL(2, m), p.y + n.y, li);
+        if (EN) {
+          lr = fmat(CL(2, m), p.x + n.x, lr);
+          li = fmat(CL(2, m), p.y + n.y, li);
+        }
         dzr = fmat(CD(2, m), p.x - n.x, dzr);
         dzi = fmat(CD(2, m), p.y - n.y, dzi);
       }
@@ -609,8 +617,10 @@ __global__ __launch_bounds__(1024) void k_observe(ObserveArgs<T> a) {
       s_px = fmat(ux, (double)dxi, fmat(-uy, (double)dxr, s_px));
       s_py = fmat(ux, (double)dyi, fmat(-uy, (double)dyr, s_py));
       s_pz = fmat(ux, (double)dzi, fmat(-uy, (double)dzr, s_pz));
-      s_kin = fmat(ux, (double)lr, fmat(uy, (double)li, s_kin));
-      s_v = fmat(vz, nn, s_v);
+      if (EN) {
+        s_kin = fmat(ux, (double)lr, fmat(uy, (double)li, s_kin));
+        s_v = fmat(vz, nn, s_v);
+      }
     }
 #pragma unroll
     for (int i = 0; i < 8; ++i) q[i] = q[i + 1];
@@ -618,8 +628,9 @@ __global__ __launch_bounds__(1024) void k_observe(ObserveArgs<T> a) {
 
   run_planes<PF>(z0, z1, plane_step);
   double v[6] = {s_norm, s_px, s_py, s_pz, s_kin, s_v};
+  constexpr int NS = EN ? 6 : 4;  // sums reduced (kin and vloc stay 0 without EN)
 #pragma unroll
-  for (int i = 0; i < 6; ++i) {
+  for (int i = 0; i < NS; ++i) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v[i] += __shfl_down(v[i], off, 64);
   }
@@ -632,7 +643,8 @@ __global__ __launch_bounds__(1024) void k_observe(ObserveArgs<T> a) {
   if (tid < 6) {
     const int nw = (blockDim.x + 63) / 64;
     double s = 0;
-    for (int w = 0; w < nw; ++w) s += red[w][tid];
+    if (tid < NS)
+      for (int w = 0; w < nw; ++w) s += red[w][tid];
     a.out[(((size_t)o * ntiles + tile) * nz + slab) * 8 + tid] = s;
   }
 }
@@ -669,23 +681,28 @@ hipError_t launch_stage(int mode, int bc, const StageArgs<T>& a, hipStream_t s) 
   return stage_bc<T, kLast>(bc, a, s);
 }
 
-template <typename T>
-hipError_t launch_observe(int bc, const ObserveArgs<T>& a, hipStream_t s) {
+template <typename T, bool EN>
+static hipError_t observe_bc(int bc, const ObserveArgs<T>& a, hipStream_t s) {
   const dim3 grid((unsigned)((size_t)a.g.n_orb * a.g.n_k * a.g.tiles_x * a.g.tiles_y * a.g.zslabs));
   const dim3 block(block_threads(a.g));
   const size_t lds = lds_elems(bc, a.g) * sizeof(typename Vec2<T>::type);
   switch (bc) {
     case kPeriodicPlane:
-      hipLaunchKernelGGL((k_observe<T, kPeriodicPlane>), grid, block, lds, s, a);
+      hipLaunchKernelGGL((k_observe<T, kPeriodicPlane, EN>), grid, block, lds, s, a);
       break;
     case kPeriodicTile:
-      hipLaunchKernelGGL((k_observe<T, kPeriodicTile>), grid, block, lds, s, a);
+      hipLaunchKernelGGL((k_observe<T, kPeriodicTile, EN>), grid, block, lds, s, a);
       break;
     default:
-      hipLaunchKernelGGL((k_observe<T, kIsolatedTile>), grid, block, lds, s, a);
+      hipLaunchKernelGGL((k_observe<T, kIsolatedTile, EN>), grid, block, lds, s, a);
       break;
   }
   return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_observe(int bc, const ObserveArgs<T>& a, hipStream_t s) {
+  return a.energy ? observe_bc<T, true>(bc, a, s) : observe_bc<T, false>(bc, a, s);
 }
 
 template hipError_t launch_stage<double>(int, int, const StageArgs<double>&, hipStream_t);
