@@ -1,50 +1,84 @@
 // Kernels of the current surrogate that stands in for a microscopic cell in
 // the multiscale coupling (Sec. 5): a causal window of the vector potential
 // -> dense W->H, tanh -> dense H->H, tanh -> dense H->1, plus a linear skip
-// W->1. FP32 throughout; every reduction runs in a fixed order, so results do
-// not depend on scheduling. Parameter layout (flat): W1 [H][W], b1 [H],
+// W->1. FP32 throughout, the dense layers on the matrix cores; every reduction
+// runs in a fixed order, so results do not depend on scheduling. Parameter layout (flat): W1 [H][W], b1 [H],
 // W2 [H][H], b2 [H], w3 [H], b3 [1], ws [W]. Adam follows Kingma and Ba
 // (ICLR 2015, Algorithm 1).
 #include "internal.h"
 
 namespace td {
 
-constexpr int kTile = 16;
+constexpr int kTile = 16;      // output tile of one workgroup (the MFMA's 16 x 16)
+constexpr int kGemmWaves = 4;  // wavefronts per tile, each a quarter of the k range
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // C[i][j] = sum_k A(i, k) B(k, j) for i < M, j < N, with A(i, k) = A[i*sai + k*sak]
 // and B(k, j) = B[k*sbk + j*sbj]; epilogue: + bias[j] (if bias), tanh (if act),
 // then * (1 - aux[i][j]^2) (if aux, the tanh derivative of a stored activation).
-__global__ __launch_bounds__(kTile* kTile) void k_gemm(const float* __restrict__ A, long sai, long sak,
-                                                      const float* __restrict__ B, long sbk, long sbj,
-                                                      float* __restrict__ C, int M, int N, int K,
-                                                      const float* __restrict__ bias, int act,
-                                                      const float* __restrict__ aux) {
-  __shared__ float ta[kTile][kTile + 1];
-  __shared__ float tb[kTile][kTile + 1];
-  const int tx = threadIdx.x % kTile, ty = threadIdx.x / kTile;
-  const int i = blockIdx.y * kTile + ty;
-  const int j = blockIdx.x * kTile + tx;
-  float acc = 0.0f;
-  for (int k0 = 0; k0 < K; k0 += kTile) {
-    {
-      const int ai = blockIdx.y * kTile + ty, ak = k0 + tx;
-      ta[ty][tx] = (ai < M && ak < K) ? A[ai * sai + ak * sak] : 0.0f;
-      const int bk = k0 + ty, bj = blockIdx.x * kTile + tx;
-      tb[ty][tx] = (bk < K && bj < N) ? B[bk * sbk + bj * sbj] : 0.0f;
-    }
-    __syncthreads();
+// On the matrix cores: v_mfma_f32_16x16x4f32 takes A(i, k) from lane i + 16 k
+// and B(k, j) from lane j + 16 k of a 16 x 4 / 4 x 16 slice and leaves
+// C(4 g + r, j) in element r of lane j + 16 g. Each of the four wavefronts of a
+// tile runs a contiguous quarter of the k steps; the partial tiles are added in
+// wavefront order, so the result does not depend on scheduling.
+__global__ __launch_bounds__(kGemmWaves * 64) void k_gemm(const float* __restrict__ A, long sai, long sak,
+                                                         const float* __restrict__ B, long sbk, long sbj,
+                                                         float* __restrict__ C, int M, int N, int K,
+                                                         const float* __restrict__ bias, int act,
+                                                         const float* __restrict__ aux) {
+  __shared__ float part[kGemmWaves - 1][kTile][kTile + 1];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = lane & 15, q = lane >> 4;
+  const int i0 = blockIdx.y * kTile, j0 = blockIdx.x * kTile;
+  // rows and columns past the matrix load a clamped in-range element and use 0
+  const bool aok = i0 + r < M, bok = j0 + r < N;
+  const long ia = min(i0 + r, M - 1), jb = min(j0 + r, N - 1);
+  const int steps = (K + 3) / 4;
+  const int per = (steps + kGemmWaves - 1) / kGemmWaves;
+  const int s0 = wave * per, s1 = min(steps, s0 + per);
+  f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+  // chunks of kChunk k steps: every load of a chunk is issued before its
+  // products (steps past s1 or K load a clamped element and use 0)
+  constexpr int kChunk = 8;
+  for (int c0 = s0; c0 < s1; c0 += kChunk) {
+    float av[kChunk], bv[kChunk];
 #pragma unroll
-    for (int kk = 0; kk < kTile; ++kk) acc = fmaf(ta[ty][kk], tb[kk][tx], acc);
-    __syncthreads();
-  }
-  if (i < M && j < N) {
-    if (bias) acc += bias[j];
-    if (act) acc = tanhf(acc);
-    if (aux) {
-      const float h = aux[(long)i * N + j];
-      acc *= 1.0f - h * h;
+    for (int u = 0; u < kChunk; ++u) {
+      const long kc = min(4 * (c0 + u) + q, K - 1);
+      av[u] = A[ia * sai + kc * sak];
+      bv[u] = B[kc * sbk + jb * sbj];
     }
-    C[(long)i * N + j] = acc;
+#pragma unroll
+    for (int u = 0; u < kChunk; ++u) {
+      const bool kin = c0 + u < s1 && 4 * (c0 + u) + q < K;
+      const float a = (aok && kin) ? av[u] : 0.0f;
+      const float b = (bok && kin) ? bv[u] : 0.0f;
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+    }
+  }
+  if (wave > 0) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) part[wave - 1][4 * q + e][r] = acc[e];
+  }
+  __syncthreads();
+  if (wave == 0) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      float v = acc[e];
+#pragma unroll
+      for (int w = 0; w < kGemmWaves - 1; ++w) v += part[w][4 * q + e][r];
+      const int i = i0 + 4 * q + e, j = j0 + r;
+      if (i < M && j < N) {
+        if (bias) v += bias[j];
+        if (act) v = tanhf(v);
+        if (aux) {
+          const float h = aux[(long)i * N + j];
+          v *= 1.0f - h * h;
+        }
+        C[(long)i * N + j] = v;
+      }
+    }
   }
 }
 
@@ -146,7 +180,7 @@ __global__ void k_accum(const float* __restrict__ src, float* __restrict__ dst) 
 static hipError_t gemm(const float* A, long sai, long sak, const float* B, long sbk, long sbj, float* C, int M,
                        int N, int K, const float* bias, int act, const float* aux, hipStream_t s) {
   const dim3 grid((unsigned)((N + kTile - 1) / kTile), (unsigned)((M + kTile - 1) / kTile));
-  hipLaunchKernelGGL(k_gemm, grid, dim3(kTile * kTile), 0, s, A, sai, sak, B, sbk, sbj, C, M, N, K, bias, act,
+  hipLaunchKernelGGL(k_gemm, grid, dim3(kGemmWaves * 64), 0, s, A, sai, sak, B, sbk, sbj, C, M, N, K, bias, act,
                      aux);
   return hipGetLastError();
 }
