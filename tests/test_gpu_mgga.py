@@ -94,7 +94,7 @@ def test_tb09_several_density_chunks(prec, flags):
     else:
         assert abs(g["c1"] - o["c1"]) < 1e-6
         assert rel_l2(g["rho"], o["rho"]) < 2e-6 * np.sqrt(nsteps)
-        assert max_rel_series(g["J"], o["J"]) < 1e-4
+        assert max_rel_series(g["J"], o["J"]) < 1e-5
 
 
 @pytest.mark.parametrize("flags", PATHS)
@@ -121,7 +121,7 @@ def test_mixed_path_tb09():
     n = s.A.shape[0] - 1
     assert rel_l2(g["rho"], o["rho"]) < 2e-6 * np.sqrt(n)
     assert abs(g["c1"] - o["c1"]) < 1e-6
-    assert max_rel_series(g["J"], o["J"]) < 1e-4
+    assert max_rel_series(g["J"], o["J"]) < 1e-5
 
 
 def test_isolated_length_gauge_bj():

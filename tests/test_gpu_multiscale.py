@@ -89,24 +89,27 @@ def test_pseudopotential_cells_match_oracle():
 W_, H_ = 24, 16
 
 
-def _net(seed, a_scale=1.0, j_scale=1.0, lr=1e-3):
+def _net(seed, a_scale=1.0, j_scale=1.0, lr=1e-3, W=W_, H=H_):
     from paper_1804_01404_amd.binding import Surrogate
     import synth
-    th = synth.surrogate_init(W_, H_, seed)
-    return Surrogate(W_, H_, th, a_scale=a_scale, j_scale=j_scale, lr=lr), th
+    th = synth.surrogate_init(W, H, seed)
+    return Surrogate(W, H, th, a_scale=a_scale, j_scale=j_scale, lr=lr), th
 
 
-def test_surrogate_forward_and_gradient_match_oracle():
-    nn, th = _net(6601)
+# (window, hidden, batch): multiples of the 16 x 16 x 4 matrix-core tile, and
+# ragged rows, columns and k steps in every GEMM of the forward and backward pass
+@pytest.mark.parametrize("W,H,B", [(24, 16, 37), (30, 12, 5), (512, 16, 256)])
+def test_surrogate_forward_and_gradient_match_oracle(W, H, B):
+    nn, th = _net(6601, W=W, H=H)
     rng = rng_for(6602)
-    x = rng.normal(size=(37, W_)).astype(np.float32)
-    t = rng.normal(size=37).astype(np.float32)
-    announce("surrogate forward / gradient vs oracle")
+    x = rng.normal(size=(B, W)).astype(np.float32)
+    t = rng.normal(size=B).astype(np.float32)
+    announce(f"surrogate forward / gradient vs oracle, W {W} H {H} B {B}")
     with nn:
         y = nn.forward(x)
         loss, g = nn.loss_grad(x, t)
-        yo, _, _ = surrogate.forward(th.astype(np.float64), x.astype(np.float64), W_, H_)
-        lo, go = surrogate.loss_and_grad(th.astype(np.float64), x.astype(np.float64), t.astype(np.float64), W_, H_)
+        yo, _, _ = surrogate.forward(th.astype(np.float64), x.astype(np.float64), W, H)
+        lo, go = surrogate.loss_and_grad(th.astype(np.float64), x.astype(np.float64), t.astype(np.float64), W, H)
         assert np.max(np.abs(y - yo)) < 1e-5 * max(1.0, np.max(np.abs(yo)))
         assert abs(loss - lo) < 1e-5 * lo
         assert np.max(np.abs(g - go)) < 1e-3 * np.max(np.abs(go))

@@ -7,8 +7,8 @@ Tolerances (derivation in the design notes):
 * mixed path (complex FP32 orbitals and stencil, FP64 reductions): FP32
   rounding of the stored orbitals, 2^-24 ~ 6e-8 per component and step,
   accumulated over n steps and amplified by the current's cancellation:
-  orbitals and density <= 2e-6 * sqrt(n) relative, current <= 1e-4 of its
-  maximum over the windows used here.
+  orbitals and density <= 2e-6 * sqrt(n) relative, current <= 1e-5 of its
+  maximum per component over the windows used here (measured: 1e-7 to 1.2e-6).
 """
 import numpy as np
 import pytest
@@ -130,7 +130,7 @@ def test_diamond20_kpoints(prec, flags):
         tol = 2e-6 * np.sqrt(nsteps)
         assert rel_l2(g["rho"], o["rho"]) < tol
         assert rel_l2(g["psi"], o["psi"]) < tol
-        assert max_rel_series(g["J"], o["J"]) < 1e-4
+        assert max_rel_series(g["J"], o["J"]) < 1e-5
         assert abs(g["E"] - o["E"]) < 1e-6 * abs(o["E"])
 
 
@@ -386,7 +386,7 @@ def test_fused_24_cubed_mixed_matches_oracle(boundary):
     o = oracle_run(s)
     assert rel_l2(g["rho"], o["rho"]) < 2e-6 * np.sqrt(nsteps)
     assert rel_l2(g["psi"], o["psi"]) < 2e-6 * np.sqrt(nsteps)
-    assert max_rel_series(g["J"], o["J"]) < 1e-4
+    assert max_rel_series(g["J"], o["J"]) < 1e-5
 
 
 @pytest.mark.parametrize("prec", ["c128", "mixed"])
