@@ -71,23 +71,38 @@ __global__ __launch_bounds__(256) void k_project(ProjArgs<T> a) {
   for (int at = at0; at < at1; ++at) {
     const int e0 = a.nl.atom_start[at], e1 = a.nl.atom_start[at + 1];
     d4_t acc = {0.0, 0.0, 0.0, 0.0};
-    for (int eb = e0 + 4 * sub; eb < e1; eb += 4 * SPLIT) {
-      const int e = eb + kk;
-      double av = 0.0, bv = 0.0;
-      if (e < e1) {
-        bv = a.nl.ent_B[(size_t)e * kCols + j];
-        if (row_ok) {
-          const int idx = a.nl.ent_idx[e];
-          const T2 uv = urow[idx];
-          const double2 p1 = phk[e];
-          const double2 p2 = a.phA[e];
-          const double pr = p1.x * p2.x - p1.y * p2.y;
-          const double pim = p1.x * p2.y + p1.y * p2.x;
-          const double ur = (double)uv.x, ui = (double)uv.y;
-          av = part ? (pr * ui + pim * ur) : (pr * ur - pim * ui);
-        }
+    // kPipe k steps at a time, loads first (as in k_project_eu): steps past
+    // the sphere load its last entry and use 0
+    constexpr int kPipe = 4;
+    const int step = 4 * SPLIT;
+    for (int eb = e0 + 4 * sub; eb < e1; eb += step * kPipe) {
+      bool ein[kPipe];
+      int idx[kPipe];
+      double bv[kPipe];
+      double2 p1[kPipe], p2[kPipe];
+#pragma unroll
+      for (int u = 0; u < kPipe; ++u) {
+        const int e = eb + step * u + kk;
+        ein[u] = e < e1;
+        const int ec = min(e, e1 - 1);
+        bv[u] = a.nl.ent_B[(size_t)ec * kCols + j];
+        idx[u] = a.nl.ent_idx[ec];
+        p1[u] = phk[ec];
+        p2[u] = a.phA[ec];
       }
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+      T2 uv[kPipe];
+#pragma unroll
+      for (int u = 0; u < kPipe; ++u) uv[u] = urow[idx[u]];
+#pragma unroll
+      for (int u = 0; u < kPipe; ++u) {
+        const double pr = p1[u].x * p2[u].x - p1[u].y * p2[u].y;
+        const double pim = p1[u].x * p2[u].y + p1[u].y * p2[u].x;
+        const double ur = (double)uv[u].x, ui = (double)uv[u].y;
+        const double avv = part ? (pr * ui + pim * ur) : (pr * ur - pim * ui);
+        const double av = (ein[u] && row_ok) ? avv : 0.0;
+        const double b = ein[u] ? bv[u] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b, acc, 0, 0, 0);
+      }
     }
     if (SPLIT > 1) {
 #pragma unroll
@@ -148,7 +163,7 @@ __global__ __launch_bounds__(256) void k_project(ProjArgs<T> a) {
 // Stage mode: E_p u_p of every (orbital, atom, projector) on the four-block
 // MFMA. One wavefront per (group of eight orbitals, atom); SPLIT as in
 // k_project.
-template <typename T, int SPLIT>
+template <typename T, int SPLIT, bool ADD>
 __global__ __launch_bounds__(256) void k_project_eu(ProjArgs<T> a) {
   using T2 = typename Vec2<T>::type;
   __shared__ double dpart[SPLIT > 1 ? SPLIT : 1][64];
@@ -174,7 +189,8 @@ __global__ __launch_bounds__(256) void k_project_eu(ProjArgs<T> a) {
   // B operand: column j = lane & 3 is projector j (its m = 0 column), row k_op
   const int j_b = lane & 3;
   // the previous stage's E_p u_p of this lane's orbital and the wavefront's atom
-  const bool addback = a.Eu_prev != nullptr;
+  // ADD: a.Eu_prev is set and the previous stage's nonlocal term is added
+  constexpr bool addback = ADD;
   double2 ep[kMaxProj];
 #pragma unroll
   for (int p = 0; p < kMaxProj; ++p) {
@@ -184,40 +200,64 @@ __global__ __launch_bounds__(256) void k_project_eu(ProjArgs<T> a) {
 
   const int e0 = a.nl.atom_start[at], e1 = a.nl.atom_start[at + 1];
   double acc = 0.0;
-  for (int eb = e0 + 4 * sub; eb < e1; eb += 4 * SPLIT) {
-    const int e = eb + k_op;
-    double av = 0.0, bv = 0.0;
-    if (e < e1) {
-      bv = a.nl.ent_B[(size_t)e * kCols + 4 * j_b];
-      if (row_ok) {
-        const int idx = a.nl.ent_idx[e];
-        T2 uv = urow[idx];
-        const double2 p1 = phk[e];
-        const double2 p2 = a.phA[e];
-        const double pr = p1.x * p2.x - p1.y * p2.y;
-        const double pim = p1.x * p2.y + p1.y * p2.x;
-        if (addback) {
-          // the previous stage's nonlocal term at this point, with the same
-          // arithmetic as k_nl_addback (FP64 sum, one rounding to the stage
-          // precision); with disjoint spheres this (orbital, point) belongs to
-          // this wavefront alone, and the lane holding the real part writes it
-          double sr = 0.0, si = 0.0;
+  // kPipe k steps at a time: their table and index loads are issued first,
+  // then their gathers, then their products, so the gathers of a group are in
+  // flight together. Steps past the sphere load its last entry and use 0 (the
+  // products then add exact zeros). With the add-back, the points of a group
+  // are distinct and the wavefront's own, so its loads may precede its stores.
+  constexpr int kPipe = 4;
+  const int step = 4 * SPLIT;
+  for (int eb = e0 + 4 * sub; eb < e1; eb += step * kPipe) {
+    bool ein[kPipe];
+    int ec[kPipe], idx[kPipe];
+    double bv[kPipe];
+    double2 p1[kPipe], p2[kPipe];
 #pragma unroll
-          for (int p = 0; p < kMaxProj; ++p) {
-            const double b = a.ent_beta[(size_t)e * kMaxProj + p];
-            sr += b * ep[p].x;
-            si += b * ep[p].y;
-          }
-          const double hr = pr * sr + pim * si, hi = pr * si - pim * sr;
-          uv.x += (T)(a.tau * hi + a.tau_re * hr);
-          uv.y += (T)(-a.tau * hr + a.tau_re * hi);
-          if (part == 0) urow[idx] = uv;
-        }
-        const double ur = (double)uv.x, ui = (double)uv.y;
-        av = part ? (pr * ui + pim * ur) : (pr * ur - pim * ui);
-      }
+    for (int u = 0; u < kPipe; ++u) {
+      const int e = eb + step * u + k_op;
+      ein[u] = e < e1;
+      ec[u] = min(e, e1 - 1);
+      bv[u] = a.nl.ent_B[(size_t)ec[u] * kCols + 4 * j_b];
+      idx[u] = a.nl.ent_idx[ec[u]];
+      p1[u] = phk[ec[u]];
+      p2[u] = a.phA[ec[u]];
     }
-    acc = __builtin_amdgcn_mfma_f64_4x4x4f64(av, bv, acc, 0, 0, 0);
+    T2 uv[kPipe];
+#pragma unroll
+    for (int u = 0; u < kPipe; ++u) uv[u] = urow[idx[u]];
+    double bt[kPipe][kMaxProj];
+#pragma unroll
+    for (int u = 0; u < kPipe; ++u)
+#pragma unroll
+      for (int p = 0; p < kMaxProj; ++p) bt[u][p] = addback ? a.ent_beta[(size_t)ec[u] * kMaxProj + p] : 0.0;
+#pragma unroll
+    for (int u = 0; u < kPipe; ++u) {
+      const bool use = ein[u] && row_ok;
+      const double pr = p1[u].x * p2[u].x - p1[u].y * p2[u].y;
+      const double pim = p1[u].x * p2[u].y + p1[u].y * p2[u].x;
+      T2 v = uv[u];
+      if (addback) {
+        // the previous stage's nonlocal term at this point, with the same
+        // arithmetic as k_nl_addback (FP64 sum, one rounding to the stage
+        // precision); with disjoint spheres this (orbital, point) belongs to
+        // this wavefront alone, and the lane holding the real part writes it
+        double sr = 0.0, si = 0.0;
+#pragma unroll
+        for (int p = 0; p < kMaxProj; ++p) {
+          sr += bt[u][p] * ep[p].x;
+          si += bt[u][p] * ep[p].y;
+        }
+        const double hr = pr * sr + pim * si, hi = pr * si - pim * sr;
+        v.x += (T)(a.tau * hi + a.tau_re * hr);
+        v.y += (T)(-a.tau * hr + a.tau_re * hi);
+        if (use && part == 0) urow[idx[u]] = v;
+      }
+      const double ur = (double)v.x, ui = (double)v.y;
+      const double avv = part ? (pr * ui + pim * ur) : (pr * ur - pim * ui);
+      const double av = use ? avv : 0.0;
+      const double b = ein[u] ? bv[u] : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_4x4x4f64(av, b, acc, 0, 0, 0);
+    }
   }
   if (SPLIT > 1) {
     dpart[wave][lane] = acc;
@@ -264,10 +304,19 @@ hipError_t launch_project(const ProjArgs<T>& a, hipStream_t s) {
   // 256 atoms: 0.075 -> 0.048 ms per projection; the 20^3 cell with 512
   // k-points on the per-stage path, 1024 groups x 8 atoms: 0.172 -> 0.140 ms)
   if (!a.moments) {
-    if (total < 16384)
-      hipLaunchKernelGGL((k_project_eu<T, 4>), dim3((unsigned)total), dim3(256), 0, s, a);
-    else
-      hipLaunchKernelGGL((k_project_eu<T, 1>), dim3((unsigned)((total + 3) / 4)), dim3(256), 0, s, a);
+    const bool add = a.Eu_prev != nullptr;
+    if (total < 16384) {
+      if (add)
+        hipLaunchKernelGGL((k_project_eu<T, 4, true>), dim3((unsigned)total), dim3(256), 0, s, a);
+      else
+        hipLaunchKernelGGL((k_project_eu<T, 4, false>), dim3((unsigned)total), dim3(256), 0, s, a);
+    } else {
+      const dim3 grid((unsigned)((total + 3) / 4));
+      if (add)
+        hipLaunchKernelGGL((k_project_eu<T, 1, true>), grid, dim3(256), 0, s, a);
+      else
+        hipLaunchKernelGGL((k_project_eu<T, 1, false>), grid, dim3(256), 0, s, a);
+    }
     return hipGetLastError();
   }
   if (total < 16384)

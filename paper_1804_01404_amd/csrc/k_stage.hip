@@ -414,21 +414,36 @@ __global__ void k_nl_addback(StageArgs<T> a, const int* __restrict__ ents, int n
   const int idx = a.nl.ent_idx[e];
   // the entry's table values serve the block's orbitals of this k-point
   const int j0 = blockIdx.z * ob, j1 = min(n_orb, j0 + ob);
-  for (int j = j0; j < j1; ++j) {
-    const size_t o = (size_t)k * n_orb + j;
-    const double2* eu = a.Eu + (o * a.nl.n_atoms + at) * kMaxProj;
-    double sr = 0.0, si = 0.0;
+  // kPipe orbitals at a time, every load before any store (the points of
+  // different orbitals are distinct); past j1 the last orbital is loaded again
+  // and not stored
+  constexpr int kPipe = 4;
+  for (int j = j0; j < j1; j += kPipe) {
+    double2 eu[kPipe][kMaxProj];
+    T2 v[kPipe];
+    T2* dst[kPipe];
 #pragma unroll
-    for (int p = 0; p < kMaxProj; ++p) {
-      sr += b[p] * eu[p].x;
-      si += b[p] * eu[p].y;
+    for (int u = 0; u < kPipe; ++u) {
+      const size_t o = (size_t)k * n_orb + min(j + u, j1 - 1);
+      const double2* eo = a.Eu + (o * a.nl.n_atoms + at) * kMaxProj;
+#pragma unroll
+      for (int p = 0; p < kMaxProj; ++p) eu[u][p] = eo[p];
+      dst[u] = a.out + o * N + idx;
+      v[u] = *dst[u];
     }
-    const double hr = pr * sr + pim * si, hi = pr * si - pim * sr;
-    T2* dst = a.out + o * N + idx;
-    T2 v = *dst;
-    v.x += (T)(a.tau * hi + a.tau_re * hr);
-    v.y += (T)(-a.tau * hr + a.tau_re * hi);
-    *dst = v;
+#pragma unroll
+    for (int u = 0; u < kPipe; ++u) {
+      double sr = 0.0, si = 0.0;
+#pragma unroll
+      for (int p = 0; p < kMaxProj; ++p) {
+        sr += b[p] * eu[u][p].x;
+        si += b[p] * eu[u][p].y;
+      }
+      const double hr = pr * sr + pim * si, hi = pr * si - pim * sr;
+      v[u].x += (T)(a.tau * hi + a.tau_re * hr);
+      v[u].y += (T)(-a.tau * hr + a.tau_re * hi);
+      if (j + u < j1) *dst[u] = v[u];
+    }
   }
 }
 
