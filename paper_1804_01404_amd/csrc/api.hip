@@ -293,13 +293,25 @@ tddft_status enqueue_density_potential(tddft_ctx* c) {
   if (!one) LAUNCH(launch_rho_reduce(c->rho_part, c->rho_nchunks, N, c->rho, c->stream), "rho_reduce");
   if (!c->potential_set) return TDDFT_OK;
   if (c->cfg.hartree) {
-    // the x pass packs rho into the M-box, the z pass applies the kernel K
-    for (int ax = 0; ax < 3; ++ax)
-      LAUNCH(launch_fft_axis(c->fft, c->M[0], c->M[1], c->M[2], ax, -1, c->stream, ax == 0 ? c->rho : nullptr,
-                             c->g.n1, c->g.n2, c->g.n3, ax == 2 ? c->Kfft : nullptr),
-             "fft fwd");
-    for (int ax = 0; ax < 3; ++ax)
-      LAUNCH(launch_fft_axis(c->fft, c->M[0], c->M[1], c->M[2], ax, +1, c->stream), "fft inv");
+    // rho fills the corner n1 x n2 x n3 of the M-box (all of it for a
+    // periodic cell) and only that corner of the potential is read back, so
+    // each pass transforms only the lines that hold data or are needed:
+    // forward x over y < n2, z < n3 (packing rho into the box), forward y
+    // over z < n3 (zero beyond y = n2), then along z the forward transform,
+    // the kernel K and the inverse in one pass, storing z < n3, inverse y over
+    // z < n3 storing y < n2, inverse x over y < n2, z < n3 storing x < n1
+    const int M1 = c->M[0], M2 = c->M[1], M3 = c->M[2];
+    const int n1 = c->g.n1, n2 = c->g.n2, n3 = c->g.n3;
+    LAUNCH(launch_fft_lines(c->fft, M1, M2, M3, 0, -1, c->stream, c->rho, n1, n2, n3, nullptr, n2, n3, n1, M1, 0),
+           "fft x");
+    LAUNCH(launch_fft_lines(c->fft, M1, M2, M3, 1, -1, c->stream, nullptr, 0, 0, 0, nullptr, M1, n3, n2, M2, 0),
+           "fft y");
+    LAUNCH(launch_fft_lines(c->fft, M1, M2, M3, 2, -1, c->stream, nullptr, 0, 0, 0, c->Kfft, M1, M2, n3, n3, 1),
+           "fft z, kernel, inverse z");
+    LAUNCH(launch_fft_lines(c->fft, M1, M2, M3, 1, +1, c->stream, nullptr, 0, 0, 0, nullptr, M1, n3, M2, n2, 0),
+           "inverse fft y");
+    LAUNCH(launch_fft_lines(c->fft, M1, M2, M3, 0, +1, c->stream, nullptr, 0, 0, 0, nullptr, n2, n3, M1, n1, 0),
+           "inverse fft x");
   }
   if (mgga)
     LAUNCH(launch_mgga_potential(c->rho, c->tau, mgga_args(c), c->cfg.xc == TDDFT_XC_TB09, c->dV, c->volume,

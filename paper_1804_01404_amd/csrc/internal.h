@@ -213,6 +213,13 @@ hipError_t launch_rho_reduce(const double* part, int nchunks, int N, double* rho
 hipError_t launch_fft_axis(double2* data, int M1, int M2, int M3, int axis, int sign, hipStream_t s,
                            const double* rho = nullptr, int n1 = 0, int n2 = 0, int n3 = 0,
                            const double* K = nullptr);
+// a pass over part of the box: lines (i1 < l1, i2 < l2) — (y, z) for the x
+// axis, (x, z) for y, (x, y) for z — reading elements below n_in (the rest is
+// 0) and storing those below n_out; fused (z axis, with K): forward, times K,
+// inverse in one pass
+hipError_t launch_fft_lines(double2* data, int M1, int M2, int M3, int axis, int sign, hipStream_t s,
+                            const double* rho, int n1, int n2, int n3, const double* K, int l1, int l2, int n_in,
+                            int n_out, int fused);
 hipError_t launch_xc_assemble(const double2* data, int n1, int n2, int n3, int M1, int M2, int M3,
                               double vh_scale, const double* rho, const double* Vloc, int hartree,
                               int xc, const double* vx_mgga, double* Vd, float* Vf, double* vh, double* exc,

@@ -202,8 +202,10 @@ __device__ __forceinline__ void dft_small<5>(double2* v, int sign) {
   for (int s = 0; s < 5; ++s) v[s] = o[s];
 }
 
+// twiddles of a stage: tw[jm (R - 1) + r - 1] = exp(sign 2 pi i r jm / (Ns R)), jm < Ns
 template <int R>
-__device__ void stockham_stage(const double2* in, double2* out, int B, int M, int Ns, int sign) {
+__device__ void stockham_stage(const double2* in, double2* out, int B, int M, int Ns, int sign,
+                               const double2* tw) {
   const int nb = M / R;
   for (int t = threadIdx.x; t < B * nb; t += blockDim.x) {
     const int line = t / nb;
@@ -215,11 +217,7 @@ __device__ void stockham_stage(const double2* in, double2* out, int B, int M, in
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       v[r] = li[jj + r * nb];
-      if (r > 0 && jm != 0) {
-        double sn, cs;
-        sincospi(2.0 * sign * (double)(r * jm) / (double)(Ns * R), &sn, &cs);
-        v[r] = cmul(v[r], make_double2(cs, sn));
-      }
+      if (r > 0 && jm != 0) v[r] = cmul(v[r], tw[jm * (R - 1) + r - 1]);
     }
     dft_small<R>(v, sign);
     const int d = (jj / Ns) * Ns * R + jm;
@@ -228,35 +226,83 @@ __device__ void stockham_stage(const double2* in, double2* out, int B, int M, in
   }
 }
 
+// the twiddles of every stage of the plan, stage after stage (M - 1 values)
+__device__ void fft_twiddles(const FFTPlan& plan, int sign, double2* tw) {
+  int off = 0, Ns = 1;
+  for (int f = 0; f < plan.nf; ++f) {
+    const int R = plan.f[f];
+    for (int t = threadIdx.x; t < Ns * (R - 1); t += blockDim.x) {
+      const int jm = t / (R - 1), r = t - jm * (R - 1) + 1;
+      double sn, cs;
+      sincospi(2.0 * sign * (double)(r * jm) / (double)(Ns * R), &sn, &cs);
+      tw[off + t] = make_double2(cs, sn);
+    }
+    off += Ns * (R - 1);
+    Ns *= R;
+  }
+}
+
+// the plan's stages on B lines of length M in LDS (in -> out alternating);
+// returns the buffer that holds the result
+__device__ double2* fft_lines_lds(const FFTPlan& plan, double2* in, double2* out, int nl, int sign,
+                                  const double2* tw) {
+  const int M = plan.M;
+  int Ns = 1, off = 0;
+  for (int f = 0; f < plan.nf; ++f) {
+    const int R = plan.f[f];
+    if (R == 4) stockham_stage<4>(in, out, nl, M, Ns, sign, tw + off);
+    else if (R == 2) stockham_stage<2>(in, out, nl, M, Ns, sign, tw + off);
+    else if (R == 3) stockham_stage<3>(in, out, nl, M, Ns, sign, tw + off);
+    else stockham_stage<5>(in, out, nl, M, Ns, sign, tw + off);
+    __syncthreads();
+    off += Ns * (R - 1);
+    Ns *= R;
+    double2* t = in;
+    in = out;
+    out = t;
+  }
+  return in;
+}
+
 // Optional ends of the Poisson solve, so that they cost no launch of their
 // own: rho (n1 x n2 x n3, zero beyond it in the M-box) is read in place of
-// data by the first (x) pass, and the stored result is multiplied by K by the
-// last forward (z) pass.
+// data by the first (x) pass, and the result is multiplied by K (the Poisson
+// kernel) by the z pass.
 struct FFTEnds {
   const double* rho;
   int n1, n2, n3;
   const double* K;
 };
 
+// The lines a pass transforms and the part of each it reads and writes: lines
+// (i1, i2) with i1 < l1, i2 < l2 — (y, z) for the x axis, (x, z) for y, (x, y)
+// for z — elements at or beyond n_in read as 0, elements at or beyond n_out
+// not stored. fused (z axis): forward transform, times K, inverse transform
+// with the opposite sign, in one pass.
+struct FFTLines {
+  int l1, l2, n_in, n_out, fused;
+};
+
 __global__ __launch_bounds__(256) void k_fft_axis(double2* data, int M1, int M2, int M3, int axis,
-                                                  int sign, int B, FFTPlan plan, FFTEnds ends) {
+                                                  int sign, int B, FFTPlan plan, FFTEnds ends, FFTLines ln) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  double2* buf0 = reinterpret_cast<double2*>(smem_raw);
   const int M = plan.M;
+  double2* buf0 = reinterpret_cast<double2*>(smem_raw);
   double2* buf1 = buf0 + (size_t)B * M;
-  const long total = (long)M1 * M2 * M3;
-  const long nlines = total / M;
+  double2* tw = buf1 + (size_t)B * M;   // M entries
+  double2* twi = tw + M;                // M entries (fused: the inverse's)
+  const long nlines = (long)ln.l1 * ln.l2;
   const long L0 = (long)blockIdx.x * B;
   const int nl = (int)min((long)B, nlines - L0);
   const long stride = (axis == 0) ? 1 : (axis == 1 ? M1 : (long)M1 * M2);
   auto line_base = [&](long L) -> long {
-    if (axis == 0) return L * M1;
-    if (axis == 1) {
-      const long z = L / M1, x = L - z * M1;
-      return z * (long)M1 * M2 + x;
-    }
-    return L;  // axis 2: L = y * M1 + x
+    const long i2 = L / ln.l1, i1 = L - i2 * ln.l1;
+    if (axis == 0) return (i2 * M2 + i1) * M1;
+    if (axis == 1) return i2 * (long)M1 * M2 + i1;
+    return i2 * M1 + i1;
   };
+  fft_twiddles(plan, sign, tw);
+  if (ln.fused) fft_twiddles(plan, -sign, twi);
   // load
   for (int i = threadIdx.x; i < nl * M; i += blockDim.x) {
     int line, e;
@@ -267,31 +313,30 @@ __global__ __launch_bounds__(256) void k_fft_axis(double2* data, int M1, int M2,
       e = i / nl;
       line = i - e * nl;
     }
-    const long gi = line_base(L0 + line) + (long)e * stride;
-    if (ends.rho) {
-      const int x = (int)(gi % M1), y = (int)((gi / M1) % M2), z = (int)(gi / ((long)M1 * M2));
-      double v = 0.0;
-      if (x < ends.n1 && y < ends.n2 && z < ends.n3) v = ends.rho[((size_t)z * ends.n2 + y) * ends.n1 + x];
-      buf0[line * M + e] = make_double2(v, 0.0);
-    } else {
-      buf0[line * M + e] = data[gi];
+    double2 v = make_double2(0.0, 0.0);
+    if (e < ln.n_in) {
+      const long gi = line_base(L0 + line) + (long)e * stride;
+      if (ends.rho) {
+        const int x = (int)(gi % M1), y = (int)((gi / M1) % M2), z = (int)(gi / ((long)M1 * M2));
+        if (x < ends.n1 && y < ends.n2 && z < ends.n3)
+          v = make_double2(ends.rho[((size_t)z * ends.n2 + y) * ends.n1 + x], 0.0);
+      } else {
+        v = data[gi];
+      }
     }
+    buf0[line * M + e] = v;
   }
   __syncthreads();
-  double2* in = buf0;
-  double2* out = buf1;
-  int Ns = 1;
-  for (int f = 0; f < plan.nf; ++f) {
-    const int R = plan.f[f];
-    if (R == 4) stockham_stage<4>(in, out, nl, M, Ns, sign);
-    else if (R == 2) stockham_stage<2>(in, out, nl, M, Ns, sign);
-    else if (R == 3) stockham_stage<3>(in, out, nl, M, Ns, sign);
-    else stockham_stage<5>(in, out, nl, M, Ns, sign);
+  double2* res = fft_lines_lds(plan, buf0, buf1, nl, sign, tw);
+  if (ln.fused) {
+    for (int i = threadIdx.x; i < nl * M; i += blockDim.x) {
+      const int e = i / nl, line = i - e * nl;
+      const double k = ends.K[line_base(L0 + line) + (long)e * stride];
+      const double2 v = res[line * M + e];
+      res[line * M + e] = make_double2(v.x * k, v.y * k);
+    }
     __syncthreads();
-    Ns *= R;
-    double2* t = in;
-    in = out;
-    out = t;
+    res = fft_lines_lds(plan, res, res == buf0 ? buf1 : buf0, nl, -sign, twi);
   }
   for (int i = threadIdx.x; i < nl * M; i += blockDim.x) {
     int line, e;
@@ -302,9 +347,10 @@ __global__ __launch_bounds__(256) void k_fft_axis(double2* data, int M1, int M2,
       e = i / nl;
       line = i - e * nl;
     }
+    if (e >= ln.n_out) continue;
     const long gi = line_base(L0 + line) + (long)e * stride;
-    double2 v = in[line * M + e];
-    if (ends.K) {
+    double2 v = res[line * M + e];
+    if (ends.K && !ln.fused) {
       const double k = ends.K[gi];
       v = make_double2(v.x * k, v.y * k);
     }
@@ -312,8 +358,9 @@ __global__ __launch_bounds__(256) void k_fft_axis(double2* data, int M1, int M2,
   }
 }
 
-hipError_t launch_fft_axis(double2* data, int M1, int M2, int M3, int axis, int sign, hipStream_t s,
-                           const double* rho, int n1, int n2, int n3, const double* K) {
+hipError_t launch_fft_lines(double2* data, int M1, int M2, int M3, int axis, int sign, hipStream_t s,
+                            const double* rho, int n1, int n2, int n3, const double* K, int l1, int l2, int n_in,
+                            int n_out, int fused) {
   FFTPlan plan;
   plan.M = axis == 0 ? M1 : (axis == 1 ? M2 : M3);
   plan.nf = 0;
@@ -326,16 +373,26 @@ hipError_t launch_fft_axis(double2* data, int M1, int M2, int M3, int axis, int 
     }
   }
   if (rem != 1) return hipErrorInvalidValue;
-  const long nlines = (long)M1 * M2 * M3 / plan.M;
+  if (fused && (axis != 2 || !K)) return hipErrorInvalidValue;
+  const long nlines = (long)l1 * l2;
+  if (nlines <= 0) return hipSuccess;
   // lines per workgroup: up to 2048 points, but small boxes are spread over at
   // least 64 workgroups (each line is transformed the same way wherever it runs)
   int B = max(1, min(256, 2048 / plan.M));
   while (B > 1 && nlines / B < 64) B /= 2;
-  const size_t lds = (size_t)2 * B * plan.M * sizeof(double2);
+  const size_t lds = ((size_t)2 * B * plan.M + 2 * (size_t)plan.M) * sizeof(double2);
   FFTEnds ends{rho, n1, n2, n3, K};
-  hipLaunchKernelGGL(k_fft_axis, dim3((unsigned)((nlines + B - 1) / B)), dim3(256), lds, s, data, M1,
-                     M2, M3, axis, sign, B, plan, ends);
+  FFTLines ln{l1, l2, n_in, n_out, fused};
+  hipLaunchKernelGGL(k_fft_axis, dim3((unsigned)((nlines + B - 1) / B)), dim3(256), lds, s, data, M1, M2, M3,
+                     axis, sign, B, plan, ends, ln);
   return hipGetLastError();
+}
+
+hipError_t launch_fft_axis(double2* data, int M1, int M2, int M3, int axis, int sign, hipStream_t s,
+                           const double* rho, int n1, int n2, int n3, const double* K) {
+  const int l1 = axis == 0 ? M2 : M1, l2 = axis == 2 ? M2 : M3;
+  const int M = axis == 0 ? M1 : (axis == 1 ? M2 : M3);
+  return launch_fft_lines(data, M1, M2, M3, axis, sign, s, rho, n1, n2, n3, K, l1, l2, M, M, 0);
 }
 
 // ---------------------------------------------------------------- LDA + V
