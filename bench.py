@@ -18,9 +18,10 @@ beside it. The JSON line also carries the roofline of the dominant kernel
 launches on the library's stream) and the CPU oracle timed on the host cores
 (one worker process per core) on a bounded sample of the same workload.
 Further lines run the other workloads at their stated shapes: the 96^3
-cluster with all 512 orbitals, the 64-cell uneven batch with 8-64 orbitals
-and 1-64 k-points, and the multiscale slab of 256 cells (16^3, 16 orbitals,
-64 k-points).
+cluster with all 512 orbitals (mixed, and a complex128 twin), the 64-cell
+uneven batch with 8-64 orbitals and 1-64 k-points, and the multiscale slab of
+256 cells (16^3, 16 orbitals, 64 k-points); a plain device copy gives the
+streaming rate of the box.
 """
 import argparse
 import json
@@ -374,7 +375,34 @@ def bench_cluster(steps=5, warmup=2, n_orb=512):
            "current_finite": bool(np.all(np.isfinite(J)))}
     out.update(per_stage_figures(s, kern, 8, "cluster96_orb512" if n_orb == 512 else None))
     out["mfma_projection"] = mfma_projection(s, kern["project_ms"], 8)
+    # the complex128 twin of the same cell (three timed steps)
+    log("  cluster complex128 twin")
+    ms64, dev64, kern64, _ = time_path(s, "c128", 3, 1)
+    out["c128"] = {"ms_per_step": ms64, "device_ms_per_step": dev64, "value": s.og / (ms64 * 1e-3),
+                   "stage_ms": kern64["stage_ms"], "steps": 3, "warmup": 1}
+    out["speedup_mixed_over_c128"] = ms64 / ms
     return out
+
+
+def copy_bandwidth(mib=2048, reps=10):
+    """A plain device-to-device copy of mib MiB (torch's copy kernel), timed
+    with HIP events: the streaming rate this machine reaches, beside which the
+    kernels' HBM fractions can be read."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    gbs = 2 * n * 4 / (ms * 1e-3) / 1e9
+    del src, dst
+    return {"bytes_per_copy": 2 * n * 4, "ms": ms, "GBs": gbs, "frac_hbm": gbs / HBM_PEAK_GBS}
 
 
 def bench_batch(steps=12, warmup=6):
@@ -638,6 +666,8 @@ def main():
         "mfma_projection": mfma_projection(s, kern["project_ms"], esz),
         "current_finite": bool(np.all(np.isfinite(J))),
     }
+    log("copy bandwidth")
+    out["copy_bandwidth"] = copy_bandwidth()
     if not args.no_twin:
         log("complex128 twin")
         other = "c128" if args.precision == "mixed" else "mixed"
