@@ -487,6 +487,34 @@ def bench_multiscale():
             "loss_first_last": [float(losses[0]), float(losses[-1])]}
 
 
+def sentinel_error_scan(cell, psi, nn, kw, n_mat, e0, dt, dx, n_macro=4000, every=25):
+    """The coupled run over n_macro macroscopic steps under a 20 fs cos^2 pulse
+    of peak field e0 through the network, with the spot-check threshold and the
+    amplitude gate out of reach (so it never falls back): the sentinel error
+    met at each check (every `every` steps), relative to the output scale."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_1804_01404_amd.binding import Multiscale
+    T20 = 20.0 * 41.341373335
+    inc = synth.incident_table(n_macro, dt, dx, delay=0.0, E0=e0, omega=1.55 / 27.211386245988, T=T20)
+    errs = []
+    with Multiscale(cell, psi, precision="mixed", **kw) as ms:
+        ms.attach_surrogate(nn, a_max=1e30, sentinels=[0, n_mat // 2], check_every=every, tol=1e30)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for c in range(0, n_macro, every):
+            ms.step(every, inc[c:c + every + 1])
+            errs.append(ms.status()["last_check"])
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+    over = [i for i, e in enumerate(errs) if e > 1e-3]
+    return {"macro_steps": n_macro, "pulse": f"cos^2, 1.55 eV, T = 20 fs, E0 {e0:g}", "checks": len(errs),
+            "max_error": max(errs), "checks_over_1e-3": len(over),
+            "first_step_over_1e-3": (over[0] + 1) * every if over else None,
+            "ms_per_macro_step": el / n_macro * 1e3}
+
+
 def bench_multiscale_cfg5(n_macro=600, timed_cells=8, n_traj=64, e0=5.34e-3, a_train=16.0):
     """The multiscale workload at its cell shape and point count: 256 medium
     points (plus 64 vacuum points on each side), each a 16^3 diamond cell with
@@ -497,7 +525,9 @@ def bench_multiscale_cfg5(n_macro=600, timed_cells=8, n_traj=64, e0=5.34e-3, a_t
     the cells path per macroscopic step (timed_cells steps), and the coupled
     run through a network with a 512-step window trained on n_traj
     trajectories of this cell (batch path), two sentinel cells checked every
-    25 steps at the spot-check error 1e-3, with its fallback status."""
+    25 steps at the spot-check error 1e-3, with its fallback status; then the
+    stated 4000-step run under the 20 fs pulse through the same network as a
+    scan of the sentinel errors it meets (no fallback taken)."""
     import numpy as np
     import torch
     import synth
@@ -541,6 +571,8 @@ def bench_multiscale_cfg5(n_macro=600, timed_cells=8, n_traj=64, e0=5.34e-3, a_t
     with nn:
         An, _, tn, st = pipeline.run_slab(cell, psi, inc, precision="mixed", nn=nn, a_max=a_scale,
                                           sentinels=[0, n_mat // 2], check_every=25, tol=1e-3, **kw)
+        log("  cfg5 slab: 4000-step sentinel error scan (20 fs pulse)")
+        long_scan = sentinel_error_scan(cell, psi, nn, kw, n_mat, e0, dt, dx)
     return {"workload": f"multiscale-256X: {n_mat} cells (16^3, 16 orbitals, 64 k-points, mixed) + "
                         f"{2 * n_vac} vacuum points, dX 147.6, dt 0.32 = 4 cell steps of 0.08",
             "og_per_macro_step": og_macro, "cells_ms_per_macro_step": t_cells * 1e3,
@@ -549,6 +581,7 @@ def bench_multiscale_cfg5(n_macro=600, timed_cells=8, n_traj=64, e0=5.34e-3, a_t
                               "ms_per_macro_step": tn / n_macro * 1e3,
                               "speedup_over_cells_per_step": t_cells / (tn / n_macro), "status": st,
                               "sentinel_tol": 1e-3, "pulse": f"cos^2, 1.55 eV, T = 100 a.u., E0 {e0:g}"},
+            "long_run_sentinel_scan": long_scan,
             "ground_state_s": t_gs, "zero_field_current_rel": float(np.max(np.abs(J0)) / j_scale),
             "training_a_max": a_scale, "trajectories": n_traj, "trajectory_steps": n_macro, "trajectories_s": t_gen, "train_s": t_train,
             "loss_first_last": [float(losses[0]), float(losses[-1])]}
