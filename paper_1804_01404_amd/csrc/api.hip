@@ -1775,6 +1775,15 @@ struct BatchGroup {
   std::vector<std::pair<int, int>> cand;  // (zs, workgroups)
   std::vector<double> cand_ms;
   hipEvent_t e0 = nullptr, e1 = nullptr;
+  // the end of the step (current, density, Poisson, xc) as one launch per
+  // kernel over the group's cells, when they all take the same kernels
+  bool tail_ok = false;
+  int max_chunks = 1;
+  TailCell* d_tail = nullptr;
+  // the start of the step (field, kappa, phases, coefficients) for all cells
+  ParamCell* d_par = nullptr;
+  int max_S = 0, max_nk = 0;
+  long max_phases = 0;
 };
 
 }  // namespace
@@ -1874,6 +1883,32 @@ tddft_status batch_plan(tddft_batch* b) {
     g.wgs = b->n_cu;
     BHIP(hipEventCreate(&g.e0));
     BHIP(hipEventCreate(&g.e1));
+    // one tail launch per kernel for the whole group when every cell runs
+    // the same tail kernels (LDA or no xc, the same Hartree switch and box)
+    const tddft_ctx* c0 = b->cells[g.cells[0]];
+    g.tail_ok = true;
+    for (int i : g.cells) {
+      const tddft_ctx* c = b->cells[i];
+      g.max_chunks = std::max(g.max_chunks, c->rho_nchunks);
+      if (is_mgga(c) || c->cfg.hartree != c0->cfg.hartree || c->cfg.xc != c0->cfg.xc ||
+          c->rho_chunk != c0->rho_chunk || c->N != c0->N || c->M[0] != c0->M[0] || c->M[1] != c0->M[1] ||
+          c->M[2] != c0->M[2])
+        g.tail_ok = false;
+    }
+    if (g.tail_ok) {
+      BHIP(hipMalloc(&p, g.cells.size() * sizeof(TailCell)));
+      b->allocs.push_back(p);
+      g.d_tail = static_cast<TailCell*>(p);
+    }
+    for (int i : g.cells) {
+      const tddft_ctx* c = b->cells[i];
+      g.max_S = std::max(g.max_S, c->nl.n_ent);
+      g.max_nk = std::max(g.max_nk, c->cfg.n_k);
+      g.max_phases = std::max(g.max_phases, (long)c->cfg.n_k * c->nl.n_ent);
+    }
+    BHIP(hipMalloc(&p, g.cells.size() * sizeof(ParamCell)));
+    b->allocs.push_back(p);
+    g.d_par = static_cast<ParamCell*>(p);
   }
   // per-stage cells: longest-processing-time-first over up to four streams
   const int L = std::min<int>(4, (int)streaming.size());
@@ -1903,15 +1938,115 @@ tddft_status batch_plan(tddft_batch* b) {
   return TDDFT_OK;
 }
 
+// the group tail tables from the cells' current buffers (a cell's A and J
+// tables move when a longer run needs more room)
+tddft_status batch_tail_upload(tddft_batch* b) {
+  for (auto& g : b->groups) {
+    std::vector<ParamCell> par(g.cells.size());
+    for (size_t j = 0; j < g.cells.size(); ++j) {
+      tddft_ctx* c = b->cells[g.cells[j]];
+      ParamCell& q = par[j];
+      q.A = c->Atab;
+      q.counter = c->counter;
+      q.kpt = c->kpt_d;
+      q.n_k = c->cfg.n_k;
+      q.S = c->nl.n_ent;
+      q.gauge = c->cfg.gauge;
+      q.ent_x = c->ent_x;
+      q.dt = c->cfg.dt;
+      q.kappa = c->kappa;
+      q.kappaJ = c->kappaJ;
+      q.efield = c->efield;
+      q.phA = c->phA;
+      q.phAJ = c->phAJ;
+      q.Alast = c->Alast;
+      std::memcpy(q.dh, c->dh, sizeof(q.dh));
+      q.cdiag = c->cdiag;
+      q.coef = c->coef;
+      q.phk = c->nl.phk;
+      q.phkA = c->phkA;
+    }
+    BHIP(hipMemcpyAsync(g.d_par, par.data(), par.size() * sizeof(ParamCell), hipMemcpyHostToDevice, b->stream));
+    BHIP(hipStreamSynchronize(b->stream));
+    if (!g.tail_ok) continue;
+    std::vector<TailCell> tab(g.cells.size());
+    for (size_t j = 0; j < g.cells.size(); ++j) {
+      tddft_ctx* c = b->cells[g.cells[j]];
+      TailCell& t = tab[j];
+      t.w = c->W;
+      t.kw = c->kw_d;
+      t.n_orb = c->cfg.n_orb;
+      t.n_k = c->cfg.n_k;
+      t.nchunks = c->rho_nchunks;
+      t.rho_out = c->rho_nchunks == 1 ? c->rho : c->rho_part;
+      t.rho_part = c->rho_part;
+      t.rho = c->rho;
+      t.fft = c->fft;
+      t.Kfft = c->Kfft;
+      t.vh_scale = c->vh_scale;
+      t.Vloc = c->Vloc;
+      t.Vd = c->Vd;
+      t.Vf = c->Vf;
+      t.vh = c->vh;
+      t.exc = c->exc;
+      t.obs = c->obs;
+      t.jnl = c->jnl;
+      t.use_nl = c->nl.n_atoms > 0 ? 1 : 0;
+      t.kappaJ = c->kappaJ;
+      t.dV = c->dV;
+      t.volume = c->volume;
+      t.counter = c->counter;
+      t.Jtab = c->Jtab;
+      t.scalars = c->scalars;
+      t.nanflag = c->nanflag;
+      t.norm_tol = norm_tol(c);
+    }
+    BHIP(hipMemcpyAsync(g.d_tail, tab.data(), tab.size() * sizeof(TailCell), hipMemcpyHostToDevice, b->stream));
+    BHIP(hipStreamSynchronize(b->stream));
+  }
+  return TDDFT_OK;
+}
+
+// the end of the step for every cell of a group, one launch per kernel: the
+// same kernels and order as enqueue_fused_tail applied to each cell
+template <typename T>
+tddft_status enqueue_group_tail(tddft_batch* b, const BatchGroup& g, hipStream_t s) {
+  const tddft_ctx* c0 = b->cells[g.cells[0]];
+  const int nc = (int)g.cells.size();
+  const int N = (int)c0->N;
+  BHIP(launch_finish_group(g.d_tail, nc, 1, s));
+  BHIP(launch_rho_partial_group<T>(g.d_tail, nc, N, c0->rho_chunk, g.max_chunks, s));
+  if (g.max_chunks > 1) BHIP(launch_rho_reduce_group(g.d_tail, nc, N, s));
+  const int M1 = c0->M[0], M2 = c0->M[1], M3 = c0->M[2];
+  const int n1 = c0->g.n1, n2 = c0->g.n2, n3 = c0->g.n3;
+  if (c0->cfg.hartree) {
+    BHIP(launch_fft_lines_group(g.d_tail, nc, M1, M2, M3, 0, -1, 1, n1, n2, n3, 0, n2, n3, n1, M1, 0, s));
+    BHIP(launch_fft_lines_group(g.d_tail, nc, M1, M2, M3, 1, -1, 0, n1, n2, n3, 0, M1, n3, n2, M2, 0, s));
+    BHIP(launch_fft_lines_group(g.d_tail, nc, M1, M2, M3, 2, -1, 0, n1, n2, n3, 1, M1, M2, n3, n3, 1, s));
+    BHIP(launch_fft_lines_group(g.d_tail, nc, M1, M2, M3, 1, +1, 0, n1, n2, n3, 0, M1, n3, M2, n2, 0, s));
+    BHIP(launch_fft_lines_group(g.d_tail, nc, M1, M2, M3, 0, +1, 0, n1, n2, n3, 0, n2, n3, M1, n1, 0, s));
+  }
+  BHIP(launch_xc_group(g.d_tail, nc, n1, n2, n3, M1, M2, c0->cfg.hartree, c0->cfg.xc, s));
+  return TDDFT_OK;
+}
+
 // One batch step. timing: bracket each group's persistent launch with events.
 template <typename T>
 tddft_status batch_step(tddft_batch* b, bool timing) {
-  for (size_t i = 0; i < b->cells.size(); ++i) {
-    tddft_ctx* c = b->cells[i];
-    c->stream = b->stream;
-    tddft_status st = enqueue_params(c);
-    if (st != TDDFT_OK) return bcell(b, st, (int)i);
+  // the start of the step: one launch per kernel for each fused group, per
+  // cell for the per-stage lanes (the same kernels and arithmetic either way)
+  for (auto& g : b->groups) {
+    const int nc = (int)g.cells.size();
+    BHIP(launch_step_params_group(g.d_par, nc, g.max_S, b->stream));
+    BHIP(launch_fused_coef_group<T>(g.d_par, nc, g.max_nk, g.max_phases, b->stream));
   }
+  for (auto& lane : b->lanes)
+    for (int i : lane) {
+      tddft_ctx* c = b->cells[i];
+      c->stream = b->stream;
+      tddft_status st = enqueue_params(c);
+      if (st != TDDFT_OK) return bcell(b, st, i);
+    }
   BHIP(hipEventRecord(b->fork, b->stream));
   int si = 0;
   for (auto& g : b->groups) {
@@ -1922,12 +2057,17 @@ tddft_status batch_step(tddft_batch* b, bool timing) {
     BHIP(launch_fused_persistent<T>(g.n, g.zs, g.periodic, static_cast<const FusedArgs<T>*>(g.d_args), g.d_items,
                                     g.n_items, g.d_queue, g.wgs, g.lds, s));
     if (timing) BHIP(hipEventRecord(g.e1, s));
-    for (int i : g.cells) {
-      tddft_ctx* c = b->cells[i];
-      c->stream = s;
-      tddft_status st = enqueue_fused_tail<T>(c);
-      c->stream = b->stream;
-      if (st != TDDFT_OK) return bcell(b, st, i);
+    if (g.tail_ok) {
+      tddft_status st = enqueue_group_tail<T>(b, g, s);
+      if (st != TDDFT_OK) return st;
+    } else {
+      for (int i : g.cells) {
+        tddft_ctx* c = b->cells[i];
+        c->stream = s;
+        tddft_status st = enqueue_fused_tail<T>(c);
+        c->stream = b->stream;
+        if (st != TDDFT_OK) return bcell(b, st, i);
+      }
     }
     BHIP(hipEventRecord(b->side_done[si], s));
     ++si;
@@ -1953,6 +2093,10 @@ template <typename T>
 tddft_status batch_propagate(tddft_batch* b, int32_t nsteps) {
   if (!b->planned) {
     tddft_status st = batch_plan<T>(b);
+    if (st != TDDFT_OK) return st;
+  }
+  {
+    tddft_status st = batch_tail_upload(b);
     if (st != TDDFT_OK) return st;
   }
   int done = 0;

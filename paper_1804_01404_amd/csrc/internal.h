@@ -220,6 +220,76 @@ hipError_t launch_fft_axis(double2* data, int M1, int M2, int M3, int axis, int 
 hipError_t launch_fft_lines(double2* data, int M1, int M2, int M3, int axis, int sign, hipStream_t s,
                             const double* rho, int n1, int n2, int n3, const double* K, int l1, int l2, int n_in,
                             int n_out, int fused);
+// Per-cell arguments of the end of a step (current, density, Poisson, xc)
+// when a group of same-shape cells runs it with one launch per kernel: the
+// cell is a grid dimension and each cell's pointers come from this table.
+struct TailCell {
+  const void* w;          // orbitals [n_orb n_k][N], stage precision
+  const double* kw;       // [n_k]
+  int n_orb, n_k, nchunks;
+  double* rho_out;        // the density pass's output: rho with one chunk, else rho_part
+  double* rho_part;       // [nchunks][N]
+  double* rho;            // [N]
+  double2* fft;           // M-box
+  const double* Kfft;     // Poisson kernel on the M-box
+  double vh_scale;
+  const double* Vloc;
+  double* Vd;
+  float* Vf;
+  double* vh;
+  double* exc;
+  const double* obs;      // [n_orb n_k][tiles][8]
+  const double* jnl;      // [n_orb n_k][4] or nullptr
+  int use_nl;
+  const double* kappaJ;
+  double dV, volume;
+  int* counter;
+  double* Jtab;
+  double* scalars;
+  int* nanflag;
+  double norm_tol;
+};
+
+// Per-cell arguments of the start of a fused step (field, kappa and phases,
+// the stencil coefficients, the per-k sphere phases) for one launch per
+// kernel over a group of cells.
+struct ParamCell {
+  const double* A;        // A table [..][3]
+  const int* counter;
+  const double* kpt;      // [n_k][3]
+  int n_k, S, gauge;
+  const double* ent_x;    // [S][3]
+  double dt;
+  double* kappa;
+  double* kappaJ;
+  double* efield;
+  double2* phA;
+  double2* phAJ;
+  double* Alast;
+  double dh[3][4];
+  double cdiag;
+  void* coef;             // [n_k][16] stage precision
+  const double2* phk;     // [n_k][S]
+  double2* phkA;          // [n_k][S]
+};
+
+hipError_t launch_step_params_group(const ParamCell* tab, int ncells, int max_S, hipStream_t s);
+template <typename T>
+hipError_t launch_fused_coef_group(const ParamCell* tab, int ncells, int max_nk, long max_phases, hipStream_t s);
+
+template <typename T>
+hipError_t launch_rho_partial_group(const TailCell* tab, int ncells, int N, int chunk, int max_chunks,
+                                    hipStream_t s);
+hipError_t launch_rho_reduce_group(const TailCell* tab, int ncells, int N, hipStream_t s);
+// as launch_fft_lines for every cell of tab (same box and lines); use_rho /
+// use_K: the pass reads the cell's rho / multiplies by its K
+hipError_t launch_fft_lines_group(const TailCell* tab, int ncells, int M1, int M2, int M3, int axis, int sign,
+                                  int use_rho, int n1, int n2, int n3, int use_K, int l1, int l2, int n_in,
+                                  int n_out, int fused, hipStream_t s);
+hipError_t launch_xc_group(const TailCell* tab, int ncells, int n1, int n2, int n3, int M1, int M2, int hartree,
+                           int xc, hipStream_t s);
+hipError_t launch_finish_group(const TailCell* tab, int ncells, int tiles, hipStream_t s);
+
 hipError_t launch_xc_assemble(const double2* data, int n1, int n2, int n3, int M1, int M2, int M3,
                               double vh_scale, const double* rho, const double* Vloc, int hartree,
                               int xc, const double* vx_mgga, double* Vd, float* Vf, double* vh, double* exc,

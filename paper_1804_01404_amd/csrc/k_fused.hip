@@ -576,30 +576,68 @@ __global__ __launch_bounds__(MAXT) void k_fused_persistent(const FusedArgs<T>* _
 // the step midpoint): kappa_mu d_m / h_mu and the diagonal
 // -1/2 sum_mu c_0 / h_mu^2 + |kappa|^2 / 2
 template <typename T>
-__global__ void k_fused_coef(const double* __restrict__ kappa, int n_k, FusedCoefIn in, T* __restrict__ coef) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n_k) return;
+__device__ __forceinline__ void fused_coef_k(const double* __restrict__ kappa, const double (&dh)[3][4], double cdiag,
+                                             T* __restrict__ coef, int k) {
   const double kx = kappa[3 * k], ky = kappa[3 * k + 1], kz = kappa[3 * k + 2];
   T* c = coef + (size_t)k * kCoef;
   for (int m = 0; m < 4; ++m) {
-    c[m] = (T)(kx * in.dh[0][m]);
-    c[4 + m] = (T)(ky * in.dh[1][m]);
-    c[8 + m] = (T)(kz * in.dh[2][m]);
+    c[m] = (T)(kx * dh[0][m]);
+    c[4 + m] = (T)(ky * dh[1][m]);
+    c[8 + m] = (T)(kz * dh[2][m]);
   }
-  c[12] = (T)(in.cdiag + 0.5 * (kx * kx + ky * ky + kz * kz));
+  c[12] = (T)(cdiag + 0.5 * (kx * kx + ky * ky + kz * kz));
   c[13] = c[14] = c[15] = (T)0;
+}
+
+template <typename T>
+__global__ void k_fused_coef(const double* __restrict__ kappa, int n_k, FusedCoefIn in, T* __restrict__ coef) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_k) return;
+  fused_coef_k<T>(kappa, in.dh, in.cdiag, coef, k);
 }
 
 // exp(i kappa . x_e) = exp(i k . x_e) exp(i A . x_e / c) for every k-point and
 // sphere entry, once per step (each workgroup then reads one factor per entry)
-__global__ void k_fused_phase(const double2* __restrict__ phk, const double2* __restrict__ phA, int S, int n_k,
-                              double2* __restrict__ out) {
-  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (size_t)n_k * S) return;
+__device__ __forceinline__ void fused_phase_t(const double2* __restrict__ phk, const double2* __restrict__ phA, int S,
+                                              double2* __restrict__ out, size_t t) {
   const int e = (int)(t % S);
   const double2 p1 = phk[t], p2 = phA[e];
   out[t] = make_double2(p1.x * p2.x - p1.y * p2.y, p1.x * p2.y + p1.y * p2.x);
 }
+
+__global__ void k_fused_phase(const double2* __restrict__ phk, const double2* __restrict__ phA, int S, int n_k,
+                              double2* __restrict__ out) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (size_t)n_k * S) return;
+  fused_phase_t(phk, phA, S, out, t);
+}
+
+// the same two for the cells of a group (cell blockIdx.y)
+template <typename T>
+__global__ void k_fused_coef_group(const ParamCell* __restrict__ tab) {
+  const ParamCell& c = tab[blockIdx.y];
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= c.n_k) return;
+  fused_coef_k<T>(c.kappa, c.dh, c.cdiag, static_cast<T*>(c.coef), k);
+}
+
+__global__ void k_fused_phase_group(const ParamCell* __restrict__ tab) {
+  const ParamCell& c = tab[blockIdx.y];
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c.S == 0 || t >= (size_t)c.n_k * c.S) return;
+  fused_phase_t(c.phk, c.phA, c.S, c.phkA, t);
+}
+
+template <typename T>
+hipError_t launch_fused_coef_group(const ParamCell* tab, int ncells, int max_nk, long max_phases, hipStream_t s) {
+  hipLaunchKernelGGL((k_fused_coef_group<T>), dim3((unsigned)((max_nk + 63) / 64), ncells), dim3(64), 0, s, tab);
+  if (max_phases > 0)
+    hipLaunchKernelGGL(k_fused_phase_group, dim3((unsigned)((max_phases + 255) / 256), ncells), dim3(256), 0, s,
+                       tab);
+  return hipGetLastError();
+}
+template hipError_t launch_fused_coef_group<double>(const ParamCell*, int, int, long, hipStream_t);
+template hipError_t launch_fused_coef_group<float>(const ParamCell*, int, int, long, hipStream_t);
 
 template <typename T>
 hipError_t launch_fused_coef(const FusedArgs<T>& a, hipStream_t s) {

@@ -12,10 +12,11 @@ namespace td {
 // kappa = k + (A_n + A_{n+1}) / (2c), kappaJ = k + A_{n+1} / c, and the
 // matching sphere phases exp(i A.x / c). Length gauge: kappa = kappaJ = k,
 // unit phases, E_n = -(A_{n+1} - A_n) / (c dt).
-__global__ void k_step_params(const double* A, const int* counter, int use_counter,
-                              const double* kpt, int n_k, const double* ent_x, int S, int gauge,
-                              double dt, double* kappa, double* kappaJ, double* efield,
-                              double2* phA, double2* phAJ, double* Alast) {
+__device__ __forceinline__ void step_params_block(const double* A, const int* counter, int use_counter,
+                                                  const double* kpt, int n_k, const double* ent_x, int S,
+                                                  int gauge, double dt, double* kappa, double* kappaJ,
+                                                  double* efield, double2* phA, double2* phAJ, double* Alast,
+                                                  int bx) {
   const int n = use_counter ? *counter : 0;
   const double* A0 = A + 3 * (size_t)n;
   const double* A1 = A0 + 3;
@@ -25,8 +26,8 @@ __global__ void k_step_params(const double* A, const int* counter, int use_count
     a1[i] = A1[i];
   }
   const bool vel = (gauge == 0);
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (blockIdx.x == 0) {
+  const int t = bx * blockDim.x + threadIdx.x;
+  if (bx == 0) {
     for (int k = threadIdx.x; k < n_k; k += blockDim.x) {
       for (int i = 0; i < 3; ++i) {
         kappa[3 * k + i] = kpt[3 * k + i] + (vel ? ab[i] / kC : 0.0);
@@ -53,6 +54,28 @@ __global__ void k_step_params(const double* A, const int* counter, int use_count
   }
 }
 
+__global__ void k_step_params(const double* A, const int* counter, int use_counter,
+                              const double* kpt, int n_k, const double* ent_x, int S, int gauge,
+                              double dt, double* kappa, double* kappaJ, double* efield,
+                              double2* phA, double2* phAJ, double* Alast) {
+  step_params_block(A, counter, use_counter, kpt, n_k, ent_x, S, gauge, dt, kappa, kappaJ, efield, phA, phAJ, Alast,
+                    (int)blockIdx.x);
+}
+
+// the same for the cells of a group (cell blockIdx.y), each at its own step
+__global__ void k_step_params_group(const ParamCell* __restrict__ tab) {
+  const ParamCell& c = tab[blockIdx.y];
+  if ((int)blockIdx.x > 0 && (int)blockIdx.x * (int)blockDim.x >= c.S) return;
+  step_params_block(c.A, c.counter, 1, c.kpt, c.n_k, c.ent_x, c.S, c.gauge, c.dt, c.kappa, c.kappaJ, c.efield, c.phA,
+                    c.phAJ, c.Alast, (int)blockIdx.x);
+}
+
+hipError_t launch_step_params_group(const ParamCell* tab, int ncells, int max_S, hipStream_t s) {
+  const int blocks = max_S > 0 ? (max_S + 255) / 256 : 1;
+  hipLaunchKernelGGL(k_step_params_group, dim3(blocks, ncells), dim3(256), 0, s, tab);
+  return hipGetLastError();
+}
+
 hipError_t launch_step_params(const double* A, const int* counter, int use_counter,
                               const double* kpt, int n_k, const double* ent_x, int S, int gauge,
                               double dt, double* kappa, double* kappaJ, double* efield, double2* phA,
@@ -66,11 +89,8 @@ hipError_t launch_step_params(const double* A, const int* counter, int use_count
 // ---------------------------------------------------------------- density
 // part[c][p] = sum over orbitals o in chunk c of 2 w_k |w_o(p)|^2, in order.
 template <typename T>
-__global__ void k_rho_partial(const typename Vec2<T>::type* w, const double* kw, int n_orb, int n_k,
-                              int N, int chunk, double* part) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  const int c = blockIdx.y;
-  if (p >= N) return;
+__device__ __forceinline__ void rho_partial_point(const typename Vec2<T>::type* w, const double* kw, int n_orb,
+                                                  int n_k, int N, int chunk, int c, int p, double* part) {
   const int n_tot = n_orb * n_k;
   const int o0 = c * chunk;
   const int o1 = min(n_tot, o0 + chunk);
@@ -82,6 +102,34 @@ __global__ void k_rho_partial(const typename Vec2<T>::type* w, const double* kw,
   }
   part[(size_t)c * N + p] = acc;
 }
+
+template <typename T>
+__global__ void k_rho_partial(const typename Vec2<T>::type* w, const double* kw, int n_orb, int n_k,
+                              int N, int chunk, double* part) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= N) return;
+  rho_partial_point<T>(w, kw, n_orb, n_k, N, chunk, (int)blockIdx.y, p, part);
+}
+
+// the same for the cells of a group: cell blockIdx.z, chunk blockIdx.y
+template <typename T>
+__global__ void k_rho_partial_group(const TailCell* __restrict__ tab, int N, int chunk) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const TailCell& t = tab[blockIdx.z];
+  if (p >= N || (int)blockIdx.y >= t.nchunks) return;
+  rho_partial_point<T>(static_cast<const typename Vec2<T>::type*>(t.w), t.kw, t.n_orb, t.n_k, N, chunk,
+                       (int)blockIdx.y, p, t.rho_out);
+}
+
+template <typename T>
+hipError_t launch_rho_partial_group(const TailCell* tab, int ncells, int N, int chunk, int max_chunks,
+                                    hipStream_t s) {
+  hipLaunchKernelGGL((k_rho_partial_group<T>), dim3((N + 255) / 256, max_chunks, ncells), dim3(256), 0, s, tab,
+                     N, chunk);
+  return hipGetLastError();
+}
+template hipError_t launch_rho_partial_group<double>(const TailCell*, int, int, int, int, hipStream_t);
+template hipError_t launch_rho_partial_group<float>(const TailCell*, int, int, int, int, hipStream_t);
 
 template <typename T>
 hipError_t launch_rho_partial(const typename Vec2<T>::type* w, const double* kw, int n_orb, int n_k,
@@ -104,9 +152,8 @@ template hipError_t launch_rho_partial<float>(const float2*, const double*, int,
 // of dependent loads.
 constexpr int kRedSlices = 16;
 
-__global__ __launch_bounds__(64 * kRedSlices) void k_rho_reduce(const double* __restrict__ part, int nchunks,
-                                                                int N, double* __restrict__ rho) {
-  __shared__ double red[kRedSlices][64];
+__device__ __forceinline__ void rho_reduce_block(const double* __restrict__ part, int nchunks, int N,
+                                                 double* __restrict__ rho, double (*red)[64]) {
   const int i = threadIdx.x & 63, j = threadIdx.x >> 6;
   const int p = blockIdx.x * 64 + i;
   double acc = 0.0;
@@ -119,6 +166,26 @@ __global__ __launch_bounds__(64 * kRedSlices) void k_rho_reduce(const double* __
     __syncthreads();
   }
   if (j == 0 && p < N) rho[p] = red[0][i];
+}
+
+__global__ __launch_bounds__(64 * kRedSlices) void k_rho_reduce(const double* __restrict__ part, int nchunks,
+                                                                int N, double* __restrict__ rho) {
+  __shared__ double red[kRedSlices][64];
+  rho_reduce_block(part, nchunks, N, rho, red);
+}
+
+// the same for the cells of a group (cell blockIdx.y; cells with one chunk
+// have their density already)
+__global__ __launch_bounds__(64 * kRedSlices) void k_rho_reduce_group(const TailCell* __restrict__ tab, int N) {
+  __shared__ double red[kRedSlices][64];
+  const TailCell& t = tab[blockIdx.y];
+  if (t.nchunks <= 1) return;
+  rho_reduce_block(t.rho_part, t.nchunks, N, t.rho, red);
+}
+
+hipError_t launch_rho_reduce_group(const TailCell* tab, int ncells, int N, hipStream_t s) {
+  hipLaunchKernelGGL(k_rho_reduce_group, dim3((N + 63) / 64, ncells), dim3(64 * kRedSlices), 0, s, tab, N);
+  return hipGetLastError();
 }
 
 hipError_t launch_rho_reduce(const double* part, int nchunks, int N, double* rho, hipStream_t s) {
@@ -283,16 +350,18 @@ struct FFTLines {
   int l1, l2, n_in, n_out, fused;
 };
 
-__global__ __launch_bounds__(256) void k_fft_axis(double2* data, int M1, int M2, int M3, int axis,
-                                                  int sign, int B, FFTPlan plan, FFTEnds ends, FFTLines ln) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
+// B lines of one pass from line blk B on (smem_raw: the dynamic LDS)
+__device__ __forceinline__ void fft_axis_block(double2* data, int M1, int M2, int M3, int axis, int sign, int B,
+                                               const FFTPlan& plan, const FFTEnds& ends, const FFTLines& ln,
+                                               long blk, unsigned char* smem_raw) {
+  (void)M3;
   const int M = plan.M;
   double2* buf0 = reinterpret_cast<double2*>(smem_raw);
   double2* buf1 = buf0 + (size_t)B * M;
   double2* tw = buf1 + (size_t)B * M;   // M entries
   double2* twi = tw + M;                // M entries (fused: the inverse's)
   const long nlines = (long)ln.l1 * ln.l2;
-  const long L0 = (long)blockIdx.x * B;
+  const long L0 = blk * B;
   const int nl = (int)min((long)B, nlines - L0);
   const long stride = (axis == 0) ? 1 : (axis == 1 ? M1 : (long)M1 * M2);
   auto line_base = [&](long L) -> long {
@@ -358,21 +427,63 @@ __global__ __launch_bounds__(256) void k_fft_axis(double2* data, int M1, int M2,
   }
 }
 
+__global__ __launch_bounds__(256) void k_fft_axis(double2* data, int M1, int M2, int M3, int axis,
+                                                  int sign, int B, FFTPlan plan, FFTEnds ends, FFTLines ln) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  fft_axis_block(data, M1, M2, M3, axis, sign, B, plan, ends, ln, (long)blockIdx.x, smem_raw);
+}
+
+// the same pass for the cells of a group (cell blockIdx.y)
+__global__ __launch_bounds__(256) void k_fft_axis_group(const TailCell* __restrict__ tab, int M1, int M2, int M3,
+                                                        int axis, int sign, int B, FFTPlan plan, FFTEnds ends,
+                                                        FFTLines ln, int use_rho, int use_K) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const TailCell& t = tab[blockIdx.y];
+  FFTEnds e = ends;
+  e.rho = use_rho ? t.rho : nullptr;
+  e.K = use_K ? t.Kfft : nullptr;
+  fft_axis_block(t.fft, M1, M2, M3, axis, sign, B, plan, e, ln, (long)blockIdx.x, smem_raw);
+}
+
+// the radix plan of a transform of length M (false: M has other prime factors)
+static bool fft_plan(int M, FFTPlan* plan) {
+  plan->M = M;
+  plan->nf = 0;
+  int rem = M;
+  const int radices[4] = {4, 2, 3, 5};
+  for (int r : radices) {
+    while (rem % r == 0 && plan->nf < 12) {
+      plan->f[plan->nf++] = r;
+      rem /= r;
+    }
+  }
+  return rem == 1;
+}
+
+hipError_t launch_fft_lines_group(const TailCell* tab, int ncells, int M1, int M2, int M3, int axis, int sign,
+                                  int use_rho, int n1, int n2, int n3, int use_K, int l1, int l2, int n_in,
+                                  int n_out, int fused, hipStream_t s) {
+  FFTPlan plan;
+  if (!fft_plan(axis == 0 ? M1 : (axis == 1 ? M2 : M3), &plan)) return hipErrorInvalidValue;
+  if (fused && (axis != 2 || !use_K)) return hipErrorInvalidValue;
+  const long nlines = (long)l1 * l2;
+  if (nlines <= 0 || ncells <= 0) return hipSuccess;
+  // every line is transformed the same way whatever B is; with many cells
+  // the grid is full without spreading one cell's lines thinly
+  const int B = max(1, min(256, 2048 / plan.M));
+  const size_t lds = ((size_t)2 * B * plan.M + 2 * (size_t)plan.M) * sizeof(double2);
+  FFTEnds ends{nullptr, n1, n2, n3, nullptr};
+  FFTLines ln{l1, l2, n_in, n_out, fused};
+  hipLaunchKernelGGL(k_fft_axis_group, dim3((unsigned)((nlines + B - 1) / B), ncells), dim3(256), lds, s, tab, M1,
+                     M2, M3, axis, sign, B, plan, ends, ln, use_rho, use_K);
+  return hipGetLastError();
+}
+
 hipError_t launch_fft_lines(double2* data, int M1, int M2, int M3, int axis, int sign, hipStream_t s,
                             const double* rho, int n1, int n2, int n3, const double* K, int l1, int l2, int n_in,
                             int n_out, int fused) {
   FFTPlan plan;
-  plan.M = axis == 0 ? M1 : (axis == 1 ? M2 : M3);
-  plan.nf = 0;
-  int rem = plan.M;
-  const int radices[4] = {4, 2, 3, 5};
-  for (int r : radices) {
-    while (rem % r == 0 && plan.nf < 12) {
-      plan.f[plan.nf++] = r;
-      rem /= r;
-    }
-  }
-  if (rem != 1) return hipErrorInvalidValue;
+  if (!fft_plan(axis == 0 ? M1 : (axis == 1 ? M2 : M3), &plan)) return hipErrorInvalidValue;
   if (fused && (axis != 2 || !K)) return hipErrorInvalidValue;
   const long nlines = (long)l1 * l2;
   if (nlines <= 0) return hipSuccess;
@@ -429,13 +540,10 @@ __device__ void pz81(double rho, int exchange_too, double* v, double* e) {
 }
 
 // xc: 0 none, 1 PZ81, 2 and 3 the exchange in vx_mgga plus PZ81 correlation
-__global__ void k_xc_assemble(const double2* data, int n1, int n2, int n3, int M1, int M2,
-                              double vh_scale, const double* rho, const double* Vloc, int hartree,
-                              int xc, const double* vx_mgga, double* Vd, float* Vf, double* vh_out,
-                              double* exc) {
-  const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const size_t N = (size_t)n1 * n2 * n3;
-  if (p >= N) return;
+__device__ __forceinline__ void xc_point(const double2* data, int n1, int n2, int M1, int M2, double vh_scale,
+                                         const double* rho, const double* Vloc, int hartree, int xc,
+                                         const double* vx_mgga, double* Vd, float* Vf, double* vh_out,
+                                         double* exc, size_t p) {
   const int x = (int)(p % n1);
   const int y = (int)((p / n1) % n2);
   const int z = (int)(p / ((size_t)n1 * n2));
@@ -451,6 +559,35 @@ __global__ void k_xc_assemble(const double2* data, int n1, int n2, int n3, int M
   Vf[p] = (float)v;
   vh_out[p] = vh;
   exc[p] = e;
+}
+
+__global__ void k_xc_assemble(const double2* data, int n1, int n2, int n3, int M1, int M2,
+                              double vh_scale, const double* rho, const double* Vloc, int hartree,
+                              int xc, const double* vx_mgga, double* Vd, float* Vf, double* vh_out,
+                              double* exc) {
+  const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t N = (size_t)n1 * n2 * n3;
+  if (p >= N) return;
+  xc_point(data, n1, n2, M1, M2, vh_scale, rho, Vloc, hartree, xc, vx_mgga, Vd, Vf, vh_out, exc, p);
+}
+
+// the same for the cells of a group (cell blockIdx.y; LDA or no xc)
+__global__ void k_xc_group(const TailCell* __restrict__ tab, int n1, int n2, int n3, int M1, int M2, int hartree,
+                           int xc) {
+  const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t N = (size_t)n1 * n2 * n3;
+  if (p >= N) return;
+  const TailCell& t = tab[blockIdx.y];
+  xc_point(t.fft, n1, n2, M1, M2, t.vh_scale, t.rho, t.Vloc, hartree, xc, nullptr, t.Vd, t.Vf, t.vh, t.exc, p);
+}
+
+hipError_t launch_xc_group(const TailCell* tab, int ncells, int n1, int n2, int n3, int M1, int M2, int hartree,
+                           int xc, hipStream_t s) {
+  if (xc >= 2) return hipErrorInvalidValue;
+  const size_t N = (size_t)n1 * n2 * n3;
+  hipLaunchKernelGGL(k_xc_group, dim3((unsigned)((N + 255) / 256), ncells), dim3(256), 0, s, tab, n1, n2, n3, M1,
+                     M2, hartree, xc);
+  return hipGetLastError();
 }
 
 hipError_t launch_xc_assemble(const double2* data, int n1, int n2, int n3, int M1, int M2, int M3,
@@ -471,12 +608,10 @@ hipError_t launch_xc_assemble(const double2* data, int n1, int n2, int n3, int M
 // in order, then a fixed pairwise tree combines the threads. nanflag gets
 // bit 0 for a non-finite norm or momentum, bit 1 (only when norm_tol > 0)
 // for a norm further than norm_tol from 1.
-__global__ __launch_bounds__(1024) void k_finish(const double* obs, int tiles, const double* jnl,
-                                                 int use_nl, const double* kw, const double* kappaJ,
-                                                 int n_orb, int n_k, double dV, double volume,
-                                                 int* counter, int bump, double* Jtab,
-                                                 double* scalars, int* nanflag, double norm_tol) {
-  __shared__ double red[1024][5];
+__device__ __forceinline__ void finish_block(const double* obs, int tiles, const double* jnl, int use_nl,
+                                             const double* kw, const double* kappaJ, int n_orb, int n_k,
+                                             double dV, double volume, int* counter, int bump, double* Jtab,
+                                             double* scalars, int* nanflag, double norm_tol, double (*red)[5]) {
   const int t = threadIdx.x;
   const int n_tot = n_orb * n_k;
   double cx = 0, cy = 0, cz = 0, en = 0, nr = 0;
@@ -528,6 +663,29 @@ __global__ __launch_bounds__(1024) void k_finish(const double* obs, int tiles, c
       *counter = n + 1;
     }
   }
+}
+
+__global__ __launch_bounds__(1024) void k_finish(const double* obs, int tiles, const double* jnl,
+                                                 int use_nl, const double* kw, const double* kappaJ,
+                                                 int n_orb, int n_k, double dV, double volume,
+                                                 int* counter, int bump, double* Jtab,
+                                                 double* scalars, int* nanflag, double norm_tol) {
+  __shared__ double red[1024][5];
+  finish_block(obs, tiles, jnl, use_nl, kw, kappaJ, n_orb, n_k, dV, volume, counter, bump, Jtab, scalars, nanflag,
+               norm_tol, red);
+}
+
+// one step's current of every cell of a group (one workgroup per cell)
+__global__ __launch_bounds__(1024) void k_finish_group(const TailCell* __restrict__ tab, int tiles) {
+  __shared__ double red[1024][5];
+  const TailCell& c = tab[blockIdx.x];
+  finish_block(c.obs, tiles, c.jnl, c.use_nl, c.kw, c.kappaJ, c.n_orb, c.n_k, c.dV, c.volume, c.counter, 1, c.Jtab,
+               c.scalars, c.nanflag, c.norm_tol, red);
+}
+
+hipError_t launch_finish_group(const TailCell* tab, int ncells, int tiles, hipStream_t s) {
+  hipLaunchKernelGGL(k_finish_group, dim3(ncells), dim3(1024), 0, s, tab, tiles);
+  return hipGetLastError();
 }
 
 hipError_t launch_finish(const double* obs, int tiles, const double* jnl, int use_nl,
