@@ -227,7 +227,8 @@ __device__ __forceinline__ void observe_part(const typename Vec2<T>::type* u, co
   }
 }
 
-template <typename T, int N, int ZS, bool PERIODIC>
+// ITEMS: the body runs once per item of a loop (the persistent form)
+template <typename T, int N, int ZS, bool PERIODIC, bool ITEMS = false>
 __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, const int o, unsigned char* smem_raw) {
   using T2 = typename Vec2<T>::type;
   constexpr int plane = N * N;
@@ -251,7 +252,11 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, const int o, u
   double* ja = red + 16 * 8;                                                 // [n_atoms][4]
 
   const int k = o / a.g.n_orb;
-  const int tid = threadIdx.x;
+  // in the persistent form the thread index is opaque to the compiler, so
+  // that the values derived from it are formed per item instead of being
+  // hoisted out of the item loop and held in registers across it
+  int tid = threadIdx.x;
+  if (ITEMS) asm volatile("" : "+v"(tid));
   const int lane = tid & 63, wave = tid >> 6, nwaves = blockDim.x >> 6;
   const int half = (ZS == 2 && tid >= HALF) ? 1 : 0;  // uniform per wavefront
   const int ctid = tid - half * HALF;
@@ -555,19 +560,29 @@ __global__ __launch_bounds__(MAXT) void k_fused(FusedArgs<T> a) {
 // computed exactly as in k_fused, so the result does not depend on which
 // workgroup takes it.
 template <typename T, int N, int ZS, bool PERIODIC, int MAXT>
-__global__ __launch_bounds__(MAXT) void k_fused_persistent(const FusedArgs<T>* __restrict__ cells,
+__global__ __launch_bounds__(MAXT, (MAXT <= 512 && sizeof(T) == 4) ? 4 : 1) void k_fused_persistent(const FusedArgs<T>* __restrict__ cells,
                                                            const int2* __restrict__ items, int n_items,
                                                            int* queue) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ int next;
-  for (;;) {
-    if (threadIdx.x == 0) next = atomicAdd(queue, 1);
-    __syncthreads();
-    const int it = __builtin_amdgcn_readfirstlane(next);
-    __syncthreads();
-    if (it >= n_items) break;
+  if (threadIdx.x == 0) next = atomicAdd(queue, 1);
+  __syncthreads();
+  int it = __builtin_amdgcn_readfirstlane(next);
+  __syncthreads();
+  while (it < n_items) {
+    // claim the following item now, so that the queue's round trip overlaps
+    // this item's work (every item is still taken exactly once)
+    int claim = 0;
+    if (threadIdx.x == 0) claim = atomicAdd(queue, 1);
+    // the cell and orbital are uniform: scalar registers, so that the
+    // cell's arguments are read with scalar loads as kernel arguments are
     const int2 ci = items[it];
-    fused_body<T, N, ZS, PERIODIC>(cells[ci.x], ci.y, smem_raw);
+    const int cx = __builtin_amdgcn_readfirstlane(ci.x), orb = __builtin_amdgcn_readfirstlane(ci.y);
+    fused_body<T, N, ZS, PERIODIC, true>(cells[cx], orb, smem_raw);
+    __syncthreads();
+    if (threadIdx.x == 0) next = claim;
+    __syncthreads();
+    it = __builtin_amdgcn_readfirstlane(next);
     __syncthreads();
   }
 }
