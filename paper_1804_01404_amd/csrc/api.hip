@@ -111,6 +111,9 @@ struct tddft_ctx {
   int *counter = nullptr, *nanflag = nullptr;
   double *scalars = nullptr, *sums = nullptr;
   double A_last[3] = {0, 0, 0};
+  // per-axis largest |A| of the last table that passed the stability bound
+  // (the bound grows with each; -1: none since the potential was set)
+  double bound_amax[3] = {-1.0, -1.0, -1.0};
 
   hipGraphExec_t graph = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -949,7 +952,9 @@ tddft_status tune_stage(tddft_ctx* c) {
 }
 
 // validation, table upload and counter reset shared by single-cell and batch runs
-tddft_status prepare_propagate(tddft_ctx* c, int32_t nsteps, const double* A) {
+// upload: copy the A table and reset the step counter here (a batch moves
+// its cells' tables with one copy instead)
+tddft_status prepare_propagate(tddft_ctx* c, int32_t nsteps, const double* A, bool upload = true) {
   if (c->poisoned) return fail(c, TDDFT_ESTATE, "context poisoned: " + c->err);
   if (!c->potential_set) return fail(c, TDDFT_ESTATE, "propagate before set_potential");
   if (nsteps < 1 || !A) return fail(c, TDDFT_EINVAL, "bad propagate arguments");
@@ -958,7 +963,10 @@ tddft_status prepare_propagate(tddft_ctx* c, int32_t nsteps, const double* A) {
     if (!std::isfinite(A[i])) return fail(c, TDDFT_EINVAL, "A table not finite");
     amax[i % 3] = std::max(amax[i % 3], std::fabs(A[i]));
   }
-  if (c->cfg.gauge == TDDFT_VELOCITY && !(c->cfg.flags & TDDFT_FLAG_ALLOW_UNSTABLE)) {
+  // a table within the per-axis maxima of one that passed passes too (the
+  // bound grows with each)
+  const bool known = amax[0] <= c->bound_amax[0] && amax[1] <= c->bound_amax[1] && amax[2] <= c->bound_amax[2];
+  if (c->cfg.gauge == TDDFT_VELOCITY && !(c->cfg.flags & TDDFT_FLAG_ALLOW_UNSTABLE) && !known) {
     // the potential part was checked in set_potential; recheck the kinetic part with |A|
     const double lam = spectral_bound(c, amax, -c->vabs, c->vabs);
     if (std::fabs(c->cfg.dt) * lam > 2.0 * std::sqrt(2.0)) {
@@ -968,6 +976,7 @@ tddft_status prepare_propagate(tddft_ctx* c, int32_t nsteps, const double* A) {
                     std::fabs(c->cfg.dt) * lam, lam);
       return fail(c, TDDFT_EUNSTABLE, buf);
     }
+    for (int i = 0; i < 3; ++i) c->bound_amax[i] = amax[i];
   }
   if (nsteps > c->cap_steps) {
     invalidate_graph(c);
@@ -978,8 +987,10 @@ tddft_status prepare_propagate(tddft_ctx* c, int32_t nsteps, const double* A) {
       return st;
     c->cap_steps = cap;
   }
-  HIP_TRY(hipMemcpyAsync(c->Atab, A, 3 * sizeof(double) * (nsteps + 1), hipMemcpyHostToDevice, c->stream));
-  LAUNCH(launch_set_int(c->counter, 0, c->stream), "counter reset");
+  if (upload) {
+    HIP_TRY(hipMemcpyAsync(c->Atab, A, 3 * sizeof(double) * (nsteps + 1), hipMemcpyHostToDevice, c->stream));
+    LAUNCH(launch_set_int(c->counter, 0, c->stream), "counter reset");
+  }
   return TDDFT_OK;
 }
 
@@ -1329,6 +1340,7 @@ tddft_status tddft_set_potential(tddft_ctx* c, const double* v_loc, int32_t n_at
     }
   // stability: |lambda| dt <= 2 sqrt 2 for the truncated fourth-order Taylor step
   c->vabs = std::max(std::fabs(vmin), std::fabs(vmax));
+  for (int i = 0; i < 3; ++i) c->bound_amax[i] = -1.0;
   const double lam = spectral_bound(c, kNoField, vmin, vmax);
   if (std::fabs(c->cfg.dt) * lam > 2.0 * std::sqrt(2.0) && !(c->cfg.flags & TDDFT_FLAG_ALLOW_UNSTABLE)) {
     char buf[200];
@@ -1807,6 +1819,11 @@ struct tddft_batch {
   hipGraphExec_t graph = nullptr;
   double last_ms = 0;
   std::vector<void*> allocs;
+  // one staging area each way for the cells' A and J tables: the IOCell
+  // table, then [cells][3 (n + 1)] A values, or [cells][3 n + 1] J values and flags
+  double* d_stage = nullptr;
+  double* h_stage = nullptr;  // pinned
+  size_t stage_cap = 0;       // doubles
 };
 
 namespace {
@@ -2230,24 +2247,63 @@ tddft_status tddft_batch_propagate(tddft_batch* b, int32_t nsteps, const double*
   if (b->poisoned) return bfail(b, TDDFT_ESTATE, "batch poisoned: " + b->err);
   if (nsteps < 0 || (nsteps > 0 && !A)) return bfail(b, TDDFT_EINVAL, "bad propagate arguments");
   if (nsteps == 0) return TDDFT_OK;
-  for (size_t i = 0; i < b->cells.size(); ++i) {
+  const int nc = (int)b->cells.size();
+  for (int i = 0; i < nc; ++i) {
     tddft_ctx* c = b->cells[i];
     c->stream = b->stream;
     const bool had = c->cap_steps >= nsteps;
-    tddft_status st = prepare_propagate(c, nsteps, A[i]);
-    if (st != TDDFT_OK) return bcell(b, st, (int)i);
+    tddft_status st = prepare_propagate(c, nsteps, A[i], false);
+    if (st != TDDFT_OK) return bcell(b, st, i);
     if (!had && b->graph) {  // a cell's A/J tables moved: the captured step must be rebuilt
       (void)hipGraphExecDestroy(b->graph);
       b->graph = nullptr;
     }
   }
+  // the A tables of every cell with one copy: the IOCell table and the tables
+  // staged in pinned memory, scattered on the device (counters reset there)
+  const size_t io_d = (nc * sizeof(IOCell) + sizeof(double) - 1) / sizeof(double);
+  const size_t len_in = 3 * (size_t)(nsteps + 1), len_out = 3 * (size_t)nsteps + 1;
+  const size_t need = io_d + (size_t)nc * std::max(len_in, len_out);
+  if (need > b->stage_cap) {
+    const size_t cap = std::max(need, 2 * b->stage_cap);
+    BHIP(hipStreamSynchronize(b->stream));
+    if (b->d_stage) (void)hipFree(b->d_stage);
+    if (b->h_stage) (void)hipHostFree(b->h_stage);
+    b->d_stage = nullptr;
+    b->h_stage = nullptr;
+    b->stage_cap = 0;
+    BHIP(hipMalloc(&b->d_stage, cap * sizeof(double)));
+    BHIP(hipHostMalloc(&b->h_stage, cap * sizeof(double)));
+    b->stage_cap = cap;
+  }
+  IOCell* hio = reinterpret_cast<IOCell*>(b->h_stage);
+  for (int i = 0; i < nc; ++i) {
+    tddft_ctx* c = b->cells[i];
+    hio[i] = IOCell{c->Atab, c->counter, c->Jtab, c->nanflag};
+    std::memcpy(b->h_stage + io_d + (size_t)i * len_in, A[i], len_in * sizeof(double));
+  }
+  const IOCell* dio = reinterpret_cast<const IOCell*>(b->d_stage);
+  BHIP(hipMemcpyAsync(b->d_stage, b->h_stage, (io_d + (size_t)nc * len_in) * sizeof(double), hipMemcpyHostToDevice,
+                      b->stream));
+  BHIP(launch_batch_tables_in(dio, nc, b->d_stage + io_d, (int)len_in, b->stream));
   tddft_status st = b->mixed ? batch_propagate<float>(b, nsteps) : batch_propagate<double>(b, nsteps);
   if (st != TDDFT_OK) return st;
-  for (size_t i = 0; i < b->cells.size(); ++i) {
+  // the J tables and NaN flags back with one copy and one wait
+  BHIP(launch_batch_tables_out(dio, nc, b->d_stage + io_d, (int)(len_out - 1), b->stream));
+  BHIP(hipMemcpyAsync(b->h_stage + io_d, b->d_stage + io_d, (size_t)nc * len_out * sizeof(double),
+                      hipMemcpyDeviceToHost, b->stream));
+  BHIP(hipStreamSynchronize(b->stream));
+  for (int i = 0; i < nc; ++i) {
     tddft_ctx* c = b->cells[i];
-    st = collect_propagate(c, nsteps, A[i], J_out ? J_out[i] : nullptr);
-    if (st != TDDFT_OK) return bcell(b, st, (int)i);
+    const double* out = b->h_stage + io_d + (size_t)i * len_out;
+    if (J_out && J_out[i]) std::memcpy(J_out[i], out, (len_out - 1) * sizeof(double));
+    for (int k = 0; k < 3; ++k) c->A_last[k] = A[i][3 * (size_t)nsteps + k];
     c->last_ms = b->last_ms;
+    const int flag = (int)out[len_out - 1];
+    if (flag & 1) return bcell(b, fail(c, TDDFT_ENUMERIC, "NaN or Inf in the orbital norms or current"), i);
+    if (flag & 2)
+      return bcell(b, fail(c, TDDFT_ENUMERIC, "norm watchdog: an orbital norm left 1 by more than 1e-3 (unstable step?)"),
+                   i);
   }
   return TDDFT_OK;
 }
@@ -2325,6 +2381,8 @@ void tddft_batch_free(tddft_batch* b) {
   if (b->ev0) (void)hipEventDestroy(b->ev0);
   if (b->ev1) (void)hipEventDestroy(b->ev1);
   for (void* p : b->allocs) (void)hipFree(p);
+  if (b->d_stage) (void)hipFree(b->d_stage);
+  if (b->h_stage) (void)hipHostFree(b->h_stage);
   if (b->own_stream) (void)hipStreamDestroy(b->stream);
   delete b;
 }

@@ -273,6 +273,20 @@ struct ParamCell {
   double2* phkA;          // [n_k][S]
 };
 
+// A batch's per-cell A and J tables moved with one copy each way: the cells'
+// table pointers, counters and NaN flags.
+struct IOCell {
+  double* A;
+  int* counter;
+  const double* J;
+  const int* nanflag;
+};
+// io[c] and the staged A tables (len doubles per cell): A tables to the cells,
+// their step counters to 0
+hipError_t launch_batch_tables_in(const IOCell* io, int ncells, const double* staged, int len, hipStream_t s);
+// the cells' J tables (len doubles) and NaN flags to staged [ncells][len + 1]
+hipError_t launch_batch_tables_out(const IOCell* io, int ncells, double* staged, int len, hipStream_t s);
+
 hipError_t launch_step_params_group(const ParamCell* tab, int ncells, int max_S, hipStream_t s);
 template <typename T>
 hipError_t launch_fused_coef_group(const ParamCell* tab, int ncells, int max_nk, long max_phases, hipStream_t s);

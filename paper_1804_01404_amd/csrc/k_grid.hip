@@ -86,6 +86,33 @@ hipError_t launch_step_params(const double* A, const int* counter, int use_count
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- batch tables
+__global__ void k_batch_tables_in(const IOCell* __restrict__ io, const double* __restrict__ staged, int len) {
+  const IOCell& c = io[blockIdx.x];
+  const double* src = staged + (size_t)blockIdx.x * len;
+  for (int i = threadIdx.x; i < len; i += blockDim.x) c.A[i] = src[i];
+  if (threadIdx.x == 0) *c.counter = 0;
+}
+
+__global__ void k_batch_tables_out(const IOCell* __restrict__ io, double* __restrict__ staged, int len) {
+  const IOCell& c = io[blockIdx.x];
+  double* dst = staged + (size_t)blockIdx.x * (len + 1);
+  for (int i = threadIdx.x; i < len; i += blockDim.x) dst[i] = c.J[i];
+  if (threadIdx.x == 0) dst[len] = (double)*c.nanflag;
+}
+
+hipError_t launch_batch_tables_in(const IOCell* io, int ncells, const double* staged, int len, hipStream_t s) {
+  if (ncells <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batch_tables_in, dim3(ncells), dim3(64), 0, s, io, staged, len);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_tables_out(const IOCell* io, int ncells, double* staged, int len, hipStream_t s) {
+  if (ncells <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batch_tables_out, dim3(ncells), dim3(64), 0, s, io, staged, len);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- density
 // part[c][p] = sum over orbitals o in chunk c of 2 w_k |w_o(p)|^2, in order.
 template <typename T>
