@@ -359,6 +359,10 @@ struct tddft_ms {
   int* flag = nullptr;
   double *dhist = nullptr, *dIhist = nullptr;  // [cap][n_mat] medium A and I per step
   int hist_cap = 0;
+  // the A and I rows of one tddft_ms_step call, staged on the device and
+  // copied to the caller once at its end ([out_cap][n_x] each)
+  double *dAout = nullptr, *dIout = nullptr;
+  int out_cap = 0;
   std::string err;
 };
 
@@ -640,6 +644,16 @@ tddft_status tddft_ms_step(tddft_ms* ms, int32_t n_macro, const double* inc, dou
   const double S2 = S * S, src = 4.0 * M_PI * kC * g.dt * g.dt, q = (S - 1.0) / (S + 1.0);
   tddft_status st;
   if (ms->mode == 0 && !ms->full && (st = ms_make_batch(ms, nm, &ms->full)) != TDDFT_OK) return st;
+  if ((A_out || I_out) && n_macro > ms->out_cap) {
+    MHIP(hipStreamSynchronize(ms->stream));
+    if (ms->dAout) (void)hipFree(ms->dAout);
+    if (ms->dIout) (void)hipFree(ms->dIout);
+    ms->dAout = ms->dIout = nullptr;
+    ms->out_cap = 0;
+    if (nalloc(&ms->dAout, (size_t)n_macro * nx) || nalloc(&ms->dIout, (size_t)n_macro * nx))
+      return ms_fail(ms, TDDFT_ENOMEM, "device allocation failed (output rows)");
+    ms->out_cap = n_macro;
+  }
   std::vector<double> Anew(nx), Inew(nx);
   const std::vector<int> all = [&] {
     std::vector<int> v(nm);
@@ -677,8 +691,12 @@ tddft_status tddft_ms_step(tddft_ms* ms, int32_t n_macro, const double* inc, dou
                           hipMemcpyDeviceToDevice, ms->stream));
     }
     MHIP(launch_ms_work_step(ms->A[2], ms->A[1], ms->Iold, ms->I, g.x0, nm, g.dx, g.dt, ms->energy, ms->stream));
-    if (A_out) MHIP(hipMemcpyAsync(A_out + (size_t)n * nx, ms->A[2], nx * sizeof(double), hipMemcpyDeviceToHost, ms->stream));
-    if (I_out) MHIP(hipMemcpyAsync(I_out + (size_t)n * nx, ms->I, nx * sizeof(double), hipMemcpyDeviceToHost, ms->stream));
+    if (A_out)
+      MHIP(hipMemcpyAsync(ms->dAout + (size_t)n * nx, ms->A[2], nx * sizeof(double), hipMemcpyDeviceToDevice,
+                          ms->stream));
+    if (I_out)
+      MHIP(hipMemcpyAsync(ms->dIout + (size_t)n * nx, ms->I, nx * sizeof(double), hipMemcpyDeviceToDevice,
+                          ms->stream));
     double* t = ms->A[0];
     ms->A[0] = ms->A[1];
     ms->A[1] = ms->A[2];
@@ -690,10 +708,15 @@ tddft_status tddft_ms_step(tddft_ms* ms, int32_t n_macro, const double* inc, dou
       if (trip) {
         if ((st = ms_fallback(ms)) != TDDFT_OK) return st;
         if (I_out)  // the current of this step now comes from the cells
-          MHIP(hipMemcpyAsync(I_out + (size_t)n * nx, ms->I, nx * sizeof(double), hipMemcpyDeviceToHost, ms->stream));
+          MHIP(hipMemcpyAsync(ms->dIout + (size_t)n * nx, ms->I, nx * sizeof(double), hipMemcpyDeviceToDevice,
+                              ms->stream));
       }
     }
   }
+  if (A_out && n_macro > 0)
+    MHIP(hipMemcpyAsync(A_out, ms->dAout, (size_t)n_macro * nx * sizeof(double), hipMemcpyDeviceToHost, ms->stream));
+  if (I_out && n_macro > 0)
+    MHIP(hipMemcpyAsync(I_out, ms->dIout, (size_t)n_macro * nx * sizeof(double), hipMemcpyDeviceToHost, ms->stream));
   MHIP(hipStreamSynchronize(ms->stream));
   return TDDFT_OK;
 }
@@ -726,7 +749,8 @@ void tddft_ms_free(tddft_ms* ms) {
   if (ms->stream) (void)hipStreamSynchronize(ms->stream);
   if (ms->full) tddft_batch_free(ms->full);
   if (ms->sent) tddft_batch_free(ms->sent);
-  for (double* p : {ms->A[0], ms->A[1], ms->A[2], ms->I, ms->Iold, ms->energy, ms->dhist, ms->dIhist})
+  for (double* p : {ms->A[0], ms->A[1], ms->A[2], ms->I, ms->Iold, ms->energy, ms->dhist, ms->dIhist, ms->dAout,
+                    ms->dIout})
     if (p) (void)hipFree(p);
   for (float* p : {ms->ring, ms->Xw, ms->wk.h1, ms->wk.h2, ms->wk.y})
     if (p) (void)hipFree(p);
