@@ -342,8 +342,11 @@ tddft_status tddft_conductivity_noalloc(int32_t n_t, const double *I, double dt,
  * grid of every group is chosen by timing candidates on the first steps
  * (every candidate computes identical bits), and every per-stage cell's
  * decomposition by the tuner of tddft_report, unless
- * TDDFT_FLAG_NO_TUNE is set in cfgs[0].flags. Every cell behaves as its own
- * context would alone; the current of a cell is its own. */
+ * TDDFT_FLAG_NO_TUNE is set in cfgs[0].flags. When the cells of a group
+ * share their Hartree and xc switches (LDA or none), the start and the end of
+ * their step (field, phases, current, density, Poisson, potential) run as one
+ * launch per kernel for the group. Every cell behaves as its own context
+ * would alone, bit for bit; the current of a cell is its own. */
 #define TDDFT_FLAG_NO_TUNE 0x10u
 
 typedef struct tddft_batch tddft_batch;
@@ -365,7 +368,9 @@ tddft_status tddft_batch_propagate(tddft_batch *b, int32_t nsteps, const double 
 tddft_ctx *tddft_batch_cell(tddft_batch *b, int32_t cell);
 /* Mean device time per batch step of the last propagate (ms). */
 tddft_status tddft_batch_last_timing(tddft_batch *b, double *ms_per_step);
-/* JSON text of the plan and the tuner's measurements, NUL-terminated in buf. */
+/* JSON text of the plan (per group: grid, cells, items, column split,
+ * persistent workgroups, whether the step's ends run per group) and the
+ * tuner's measurements, NUL-terminated in buf. */
 tddft_status tddft_batch_report(tddft_batch *b, char *buf, size_t len);
 const char *tddft_batch_last_error(const tddft_batch *b);
 void tddft_batch_free(tddft_batch *b);

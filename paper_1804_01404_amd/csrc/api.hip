@@ -2325,8 +2325,10 @@ tddft_status tddft_batch_report(tddft_batch* b, char* buf, size_t len) {
   for (size_t gi = 0; gi < b->groups.size(); ++gi) {
     const auto& g = b->groups[gi];
     char tmp[256];
-    std::snprintf(tmp, sizeof tmp, "%s{\"n\": %d, \"cells\": %zu, \"items\": %d, \"zs\": %d, \"workgroups\": %d, \"tuned_ms\": [",
-                  gi ? ", " : "", g.n, g.cells.size(), g.n_items, g.zs, g.wgs);
+    std::snprintf(tmp, sizeof tmp,
+                  "%s{\"n\": %d, \"cells\": %zu, \"items\": %d, \"zs\": %d, \"workgroups\": %d, "
+                  "\"grouped_tail\": %s, \"tuned_ms\": [",
+                  gi ? ", " : "", g.n, g.cells.size(), g.n_items, g.zs, g.wgs, g.tail_ok ? "true" : "false");
     r += tmp;
     for (size_t i = 0; i < g.cand_ms.size(); ++i) {
       std::snprintf(tmp, sizeof tmp, "%s[%d, %d, %.4f]", i ? ", " : "", g.cand[i].first, g.cand[i].second,

@@ -35,6 +35,31 @@ def test_batch_cells_equal_solo_runs(prec):
         assert np.array_equal(psis[i], solo["psi"]), i
 
 
+@pytest.mark.parametrize("switches", ["same", "mixed"])
+def test_one_grid_batch_equals_solo_runs(switches):
+    """Cells of one grid size form one persistent group. With the same Hartree
+    and xc switches the group runs the ends of its step as one launch per
+    kernel (some cells with several density chunks); with one cell without
+    Hartree and one without xc every cell keeps its own. Either way each cell
+    equals its solo run bit for bit."""
+    from paper_1804_01404_amd.binding import TDDFTBatch
+    cells = synth.batch_cells(cells=range(4), nsteps=5, max_orb=24, max_k=8, grids=(16,), precision="mixed")
+    if switches == "mixed":
+        cells[1].hartree = False
+        cells[2].xc = False
+    announce(f"one-grid batch, {switches} switches, orbitals x k {[c.n_orb * len(c.kw) for c in cells]}")
+    with TDDFTBatch(cells, precision="mixed") as b:
+        Js = b.propagate([c.A for c in cells])
+        psis = [b.orbitals(i) for i in range(len(cells))]
+        rep = b.report()
+    assert len(rep["groups"]) == 1
+    assert rep["groups"][0]["grouped_tail"] == (switches == "same")
+    for i, c in enumerate(cells):
+        solo = gpu_run(c, precision="mixed")
+        assert np.array_equal(Js[i], solo["J"]), i
+        assert np.array_equal(psis[i], solo["psi"]), i
+
+
 def test_batch_cells_match_oracle():
     from paper_1804_01404_amd.binding import TDDFTBatch
     cells = _cells("c128")[:3]
