@@ -217,8 +217,8 @@ def cpu_baseline(steps=6, nk=512):
     except AttributeError:
         pass
     workers = max(1, min(16, host))
-    out_npz = os.path.join(ROOT, "gpurun_out" if os.path.isdir(os.path.join(ROOT, "gpurun_out")) else ".",
-                           f".oracle_pool_{os.getpid()}.npz")
+    import tempfile
+    out_npz = os.path.join(tempfile.gettempdir(), f"oracle_pool_{os.getpid()}.npz")
     cmd = [sys.executable, os.path.abspath(__file__), "--oracle-pool-child", str(steps), str(workers), str(nk),
            out_npz]
     t_wall = time.perf_counter()
