@@ -84,6 +84,26 @@ def test_nan_orbitals_poison_the_context(flags):
             assert "poisoned" in str(e.value)
 
 
+def test_nan_cell_poisons_a_batch():
+    """A NaN orbital in one cell of a batch: the batch's propagate (which takes
+    every cell's NaN flag back with one copy) returns ENUMERIC naming that
+    cell, and the poisoned batch refuses further steps."""
+    from paper_1804_01404_amd import binding
+    cells = synth.batch_cells(cells=range(3), nsteps=3, max_orb=8, max_k=2, grids=(12, 16), precision="mixed")
+    psi = cells[1].psi0.copy()
+    psi.reshape(-1)[7] = np.nan
+    cells[1].psi0 = psi
+    announce("ENUMERIC from a NaN cell in a batch")
+    with binding.TDDFTBatch(cells, precision="mixed") as b:
+        with pytest.raises(binding.TDDFTError) as e:
+            b.propagate([c.A for c in cells])
+        assert e.value.status == binding.ENUMERIC
+        assert "cell 1" in str(e.value)
+        with pytest.raises(binding.TDDFTError) as e:
+            b.propagate([c.A for c in cells])
+        assert e.value.status == binding.ESTATE
+
+
 def test_norm_watchdog_stops_an_unstable_run():
     from paper_1804_01404_amd import binding
     # 20^3 cell at dt = 0.08: |lambda| dt = 2.97 > 2 sqrt 2, the top modes grow
