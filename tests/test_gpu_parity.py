@@ -336,6 +336,16 @@ def test_stability_bound_covers_the_spectrum():
         lam_a = _reported_bound(e.value)
         J = t.propagate(np.zeros((3, 3)))                # the field-free table still runs
         assert np.all(np.isfinite(J))
+        # a passing table along x does not let a strong one along y through
+        # (the check is skipped only for tables within the last passing one)
+        A_x = np.zeros((3, 3))
+        A_x[:, 0] = 1.0
+        assert np.all(np.isfinite(t.propagate(A_x)))
+        A_y = np.zeros((3, 3))
+        A_y[:, 1] = 200.0
+        with pytest.raises(TDDFTError) as e:
+            t.propagate(A_y)
+        assert e.value.status == EUNSTABLE
     true_a = _lambda_true(s, [200.0, 0.0, 0.0], kx)
     assert true_a <= lam_a <= 2.0 * true_a
 
